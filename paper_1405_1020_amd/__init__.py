@@ -1,0 +1,19 @@
+"""MI355X (gfx950) oil-paint filter.
+
+The filter itself runs in hand-written HIP kernels inside liboilpaint.so,
+reached through its C-ABI (include/oilpaint.h).  This package is the thin
+Python side: `binding` marshals torch tensors into that ABI, `batch` and
+`serve` drive the batched and served forms, `synth` draws seeded inputs.
+
+Submodules are imported lazily so that `synth` can be used without loading
+the GPU library.
+"""
+import importlib
+
+__all__ = ["binding", "synth", "batch", "serve", "tune"]
+
+
+def __getattr__(name):
+    if name in __all__:
+        return importlib.import_module("." + name, __name__)
+    raise AttributeError(name)
