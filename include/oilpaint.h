@@ -1,0 +1,215 @@
+/*
+ * oilpaint.h -- C-ABI of liboilpaint.so, the gfx950 (MI355X) oil-paint filter.
+ *
+ * The operation (Mukherjee, "Study on performance improvement of oil paint
+ * image filter algorithm using parallel pattern library", Section 4: the
+ * histogram-based algorithm, its interface ApplyOilPaintOnBuffer and its
+ * serial listing; Section 5 keeps the same interface for the parallel form):
+ *
+ *   For every output pixel (x, y) of an interleaved 8-bit, 3-channel image,
+ *   each pixel of the (2r+1) x (2r+1) window around (x, y) is given the
+ *   intensity level  k = ((c0 + c1 + c2) / 3) * L / 256  (unsigned integer
+ *   arithmetic, truncating, left to right; k in [0, L)).  Per level the
+ *   number of window pixels and the three channel sums are kept.  The level
+ *   holding the most pixels is chosen -- the lowest level when several hold
+ *   the same largest number -- and each output channel is that level's
+ *   channel sum divided by its pixel count, truncated.
+ *
+ *   The window is clipped to the image: near the border only its in-image
+ *   pixels take part, and every pixel of the image is written.  (The paper's
+ *   listing processes only the interior [r, W-r) x [r, H-r); that literal
+ *   form is OILPAINT_FLAG_PAPER below.)  The result is a unique byte array:
+ *   it is bit-exact, with no tolerance.
+ *
+ * Conventions shared by every entry point:
+ *   - Images are `height` rows of `width` pixels; a pixel is 3 bytes
+ *     (c0, c1, c2), and row y starts at byte y * stride.  One `stride`
+ *     (bytes, >= 3 * width) serves src and dst.  Bytes [3*width, stride) of
+ *     a row are neither read nor written.  Channel order does not matter:
+ *     the filter commutes with any permutation of the three channels.
+ *   - src and dst are device pointers (hipMalloc'd, or any memory the
+ *     current device can access) owned by the caller; the library keeps no
+ *     reference to them after the work completes.  src and dst must not
+ *     overlap (the filter is not in-place, as in the paper, whose caller
+ *     allocates a separate output buffer).
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  *_async calls only enqueue work.
+ *   - Every call returns an int status: OILPAINT_OK (0) or a negative
+ *     OILPAINT_ERR_* code.  On any error nothing is enqueued and dst is left
+ *     untouched.  An image with width == 0 or height == 0 is a no-op that
+ *     returns OILPAINT_OK once the pointers and sizes are valid.
+ *   - radius: 0 <= r <= 65535.  Any r >= max(width, height) - 1 behaves as
+ *     that value (every window already holds the whole image); an image whose
+ *     effective radius exceeds 2051 returns OILPAINT_ERR_UNSUPPORTED (the
+ *     32-bit window sums could overflow).  levels: 1 <= L <= 256.
+ *   - The library is thread-safe for calls on different streams; calls that
+ *     share an oilpaint_plan or oilpaint_queue must be serialised by the
+ *     caller.
+ */
+#ifndef OILPAINT_H
+#define OILPAINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OILPAINT_ABI_VERSION 1
+
+/* Status codes. */
+#define OILPAINT_OK              0
+#define OILPAINT_ERR_NULL       -1  /* a required pointer is NULL (the paper's E_FAIL case) */
+#define OILPAINT_ERR_ARG        -2  /* a size, radius, level count, stride or row range is invalid */
+#define OILPAINT_ERR_OVERLAP    -3  /* src and dst byte ranges overlap */
+#define OILPAINT_ERR_NOT_DEVICE -4  /* src or dst is not memory the current device can access */
+#define OILPAINT_ERR_HIP        -5  /* a HIP runtime call failed */
+#define OILPAINT_ERR_NOMEM      -6  /* the library could not allocate its own scratch */
+#define OILPAINT_ERR_FULL       -7  /* an oilpaint_queue has no free slot */
+#define OILPAINT_ERR_UNSUPPORTED -8 /* a combination this build does not handle (see each call) */
+
+/* Flags (oilpaint_desc.flags). */
+#define OILPAINT_FLAG_PAPER 1u  /* the paper's listing taken literally: level
+                                   ((c0+c1+c2) * L / 3.0) / 255 truncated, which
+                                   has L+1 levels of which the last (pure white)
+                                   is never chosen; only the interior
+                                   [r, W-r) x [r, H-r) is written; a pixel whose
+                                   scanned levels are all empty is not written */
+
+/* Library version (OILPAINT_ABI_VERSION). */
+int oilpaint_version(void);
+
+/* Static text for a status code; never NULL. */
+const char *oilpaint_strerror(int status);
+
+/* Text of the last HIP runtime failure seen by the library on the calling
+ * thread ("" if none): the call that failed and HIP's message.  Valid until
+ * the thread's next library call. */
+const char *oilpaint_last_error(void);
+
+/* Pure host-side argument check, no HIP call and no GPU needed: the checks
+ * every entry point runs first.  Returns OILPAINT_OK, ERR_NULL, ERR_ARG or
+ * ERR_OVERLAP (byte ranges [p, p + (height-1)*stride + 3*width) of src and
+ * dst intersect). */
+int oilpaint_validate(const uint8_t *src, const uint8_t *dst, int width, int height, int stride,
+                      int radius, int levels);
+
+/* Filter one image and wait for it: enqueue on the default stream, then
+ * synchronize that stream (Section 4 interface: input buffer, size, level
+ * count, radius, output buffer). */
+int oilpaint(const uint8_t *src, uint8_t *dst, int width, int height, int stride, int radius,
+             int levels);
+
+/* Filter one image asynchronously on `stream` with the launch shape the
+ * library picks for (radius, levels) -- its built-in choice or the one
+ * installed by oilpaint_set_variant. */
+int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int stride,
+                   int radius, int levels, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Launch shapes ("variants").  A tile of the image is computed by one
+ * workgroup of `waves` wavefronts of 64 lanes; each lane owns one output
+ * column and slides its window histogram down `rows` output rows.  `hist`
+ * selects the per-lane histogram layout:
+ *   OILPAINT_HIST_PACKED  one 64-bit word per level (count:10 | three
+ *                         18-bit channel sums), the tile and its halo staged
+ *                         on chip; windows up to 31 x 31 (radius <= 15) and
+ *                         levels <= 255 (<= 254 with OILPAINT_FLAG_PAPER)
+ *   OILPAINT_HIST_WIDE    32-bit count and sums, pixels read from device
+ *                         memory; any level count and radius up to 2051
+ * ------------------------------------------------------------------------- */
+#define OILPAINT_HIST_PACKED 0
+#define OILPAINT_HIST_WIDE   2
+
+typedef struct oilpaint_variant {
+    int32_t rows;   /* output rows per lane, >= 1 */
+    int32_t waves;  /* wavefronts per workgroup, 1..16 */
+    int32_t hist;   /* OILPAINT_HIST_* */
+    int32_t lanes;  /* active lanes (= output columns) per wavefront: 64, 32 or 16 */
+} oilpaint_variant;
+
+/* The variant oilpaint_async would use for (radius, levels) and an image of
+ * the given size.  Returns OK or ERR_ARG / ERR_NULL. */
+int oilpaint_pick_variant(int width, int height, int radius, int levels, oilpaint_variant *out);
+
+/* Install `v` as the choice for (radius, levels) (the autotuner's result).
+ * Returns ERR_UNSUPPORTED if v cannot run (radius, levels) -- for example a
+ * PACKED layout for a window wider than 31, or a shape whose on-chip memory
+ * exceeds the device's. */
+int oilpaint_set_variant(int radius, int levels, const oilpaint_variant *v);
+
+/* Forget every installed choice. */
+int oilpaint_clear_variants(void);
+
+/* Filter one image with an explicit variant (for tuning and tests). */
+int oilpaint_async_variant(const uint8_t *src, uint8_t *dst, int width, int height, int stride,
+                           int radius, int levels, const oilpaint_variant *v, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many images of uneven size, radius and level count in ONE
+ * persistent launch over a flattened tile queue.
+ * ------------------------------------------------------------------------- */
+typedef struct oilpaint_desc {
+    const uint8_t *src;    /* device pointer, image as above */
+    uint8_t *dst;          /* device pointer, disjoint from src */
+    int32_t width, height, stride, radius, levels;
+    int32_t row_begin;     /* compute output rows [row_begin, row_end) only; */
+    int32_t row_end;       /* row_begin = row_end = 0 selects every row      */
+    uint32_t flags;        /* OILPAINT_FLAG_* */
+} oilpaint_desc;
+
+/* Validate all n descriptors (all or nothing: on error *bad_index, if not
+ * NULL, receives the first failing index and nothing is enqueued), then
+ * enqueue one persistent launch on `stream` that computes every image.
+ * The descriptor array is copied; it may be reused when the call returns. */
+int oilpaint_batch(const oilpaint_desc *descs, int n, void *stream, int *bad_index);
+
+/* A batch plan: the descriptors are validated and laid out once (tile queue
+ * in device memory, ordered by estimated cost) and the launch -- a counter
+ * reset kernel plus the persistent kernel -- is captured in a hipGraph that
+ * oilpaint_plan_launch replays.  Replays compute the same descriptors; the
+ * caller may change the CONTENTS of the src images between replays. */
+typedef struct oilpaint_plan oilpaint_plan;
+int oilpaint_plan_create(const oilpaint_desc *descs, int n, void *stream, oilpaint_plan **out,
+                         int *bad_index);
+int oilpaint_plan_launch(oilpaint_plan *plan, void *stream);
+/* Number of tiles and of workgroups of the persistent launch. */
+int oilpaint_plan_info(const oilpaint_plan *plan, int *tiles, int *workgroups);
+int oilpaint_plan_destroy(oilpaint_plan *plan);
+
+/* ---------------------------------------------------------------------------
+ * Continuous batching.  A queue accepts filter requests at any time; each
+ * oilpaint_queue_step (also run by push and poll) packs the work that is
+ * waiting -- new requests and the unfinished rows of running ones -- into
+ * one persistent launch of at most `step_pixels` output pixels, keeping at
+ * most two launches in flight on the queue's stream, so that requests that
+ * arrive while others are on the GPU share the next launch with them.
+ * ------------------------------------------------------------------------- */
+typedef struct oilpaint_queue oilpaint_queue;
+
+/* capacity: most requests held at once (pending or running).  step_pixels:
+ * work per launch (output pixels, >= 1; 0 picks a default).  The queue uses
+ * its own non-blocking stream on the current device. */
+int oilpaint_queue_create(int capacity, int64_t step_pixels, oilpaint_queue **out);
+/* Append one request.  *ticket receives its id.  ERR_FULL if `capacity`
+ * requests are already held.  The descriptor is copied; the images must stay
+ * valid until the request is reported done. */
+int oilpaint_queue_push(oilpaint_queue *q, const oilpaint_desc *desc, uint64_t *ticket);
+/* Make progress without blocking; returns the number of launches enqueued. */
+int oilpaint_queue_step(oilpaint_queue *q);
+/* 1 if the request's output is complete (its bytes are in dst and visible
+ * to later work on any stream), 0 if not yet, ERR_ARG for an unknown ticket.
+ * Once poll has returned 1 for a ticket the queue forgets it. */
+int oilpaint_queue_poll(oilpaint_queue *q, uint64_t ticket);
+/* Block until every pushed request is complete. */
+int oilpaint_queue_drain(oilpaint_queue *q);
+/* The queue's stream (hipStream_t as void*). */
+void *oilpaint_queue_stream(oilpaint_queue *q);
+int oilpaint_queue_destroy(oilpaint_queue *q);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OILPAINT_H */

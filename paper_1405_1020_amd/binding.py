@@ -1,0 +1,343 @@
+"""ctypes binding of liboilpaint.so (include/oilpaint.h), same names.
+
+Argument marshalling only: torch supplies device memory and streams, every
+step of the filter runs in the library's HIP kernels.  There is no CPU
+fallback: if the library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "liboilpaint.so")
+HEADER = os.path.join(ROOT, "include", "oilpaint.h")
+
+OK = 0
+ERR_NULL = -1
+ERR_ARG = -2
+ERR_OVERLAP = -3
+ERR_NOT_DEVICE = -4
+ERR_HIP = -5
+ERR_NOMEM = -6
+ERR_FULL = -7
+ERR_UNSUPPORTED = -8
+
+HIST_PACKED = 0
+HIST_WIDE = 2
+FLAG_PAPER = 1
+
+
+class OilpaintError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = strerror(status) if _lib is not None else str(status)
+        if status == ERR_HIP and _lib is not None:
+            msg += " [" + _lib.oilpaint_last_error().decode() + "]"
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+class Variant(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("hist", ctypes.c_int32), ("lanes", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.rows, self.waves, self.hist, self.lanes)
+
+    def __repr__(self):
+        return "Variant(rows=%d, waves=%d, hist=%d, lanes=%d)" % self.as_tuple()
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("radius", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("row_begin", ctypes.c_int32), ("row_end", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+_SIGS = {
+    "oilpaint_version": ([], ctypes.c_int),
+    "oilpaint_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "oilpaint_last_error": ([], ctypes.c_char_p),
+    "oilpaint_validate": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5, ctypes.c_int),
+    "oilpaint": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5, ctypes.c_int),
+    "oilpaint_async": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5 + [ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_pick_variant": ([ctypes.c_int] * 4 + [ctypes.POINTER(Variant)], ctypes.c_int),
+    "oilpaint_set_variant": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(Variant)], ctypes.c_int),
+    "oilpaint_clear_variants": ([], ctypes.c_int),
+    "oilpaint_async_variant": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5
+                               + [ctypes.POINTER(Variant), ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_batch": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
+                       ctypes.c_int),
+    "oilpaint_plan_create": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p,
+                              ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "oilpaint_plan_launch": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_plan_info": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                           ctypes.c_int),
+    "oilpaint_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_queue_create": ([ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "oilpaint_queue_push": ([ctypes.c_void_p, ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_uint64)],
+                            ctypes.c_int),
+    "oilpaint_queue_step": ([ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_queue_poll": ([ctypes.c_void_p, ctypes.c_uint64], ctypes.c_int),
+    "oilpaint_queue_drain": ([ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_queue_stream": ([ctypes.c_void_p], ctypes.c_void_p),
+    "oilpaint_queue_destroy": ([ctypes.c_void_p], ctypes.c_int),
+}
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/oilpaint.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(oilpaint\w*)\s*\(", text)))
+
+
+def lib():
+    """Load liboilpaint.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OilpaintError(ERR_UNSUPPORTED,
+                                "liboilpaint.so is not built (python -m paper_1405_1020_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (argt, rest) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = argt
+            fn.restype = rest
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().oilpaint_strerror(status).decode()
+
+
+def version() -> int:
+    return lib().oilpaint_version()
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise OilpaintError(st, what)
+    return st
+
+
+# ---------------------------------------------------------------------------
+# torch marshalling
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def image_geometry(t) -> tuple[int, int, int]:
+    """(width, height, stride) of a uint8 [H, W, 3] tensor whose pixels are
+    packed (strides (S, 3, 1)); S is the row stride in bytes."""
+    torch = _torch()
+    if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[2] != 3:
+        raise ValueError("expected a uint8 [H, W, 3] tensor")
+    h, w, _ = t.shape
+    sh, sw, sc = t.stride()
+    if h > 0 and w > 0 and (sc != 1 or sw != 3 or (h > 1 and sh < 3 * w)):
+        raise ValueError("pixels must be packed: strides (S >= 3W, 3, 1), got %s" % (t.stride(),))
+    stride = sh if h > 1 else 3 * w
+    return w, h, stride
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise OilpaintError(ERR_NOT_DEVICE, "tensor is not on a GPU")
+
+
+def validate(src_ptr: int, dst_ptr: int, width: int, height: int, stride: int, radius: int,
+             levels: int) -> int:
+    """oilpaint_validate on raw addresses (pure host, no GPU needed)."""
+    return lib().oilpaint_validate(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), width, height,
+                                   stride, radius, levels)
+
+
+def oilpaint_async(src, dst, radius: int, levels: int, stream=None, variant: Variant | None = None):
+    """Enqueue the filter of src into dst (uint8 [H, W, 3] CUDA tensors with
+    the same geometry) on `stream` (default: torch's current stream)."""
+    _require_cuda(src, dst)
+    w, h, s = image_geometry(src)
+    w2, h2, s2 = image_geometry(dst)
+    if (w, h) != (w2, h2) or (h > 1 and s != s2):
+        raise ValueError("src and dst must have the same width, height and row stride")
+    L = lib()
+    if w == 0 or h == 0:
+        return OK  # nothing to filter (an empty tensor has no storage pointer)
+    if variant is None:
+        st = L.oilpaint_async(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                              w, h, s, radius, levels, _stream_ptr(stream))
+    else:
+        st = L.oilpaint_async_variant(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                      w, h, s, radius, levels, ctypes.byref(variant), _stream_ptr(stream))
+    return _check(st, "oilpaint_async")
+
+
+def oilpaint(src, radius: int, levels: int, out=None, stream=None, variant: Variant | None = None):
+    """Filter a uint8 [H, W, 3] CUDA tensor; returns `out` (allocated if None)."""
+    torch = _torch()
+    if out is None:
+        # one row stride serves both buffers: give dst the source's
+        w, h, s = image_geometry(src)
+        buf = torch.empty(max(h - 1, 0) * s + 3 * w, dtype=torch.uint8, device=src.device)
+        out = buf.as_strided((h, w, 3), (s, 3, 1))
+    oilpaint_async(src, out, radius, levels, stream=stream, variant=variant)
+    return out
+
+
+def pick_variant(width: int, height: int, radius: int, levels: int) -> Variant:
+    v = Variant()
+    _check(lib().oilpaint_pick_variant(width, height, radius, levels, ctypes.byref(v)), "pick_variant")
+    return v
+
+
+def set_variant(radius: int, levels: int, v: Variant) -> int:
+    return lib().oilpaint_set_variant(radius, levels, ctypes.byref(v))
+
+
+def clear_variants():
+    lib().oilpaint_clear_variants()
+
+
+@dataclass
+class Item:
+    """One image of a batch: src/dst CUDA tensors and its parameters."""
+    src: object
+    dst: object
+    radius: int
+    levels: int
+    row_begin: int = 0
+    row_end: int = 0
+    flags: int = 0
+
+
+def make_desc(it: Item) -> Desc:
+    _require_cuda(it.src, it.dst)
+    w, h, s = image_geometry(it.src)
+    w2, h2, s2 = image_geometry(it.dst)
+    if (w, h) != (w2, h2) or (h > 1 and s != s2):
+        raise ValueError("src and dst must have the same width, height and row stride")
+    return Desc(it.src.data_ptr(), it.dst.data_ptr(), w, h, s, it.radius, it.levels,
+                it.row_begin, it.row_end, it.flags)
+
+
+def _desc_array(items):
+    arr = (Desc * max(1, len(items)))()
+    for i, it in enumerate(items):
+        arr[i] = it if isinstance(it, Desc) else make_desc(it)
+    return arr
+
+
+def batch(items, stream=None) -> None:
+    """oilpaint_batch: one persistent launch over every item."""
+    arr = _desc_array(items)
+    bad = ctypes.c_int(-1)
+    st = lib().oilpaint_batch(arr, len(items), _stream_ptr(stream), ctypes.byref(bad))
+    if st != OK:
+        raise OilpaintError(st, "oilpaint_batch (item %d)" % bad.value)
+
+
+class Plan:
+    """oilpaint_plan: the batch laid out once and captured in a hipGraph."""
+
+    def __init__(self, items, stream=None):
+        self._items = list(items)  # keep the tensors alive
+        arr = _desc_array(self._items)
+        h = ctypes.c_void_p()
+        bad = ctypes.c_int(-1)
+        st = lib().oilpaint_plan_create(arr, len(self._items), _stream_ptr(stream), ctypes.byref(h),
+                                        ctypes.byref(bad))
+        if st != OK:
+            raise OilpaintError(st, "oilpaint_plan_create (item %d)" % bad.value)
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().oilpaint_plan_launch(self._h, _stream_ptr(stream)), "oilpaint_plan_launch")
+
+    def info(self) -> tuple[int, int]:
+        t, g = ctypes.c_int(), ctypes.c_int()
+        _check(lib().oilpaint_plan_info(self._h, ctypes.byref(t), ctypes.byref(g)), "oilpaint_plan_info")
+        return t.value, g.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().oilpaint_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Queue:
+    """oilpaint_queue: continuous batching of filter requests."""
+
+    def __init__(self, capacity: int = 4096, step_pixels: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().oilpaint_queue_create(capacity, step_pixels, ctypes.byref(h)), "oilpaint_queue_create")
+        self._h = h
+
+    def push(self, item) -> int:
+        d = item if isinstance(item, Desc) else make_desc(item)
+        t = ctypes.c_uint64()
+        st = lib().oilpaint_queue_push(self._h, ctypes.byref(d), ctypes.byref(t))
+        if st != OK:
+            raise OilpaintError(st, "oilpaint_queue_push")
+        return t.value
+
+    def try_push(self, item) -> tuple[int, int]:
+        """(status, ticket) without raising on ERR_FULL."""
+        d = item if isinstance(item, Desc) else make_desc(item)
+        t = ctypes.c_uint64()
+        st = lib().oilpaint_queue_push(self._h, ctypes.byref(d), ctypes.byref(t))
+        return st, t.value
+
+    def step(self) -> int:
+        st = lib().oilpaint_queue_step(self._h)
+        if st < 0:
+            raise OilpaintError(st, "oilpaint_queue_step")
+        return st
+
+    def poll(self, ticket: int) -> bool:
+        st = lib().oilpaint_queue_poll(self._h, ticket)
+        if st < 0:
+            raise OilpaintError(st, "oilpaint_queue_poll")
+        return st == 1
+
+    def drain(self):
+        _check(lib().oilpaint_queue_drain(self._h), "oilpaint_queue_drain")
+
+    def stream_ptr(self) -> int:
+        return lib().oilpaint_queue_stream(self._h) or 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().oilpaint_queue_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,317 @@
+// Host side of liboilpaint.so: argument validation, launch-shape choice and
+// the single-image entry points of include/oilpaint.h.
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "oilpaint_internal.h"
+
+namespace oilpaint_impl {
+
+namespace {
+thread_local char g_last_error[256] = "";
+}
+
+hipError_t note_hip(const char* where, hipError_t e) {
+    if (e != hipSuccess) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+        (void)hipGetLastError();
+    }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// Device facts
+// ---------------------------------------------------------------------------
+DeviceInfo device_info(int device) {
+    static std::mutex mu;
+    static std::map<int, DeviceInfo> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(device);
+    if (it != cache.end()) return it->second;
+    DeviceInfo d{0, 0, 0};
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) == hipSuccess) {
+        d.cus = p.multiProcessorCount;
+        d.lds_per_block = p.sharedMemPerBlock;
+        d.ok = 1;
+    }
+    cache[device] = d;
+    return d;
+}
+
+size_t lds_bytes(const Job& j) {
+    const int waves = j.waves;
+    const size_t nb = (size_t)hist_bins(j);
+    const size_t lanes = (size_t)j.lanes;
+    if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
+    const size_t tw = lanes + 2 * (size_t)j.radius;
+    const size_t th = (size_t)waves * (size_t)j.rows + 2 * (size_t)j.radius;
+    const size_t tile = (tw * th * 4 + 15) & ~(size_t)15;
+    return tile + (size_t)waves * nb * lanes * 8;
+}
+
+namespace {
+
+// Static LDS the kernels declare besides the dynamic block, with slack.
+constexpr size_t kStaticLds = 256;
+
+int effective_radius(int width, int height, int radius) {
+    const int span = std::max(width, height) - 1;
+    return std::min(radius, std::max(span, 0));
+}
+
+bool ranges_overlap(const uint8_t* a, const uint8_t* b, size_t len) {
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + len && pb < pa + len;
+}
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, oilpaint_variant> g_tuned;
+
+bool packed_ok(int reff, int levels, bool paper) {
+    return reff <= kPackedMaxRadius && levels + (paper ? 1 : 0) <= 255;
+}
+
+}  // namespace
+
+// Fill the launch-shape fields of `j` from `v`.  Returns OK or UNSUPPORTED.
+int apply_variant(Job& j, const oilpaint_variant& v, int device) {
+    if (v.rows < 1 || v.rows > 4096 || v.waves < 1 || v.waves > 16) return OILPAINT_ERR_UNSUPPORTED;
+    if (v.lanes != 64 && v.lanes != 32 && v.lanes != 16) return OILPAINT_ERR_UNSUPPORTED;
+    if (v.hist == OILPAINT_HIST_PACKED) {
+        if (!packed_ok(j.radius, j.levels, j.paper != 0)) return OILPAINT_ERR_UNSUPPORTED;
+    } else if (v.hist == OILPAINT_HIST_WIDE) {
+        if (j.radius > kWideMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
+    } else {
+        return OILPAINT_ERR_UNSUPPORTED;
+    }
+    j.rows = v.rows;
+    j.lanes = v.lanes;
+    j.hist = v.hist;
+    j.waves = v.waves;
+    const DeviceInfo d = device_info(device);
+    const size_t limit = d.ok ? d.lds_per_block : 65536;
+    if (lds_bytes(j) + kStaticLds > limit) return OILPAINT_ERR_UNSUPPORTED;
+    const int band = j.row_end - j.row_begin;
+    j.tiles_x = (j.width + j.lanes - 1) / j.lanes;
+    const long per_tile = (long)v.waves * j.rows;
+    j.tiles_y = (int)((band + per_tile - 1) / per_tile);
+    return OILPAINT_OK;
+}
+
+// The built-in launch shape for an image (before any tuning result).
+oilpaint_variant default_variant(int width, int height, int reff, int levels, bool paper, int device) {
+    oilpaint_variant v;
+    v.lanes = 64;
+    v.waves = 4;
+    v.hist = packed_ok(reff, levels, paper) ? OILPAINT_HIST_PACKED : OILPAINT_HIST_WIDE;
+    const DeviceInfo d = device_info(device);
+    const int cus = d.ok ? d.cus : 256;
+    // rows per lane: long runs amortise the (2r+1)^2 first window, short
+    // runs give more workgroups; aim for about two tiles per CU.
+    const long strips = (width + 63) / 64;
+    const long want = 2L * cus;
+    long rows = (strips * (long)height + want * v.waves - 1) / (want * v.waves);
+    const long cap = reff <= 2 ? 16 : reff <= 6 ? 32 : 64;
+    rows = std::max(8L, std::min(rows, cap));
+    v.rows = (int)rows;
+    if (v.hist == OILPAINT_HIST_WIDE) {
+        v.rows = std::min(v.rows, 16);
+    }
+    // shrink until the on-chip footprint fits
+    Job j{};
+    j.width = width;
+    j.height = height;
+    j.radius = reff;
+    j.levels = levels;
+    j.paper = paper ? 1 : 0;
+    j.row_begin = 0;
+    j.row_end = height;
+    const size_t limit = (d.ok ? d.lds_per_block : 65536) - kStaticLds;
+    for (;;) {
+        j.rows = v.rows;
+        j.lanes = v.lanes;
+        j.hist = v.hist;
+        j.waves = v.waves;
+        if (lds_bytes(j) <= limit) break;
+        if (v.waves > 1)
+            v.waves >>= 1;
+        else if (v.rows > 8)
+            v.rows >>= 1;
+        else if (v.lanes > 16)
+            v.lanes >>= 1;
+        else
+            break;
+    }
+    return v;
+}
+
+oilpaint_variant choose_variant(int width, int height, int reff, int levels, bool paper, int device) {
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find({reff, levels});
+        if (it != g_tuned.end() && !paper) return it->second;
+    }
+    return default_variant(width, height, reff, levels, paper, device);
+}
+
+// Validate a descriptor and build its Job (shape from `v`, or the library's
+// choice when v is NULL).  Pure host work apart from device facts.
+int make_job(const oilpaint_desc& d, const oilpaint_variant* v, int device, Job& j, bool& empty) {
+    const int st = oilpaint_validate(d.src, d.dst, d.width, d.height, d.stride, d.radius, d.levels);
+    if (st != OILPAINT_OK) return st;
+    if (d.flags & ~OILPAINT_FLAG_PAPER) return OILPAINT_ERR_ARG;
+    int rb = d.row_begin, re = d.row_end;
+    if (rb == 0 && re == 0) re = d.height;
+    if (rb < 0 || re < rb || re > d.height) return OILPAINT_ERR_ARG;
+    empty = d.width == 0 || d.height == 0 || rb == re;
+    std::memset(&j, 0, sizeof(j));
+    j.src = d.src;
+    j.dst = d.dst;
+    j.width = d.width;
+    j.height = d.height;
+    j.stride = d.stride;
+    j.radius = effective_radius(d.width, d.height, d.radius);
+    j.levels = d.levels;
+    j.row_begin = rb;
+    j.row_end = re;
+    j.paper = (d.flags & OILPAINT_FLAG_PAPER) ? 1 : 0;
+    if (j.radius > kWideMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
+    if (empty) return OILPAINT_OK;
+    const oilpaint_variant use =
+        v ? *v : choose_variant(d.width, d.height, j.radius, d.levels, j.paper != 0, device);
+    return apply_variant(j, use, device);
+}
+
+// Device-accessibility check of one pointer (ERR_NOT_DEVICE if host-only).
+int check_device_ptr(const void* p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return OILPAINT_ERR_NOT_DEVICE;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return OILPAINT_OK;
+    if (a.type == hipMemoryTypeHost && a.devicePointer != nullptr) return OILPAINT_OK;  // mapped pinned
+    return OILPAINT_ERR_NOT_DEVICE;
+}
+
+}  // namespace oilpaint_impl
+
+using namespace oilpaint_impl;
+
+extern "C" {
+
+int oilpaint_version(void) { return OILPAINT_ABI_VERSION; }
+
+const char* oilpaint_last_error(void) { return g_last_error; }
+
+const char* oilpaint_strerror(int status) {
+    switch (status) {
+        case OILPAINT_OK: return "ok";
+        case OILPAINT_ERR_NULL: return "null pointer";
+        case OILPAINT_ERR_ARG: return "invalid argument (size, radius, levels, stride or row range)";
+        case OILPAINT_ERR_OVERLAP: return "source and destination overlap";
+        case OILPAINT_ERR_NOT_DEVICE: return "pointer is not device memory";
+        case OILPAINT_ERR_HIP: return "HIP runtime error";
+        case OILPAINT_ERR_NOMEM: return "out of memory";
+        case OILPAINT_ERR_FULL: return "queue full";
+        case OILPAINT_ERR_UNSUPPORTED: return "unsupported combination";
+        default: return "unknown status";
+    }
+}
+
+int oilpaint_validate(const uint8_t* src, const uint8_t* dst, int width, int height, int stride, int radius,
+                      int levels) {
+    if (!src || !dst) return OILPAINT_ERR_NULL;
+    if (width < 0 || height < 0 || radius < 0 || radius > 65535) return OILPAINT_ERR_ARG;
+    if (levels < 1 || levels > 256) return OILPAINT_ERR_ARG;
+    if (width > INT_MAX / 3) return OILPAINT_ERR_ARG;
+    if (stride < 3 * width) return OILPAINT_ERR_ARG;
+    if (width == 0 || height == 0) return OILPAINT_OK;
+    const size_t span = (size_t)(height - 1) * (size_t)stride + 3 * (size_t)width;
+    if ((uintptr_t)src + span < (uintptr_t)src || (uintptr_t)dst + span < (uintptr_t)dst) return OILPAINT_ERR_ARG;
+    if (ranges_overlap(src, dst, span)) return OILPAINT_ERR_OVERLAP;
+    return OILPAINT_OK;
+}
+
+static int launch_one(const uint8_t* src, uint8_t* dst, int width, int height, int stride, int radius, int levels,
+                      const oilpaint_variant* v, hipStream_t stream) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return OILPAINT_ERR_HIP;
+    oilpaint_desc d{};
+    d.src = src;
+    d.dst = dst;
+    d.width = width;
+    d.height = height;
+    d.stride = stride;
+    d.radius = radius;
+    d.levels = levels;
+    Job j;
+    bool empty = false;
+    int st = make_job(d, v, device, j, empty);
+    if (st != OILPAINT_OK || empty) return st;
+    if ((st = check_device_ptr(src)) != OILPAINT_OK) return st;
+    if ((st = check_device_ptr(dst)) != OILPAINT_OK) return st;
+    const size_t lds = lds_bytes(j);
+    if (launch_plain(j, j.waves, lds, stream) != hipSuccess) return OILPAINT_ERR_HIP;
+    return OILPAINT_OK;
+}
+
+int oilpaint_async(const uint8_t* src, uint8_t* dst, int width, int height, int stride, int radius, int levels,
+                   void* stream) {
+    return launch_one(src, dst, width, height, stride, radius, levels, nullptr, (hipStream_t)stream);
+}
+
+int oilpaint_async_variant(const uint8_t* src, uint8_t* dst, int width, int height, int stride, int radius,
+                           int levels, const oilpaint_variant* v, void* stream) {
+    if (!v) return OILPAINT_ERR_NULL;
+    return launch_one(src, dst, width, height, stride, radius, levels, v, (hipStream_t)stream);
+}
+
+int oilpaint(const uint8_t* src, uint8_t* dst, int width, int height, int stride, int radius, int levels) {
+    const int st = launch_one(src, dst, width, height, stride, radius, levels, nullptr, nullptr);
+    if (st != OILPAINT_OK) return st;
+    if (note_hip("hipStreamSynchronize", hipStreamSynchronize(nullptr)) != hipSuccess) return OILPAINT_ERR_HIP;
+    return OILPAINT_OK;
+}
+
+int oilpaint_pick_variant(int width, int height, int radius, int levels, oilpaint_variant* out) {
+    if (!out) return OILPAINT_ERR_NULL;
+    if (width < 0 || height < 0 || radius < 0 || radius > 65535 || levels < 1 || levels > 256)
+        return OILPAINT_ERR_ARG;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) device = 0;
+    *out = choose_variant(width, height, effective_radius(width, height, radius), levels, false, device);
+    return OILPAINT_OK;
+}
+
+int oilpaint_set_variant(int radius, int levels, const oilpaint_variant* v) {
+    if (!v) return OILPAINT_ERR_NULL;
+    if (radius < 0 || radius > 65535 || levels < 1 || levels > 256) return OILPAINT_ERR_ARG;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) device = 0;
+    Job j{};
+    j.width = 1 << 20;
+    j.height = 1 << 20;
+    j.radius = radius;
+    j.levels = levels;
+    j.row_begin = 0;
+    j.row_end = 1;
+    const int st = apply_variant(j, *v, device);
+    if (st != OILPAINT_OK) return st;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned[{radius, levels}] = *v;
+    return OILPAINT_OK;
+}
+
+int oilpaint_clear_variants(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned.clear();
+    return OILPAINT_OK;
+}
+
+}  // extern "C"

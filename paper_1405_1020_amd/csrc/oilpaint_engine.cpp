@@ -1,0 +1,532 @@
+// Batched and served forms of the filter: one persistent launch over a
+// flattened tile queue (oilpaint_batch), the same launch captured once in a
+// hipGraph and replayed (oilpaint_plan_*), and a continuous-batching request
+// queue that packs waiting work into successive persistent launches
+// (oilpaint_queue_*).
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "oilpaint_internal.h"
+
+namespace oilpaint_impl {
+
+int make_job(const oilpaint_desc& d, const oilpaint_variant* v, int device, Job& j, bool& empty);
+int apply_variant(Job& j, const oilpaint_variant& v, int device);
+int check_device_ptr(const void* p);
+oilpaint_variant choose_variant(int width, int height, int reff, int levels, bool paper, int device);
+
+namespace {
+
+constexpr int kBatchWaves = 4;
+
+// Launch shape of a job inside a persistent launch of `waves` wavefronts per
+// workgroup: the job's own choice with at most `waves` computing
+// wavefronts, shrunk (computing wavefronts, then rows, then lanes) until its
+// on-chip footprint fits.
+int batch_shape(Job& j, int waves, int device) {
+    oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
+    v.waves = std::min(std::max(v.waves, 1), waves);
+    for (;;) {
+        const int st = apply_variant(j, v, device);
+        if (st == OILPAINT_OK) return st;
+        if (v.waves > 1)
+            v.waves >>= 1;
+        else if (v.rows > 8)
+            v.rows >>= 1;
+        else if (v.lanes > 16)
+            v.lanes >>= 1;
+        else
+            return st;
+    }
+}
+
+// Relative cost of one tile: window updates plus the mode search per output
+// pixel, plus the first window of every lane.
+double tile_cost(const Job& j) {
+    const double span = 2.0 * j.radius + 1.0;
+    const double px = (double)j.lanes * j.rows * j.waves;
+    return px * (2.0 * span + j.levels * 0.5 + 4.0) + (double)j.lanes * j.waves * span * span;
+}
+
+struct Layout {
+    std::vector<Job> jobs;        // queue order
+    std::vector<int32_t> first;   // njobs + 1
+    size_t lds = 0;
+    int ntiles = 0;
+};
+
+// Order jobs by tile cost (costliest first, so the long tiles start early
+// and the cheap ones fill the tail) and lay out the flattened tile queue.
+void build_layout(std::vector<Job>& jobs, Layout& out) {
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [&](const Job& a, const Job& b) { return tile_cost(a) > tile_cost(b); });
+    out.jobs = jobs;
+    out.first.assign(jobs.size() + 1, 0);
+    long total = 0;
+    size_t lds = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        out.first[i] = (int32_t)total;
+        total += (long)jobs[i].tiles_x * jobs[i].tiles_y;
+        lds = std::max(lds, lds_bytes(jobs[i]));
+    }
+    out.first[jobs.size()] = (int32_t)total;
+    out.ntiles = (int)total;
+    out.lds = lds;
+}
+
+// Bytes of the device argument block: counter, first_tile[], jobs[].
+size_t args_bytes(size_t njobs) {
+    return 256 + ((sizeof(int32_t) * (njobs + 1) + 255) & ~(size_t)255) + sizeof(Job) * njobs;
+}
+
+void pack_args(const Layout& L, uint8_t* host) {
+    std::memset(host, 0, 256);
+    const size_t fbytes = (sizeof(int32_t) * (L.jobs.size() + 1) + 255) & ~(size_t)255;
+    std::memcpy(host + 256, L.first.data(), sizeof(int32_t) * L.first.size());
+    std::memcpy(host + 256 + fbytes, L.jobs.data(), sizeof(Job) * L.jobs.size());
+}
+
+BatchArgs args_at(const Layout& L, uint8_t* dev) {
+    const size_t fbytes = (sizeof(int32_t) * (L.jobs.size() + 1) + 255) & ~(size_t)255;
+    BatchArgs a;
+    a.counter = reinterpret_cast<uint32_t*>(dev);
+    a.first_tile = reinterpret_cast<const int32_t*>(dev + 256);
+    a.jobs = reinterpret_cast<const Job*>(dev + 256 + fbytes);
+    a.njobs = (int32_t)L.jobs.size();
+    a.ntiles = L.ntiles;
+    return a;
+}
+
+// A small ring of (pinned host, device) argument buffers.  A slot is reused
+// only after the event recorded behind its last launch has completed.
+struct ArgSlot {
+    uint8_t* dev = nullptr;
+    uint8_t* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+class ArgRing {
+  public:
+    explicit ArgRing(int n) : slots_(n) {}
+    ~ArgRing() {
+        for (auto& s : slots_) {
+            if (s.pending) (void)hipEventSynchronize(s.done);
+            if (s.dev) (void)hipFree(s.dev);
+            if (s.host) (void)hipHostFree(s.host);
+            if (s.done) (void)hipEventDestroy(s.done);
+        }
+    }
+    // Returns a slot with at least `bytes` of capacity, or nullptr.
+    ArgSlot* acquire(size_t bytes) {
+        ArgSlot* s = &slots_[next_];
+        next_ = (next_ + 1) % slots_.size();
+        if (s->pending) {
+            if (hipEventSynchronize(s->done) != hipSuccess) return nullptr;
+            s->pending = false;
+        }
+        if (!s->done && hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) return nullptr;
+        if (s->cap < bytes) {
+            if (s->dev) (void)hipFree(s->dev);
+            if (s->host) (void)hipHostFree(s->host);
+            s->dev = nullptr;
+            s->host = nullptr;
+            s->cap = 0;
+            const size_t cap = std::max(bytes, (size_t)65536);
+            if (hipMalloc(&s->dev, cap) != hipSuccess) return nullptr;
+            if (hipHostMalloc(reinterpret_cast<void**>(&s->host), cap, hipHostMallocDefault) != hipSuccess) {
+                (void)hipFree(s->dev);
+                s->dev = nullptr;
+                return nullptr;
+            }
+            s->cap = cap;
+        }
+        return s;
+    }
+    void release(ArgSlot* s, hipStream_t stream) {
+        if (hipEventRecord(s->done, stream) == hipSuccess) s->pending = true;
+    }
+
+  private:
+    std::vector<ArgSlot> slots_;
+    size_t next_ = 0;
+};
+
+// Upload `L` through `ring` and enqueue reset + persistent kernel.
+int enqueue_layout(const Layout& L, int waves, int device, ArgRing& ring, hipStream_t stream) {
+    if (L.ntiles == 0) return OILPAINT_OK;
+    const size_t bytes = args_bytes(L.jobs.size());
+    ArgSlot* s = ring.acquire(bytes);
+    if (!s) return OILPAINT_ERR_NOMEM;
+    pack_args(L, s->host);
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(s->dev, s->host, bytes, hipMemcpyHostToDevice, stream)) !=
+        hipSuccess)
+        return OILPAINT_ERR_HIP;
+    const BatchArgs a = args_at(L, s->dev);
+    const int grid = std::min(batch_grid(device, waves, L.lds), L.ntiles);
+    if (launch_reset_counter(a.counter, stream) != hipSuccess) return OILPAINT_ERR_HIP;
+    if (launch_batch(a, waves, L.lds, grid, stream) != hipSuccess) return OILPAINT_ERR_HIP;
+    ring.release(s, stream);
+    return OILPAINT_OK;
+}
+
+ArgRing& device_ring(int device) {
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<ArgRing>> rings;
+    std::lock_guard<std::mutex> lock(mu);
+    auto& p = rings[device];
+    if (!p) p.reset(new ArgRing(8));
+    return *p;
+}
+
+std::mutex& ring_mutex(int device) {
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<std::mutex>> m;
+    std::lock_guard<std::mutex> lock(mu);
+    auto& p = m[device];
+    if (!p) p.reset(new std::mutex);
+    return *p;
+}
+
+// Validate all descriptors into jobs (empty images dropped).
+int collect_jobs(const oilpaint_desc* descs, int n, int device, std::vector<Job>& jobs, int* bad_index) {
+    if (n < 0) return OILPAINT_ERR_ARG;
+    if (n > 0 && !descs) return OILPAINT_ERR_NULL;
+    jobs.clear();
+    jobs.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        Job j;
+        bool empty = false;
+        int st = make_job(descs[i], nullptr, device, j, empty);
+        if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, device);
+        if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.src);
+        if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.dst);
+        if (st != OILPAINT_OK) {
+            if (bad_index) *bad_index = i;
+            return st;
+        }
+        if (!empty) jobs.push_back(j);
+    }
+    if (bad_index) *bad_index = -1;
+    return OILPAINT_OK;
+}
+
+}  // namespace
+}  // namespace oilpaint_impl
+
+using namespace oilpaint_impl;
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+struct oilpaint_plan {
+    int device = 0;
+    Layout layout;
+    uint8_t* dev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int grid = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Queue
+// ---------------------------------------------------------------------------
+struct QueueReq {
+    Job job;          // whole request (row_begin .. row_end)
+    int next_row;     // first output row not yet launched
+    int launches_left = 0;
+    bool all_launched = false;
+    bool done = false;
+};
+
+struct Inflight {
+    hipEvent_t ev;
+    std::vector<uint64_t> tickets;  // requests with a band in this launch
+};
+
+struct oilpaint_queue {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int capacity = 0;
+    int64_t step_pixels = 0;
+    uint64_t next_ticket = 1;
+    std::unordered_map<uint64_t, QueueReq> reqs;
+    std::deque<uint64_t> waiting;  // arrival order, some rows not launched
+    std::deque<Inflight> inflight;
+    std::vector<hipEvent_t> free_events;
+    std::unique_ptr<ArgRing> ring;
+    size_t held = 0;  // requests not yet reported complete
+};
+
+namespace {
+
+void retire(oilpaint_queue* q, bool block) {
+    while (!q->inflight.empty()) {
+        Inflight& f = q->inflight.front();
+        if (block) {
+            if (hipEventSynchronize(f.ev) != hipSuccess) return;
+        } else {
+            const hipError_t e = hipEventQuery(f.ev);
+            if (e == hipErrorNotReady) return;
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return;
+            }
+        }
+        for (uint64_t t : f.tickets) {
+            auto it = q->reqs.find(t);
+            if (it == q->reqs.end()) continue;
+            QueueReq& r = it->second;
+            if (--r.launches_left == 0 && r.all_launched && !r.done) {
+                r.done = true;
+                --q->held;
+            }
+        }
+        q->free_events.push_back(f.ev);
+        q->inflight.pop_front();
+        block = false;
+    }
+}
+
+// Pack waiting work into one launch.  Every waiting request gets an equal
+// share of the pixel budget (at least one tile row of its own shape), so a
+// small request that arrives behind a large one finishes in the next launch
+// instead of waiting for the large one to drain.
+int launch_step(oilpaint_queue* q) {
+    if (q->waiting.empty()) return 0;
+    std::vector<Job> jobs;
+    std::vector<uint64_t> tickets;
+    int64_t budget = q->step_pixels;
+    const int64_t share = std::max<int64_t>(1, budget / (int64_t)q->waiting.size());
+    std::deque<uint64_t> still;
+    for (uint64_t t : q->waiting) {
+        QueueReq& r = q->reqs[t];
+        if (budget <= 0) {
+            still.push_back(t);
+            continue;
+        }
+        const Job& w = r.job;
+        const int unit = std::max(1, w.waves * w.rows);  // rows per tile row
+        const int64_t row_px = (int64_t)w.width;
+        int64_t want_rows = std::max<int64_t>(unit, std::min<int64_t>(share, budget) / std::max<int64_t>(row_px, 1));
+        want_rows = (want_rows + unit - 1) / unit * unit;
+        const int rb = r.next_row;
+        const int re = (int)std::min<int64_t>(w.row_end, rb + want_rows);
+        Job band = w;
+        band.row_begin = rb;
+        band.row_end = re;
+        const long per_tile = (long)band.waves * band.rows;
+        band.tiles_y = (int)((re - rb + per_tile - 1) / per_tile);
+        jobs.push_back(band);
+        tickets.push_back(t);
+        r.next_row = re;
+        r.launches_left += 1;
+        budget -= (int64_t)(re - rb) * row_px;
+        if (re >= w.row_end)
+            r.all_launched = true;
+        else
+            still.push_back(t);
+    }
+    q->waiting.swap(still);
+    if (jobs.empty()) return 0;
+    Layout L;
+    build_layout(jobs, L);
+    int st = enqueue_layout(L, kBatchWaves, q->device, *q->ring, q->stream);
+    if (st != OILPAINT_OK) return st;
+    hipEvent_t ev;
+    if (!q->free_events.empty()) {
+        ev = q->free_events.back();
+        q->free_events.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        return OILPAINT_ERR_HIP;
+    }
+    if (hipEventRecord(ev, q->stream) != hipSuccess) return OILPAINT_ERR_HIP;
+    Inflight f;
+    f.ev = ev;
+    f.tickets = tickets;
+    q->inflight.push_back(f);
+    return 1;
+}
+
+int queue_progress(oilpaint_queue* q) {
+    retire(q, false);
+    int launched = 0;
+    while (q->inflight.size() < 2 && !q->waiting.empty()) {
+        const int st = launch_step(q);
+        if (st < 0) return st;
+        if (st == 0) break;
+        launched += st;
+    }
+    return launched;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oilpaint_batch(const oilpaint_desc* descs, int n, void* stream, int* bad_index) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return OILPAINT_ERR_HIP;
+    std::vector<Job> jobs;
+    int st = collect_jobs(descs, n, device, jobs, bad_index);
+    if (st != OILPAINT_OK || jobs.empty()) return st;
+    Layout L;
+    build_layout(jobs, L);
+    std::lock_guard<std::mutex> lock(ring_mutex(device));
+    return enqueue_layout(L, kBatchWaves, device, device_ring(device), (hipStream_t)stream);
+}
+
+int oilpaint_plan_create(const oilpaint_desc* descs, int n, void* stream, oilpaint_plan** out, int* bad_index) {
+    if (!out) return OILPAINT_ERR_NULL;
+    *out = nullptr;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return OILPAINT_ERR_HIP;
+    std::vector<Job> jobs;
+    int st = collect_jobs(descs, n, device, jobs, bad_index);
+    if (st != OILPAINT_OK) return st;
+    std::unique_ptr<oilpaint_plan> p(new oilpaint_plan);
+    p->device = device;
+    build_layout(jobs, p->layout);
+    const size_t bytes = args_bytes(p->layout.jobs.size());
+    if (hipMalloc(&p->dev, bytes) != hipSuccess) return OILPAINT_ERR_NOMEM;
+    std::vector<uint8_t> host(bytes);
+    pack_args(p->layout, host.data());
+    if (hipMemcpy(p->dev, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return OILPAINT_ERR_HIP;
+    p->grid = std::min(batch_grid(device, kBatchWaves, p->layout.lds), std::max(p->layout.ntiles, 1));
+    if (p->layout.ntiles > 0) {
+        hipStream_t cap;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return OILPAINT_ERR_HIP;
+        const BatchArgs a = args_at(p->layout, p->dev);
+        bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        // the counter is cleared by a kernel, not a memset node
+        ok = ok && launch_reset_counter(a.counter, cap) == hipSuccess;
+        ok = ok && launch_batch(a, kBatchWaves, p->layout.lds, p->grid, cap) == hipSuccess;
+        hipGraph_t g = nullptr;
+        const bool ended = hipStreamEndCapture(cap, &g) == hipSuccess;
+        (void)hipStreamDestroy(cap);
+        if (!ok || !ended || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return OILPAINT_ERR_HIP;
+        }
+        p->graph = g;
+        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) return OILPAINT_ERR_HIP;
+    }
+    (void)stream;
+    *out = p.release();
+    return OILPAINT_OK;
+}
+
+int oilpaint_plan_launch(oilpaint_plan* plan, void* stream) {
+    if (!plan) return OILPAINT_ERR_NULL;
+    if (!plan->exec) return OILPAINT_OK;  // nothing to compute
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? OILPAINT_OK : OILPAINT_ERR_HIP;
+}
+
+int oilpaint_plan_info(const oilpaint_plan* plan, int* tiles, int* workgroups) {
+    if (!plan) return OILPAINT_ERR_NULL;
+    if (tiles) *tiles = plan->layout.ntiles;
+    if (workgroups) *workgroups = plan->grid;
+    return OILPAINT_OK;
+}
+
+int oilpaint_plan_destroy(oilpaint_plan* plan) {
+    if (!plan) return OILPAINT_OK;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->dev) (void)hipFree(plan->dev);
+    delete plan;
+    return OILPAINT_OK;
+}
+
+int oilpaint_queue_create(int capacity, int64_t step_pixels, oilpaint_queue** out) {
+    if (!out) return OILPAINT_ERR_NULL;
+    *out = nullptr;
+    if (capacity < 1 || step_pixels < 0) return OILPAINT_ERR_ARG;
+    std::unique_ptr<oilpaint_queue> q(new oilpaint_queue);
+    if (hipGetDevice(&q->device) != hipSuccess) return OILPAINT_ERR_HIP;
+    if (hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking) != hipSuccess) return OILPAINT_ERR_HIP;
+    q->capacity = capacity;
+    q->step_pixels = step_pixels > 0 ? step_pixels : (int64_t)8 << 20;
+    q->ring.reset(new ArgRing(4));
+    *out = q.release();
+    return OILPAINT_OK;
+}
+
+int oilpaint_queue_push(oilpaint_queue* q, const oilpaint_desc* desc, uint64_t* ticket) {
+    if (!q || !desc || !ticket) return OILPAINT_ERR_NULL;
+    retire(q, false);
+    if ((int)q->held >= q->capacity) return OILPAINT_ERR_FULL;
+    Job j;
+    bool empty = false;
+    int st = make_job(*desc, nullptr, q->device, j, empty);
+    if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, q->device);
+    if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.src);
+    if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.dst);
+    if (st != OILPAINT_OK) return st;
+    const uint64_t t = q->next_ticket++;
+    QueueReq r;
+    r.job = j;
+    r.next_row = j.row_begin;
+    r.all_launched = empty;
+    r.done = empty;
+    q->reqs[t] = r;
+    if (!empty) {
+        q->waiting.push_back(t);
+        ++q->held;
+    }
+    *ticket = t;
+    st = queue_progress(q);
+    return st < 0 ? st : OILPAINT_OK;
+}
+
+int oilpaint_queue_step(oilpaint_queue* q) {
+    if (!q) return OILPAINT_ERR_NULL;
+    return queue_progress(q);
+}
+
+int oilpaint_queue_poll(oilpaint_queue* q, uint64_t ticket) {
+    if (!q) return OILPAINT_ERR_NULL;
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return OILPAINT_ERR_ARG;
+    if (!it->second.done) {
+        const int st = queue_progress(q);
+        if (st < 0) return st;
+        if (!it->second.done) return 0;
+    }
+    // reported complete: the ticket is forgotten
+    q->reqs.erase(it);
+    return 1;
+}
+
+int oilpaint_queue_drain(oilpaint_queue* q) {
+    if (!q) return OILPAINT_ERR_NULL;
+    for (;;) {
+        const int st = queue_progress(q);
+        if (st < 0) return st;
+        if (q->inflight.empty() && q->waiting.empty()) return OILPAINT_OK;
+        retire(q, true);
+    }
+}
+
+void* oilpaint_queue_stream(oilpaint_queue* q) { return q ? (void*)q->stream : nullptr; }
+
+int oilpaint_queue_destroy(oilpaint_queue* q) {
+    if (!q) return OILPAINT_OK;
+    (void)hipStreamSynchronize(q->stream);
+    for (auto& f : q->inflight) (void)hipEventDestroy(f.ev);
+    for (auto e : q->free_events) (void)hipEventDestroy(e);
+    q->ring.reset();
+    (void)hipStreamDestroy(q->stream);
+    delete q;
+    return OILPAINT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the kernels and the host side of
+// liboilpaint.so.  Nothing here is part of the public ABI (include/oilpaint.h).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "oilpaint.h"
+
+namespace oilpaint_impl {
+
+// Largest effective radius of the packed layout: a 31 x 31 window holds 961
+// pixels, which fits the 10-bit count field, and 255 * 961 fits 18 bits.
+constexpr int kPackedMaxRadius = 15;
+// Largest effective radius of the wide layout: 255 * 4103^2 < 2^32.
+constexpr int kWideMaxRadius = 2051;
+// Largest window pixel count the packed layout's division table covers.
+constexpr int kPackedMaxCount = 961;
+
+// One image, or a band of its output rows, as the kernels see it.  The
+// launch shape (rows, lanes, hist) is resolved on the host.
+struct Job {
+    const uint8_t* src;
+    uint8_t* dst;
+    int32_t width, height, stride;
+    int32_t radius;     // effective radius (clamped to max(width, height) - 1)
+    int32_t levels;
+    int32_t row_begin, row_end;
+    int32_t paper;      // 1: literal listing semantics (OILPAINT_FLAG_PAPER)
+    int32_t rows;       // output rows per lane
+    int32_t lanes;      // active lanes per wavefront (output columns per tile)
+    int32_t hist;       // OILPAINT_HIST_*
+    int32_t tiles_x;    // tiles across the image
+    int32_t tiles_y;    // tiles down the row band
+    int32_t waves;      // wavefronts per tile that compute (<= the workgroup's)
+    int32_t pad0;
+};
+
+// Work-queue form of a batch: jobs[] in queue order, first_tile[i] the
+// queue index of job i's first tile, first_tile[njobs] the total.
+struct BatchArgs {
+    const Job* jobs;
+    const int32_t* first_tile;
+    int32_t njobs;
+    int32_t ntiles;
+    uint32_t* counter;   // tile counter, reset to 0 before every launch
+};
+
+// On-chip bytes one workgroup needs for job `j` (its `waves` computing
+// wavefronts).
+size_t lds_bytes(const Job& j);
+
+// Number of histogram bins a job keeps per lane (levels, plus the extra
+// white level of the paper form, plus one bin that absorbs pixels outside
+// the image).
+inline int hist_bins(const Job& j) { return j.levels + (j.paper ? 1 : 0) + 1; }
+
+// Kernel launches (oilpaint_kernels.hip).  Each returns a hipError_t.
+hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream);
+hipError_t launch_batch(const BatchArgs& a, int waves, size_t lds, int grid, hipStream_t stream);
+hipError_t launch_reset_counter(uint32_t* counter, hipStream_t stream);
+
+// Record a failed HIP call (text readable through oilpaint_last_error) and
+// clear the runtime's sticky last-error state.  Returns `e`.
+hipError_t note_hip(const char* where, hipError_t e);
+
+// Device facts, cached per device.
+struct DeviceInfo {
+    int cus;
+    size_t lds_per_block;
+    int ok;
+};
+DeviceInfo device_info(int device);
+
+// Most workgroups of the persistent kernel that can be resident at once.
+int batch_grid(int device, int waves, size_t lds);
+
+}  // namespace oilpaint_impl

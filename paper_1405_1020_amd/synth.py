@@ -63,6 +63,51 @@ def make_image(width: int, height: int, seed: int, n_blobs: int = 40,
     return out
 
 
+def make_image_device(width: int, height: int, seed: int, n_blobs: int = 40,
+                      sigma: tuple[float, float] = (30.0, 200.0), noise: int = 8,
+                      salt_pepper: float = 0.0, device: str = "cuda"):
+    """The same recipe as make_image, drawn and rendered on the GPU with
+    torch (for the large batch and serving workloads).  Blob parameters come
+    from numpy's generator with `seed`; the noise and the salt-and-pepper
+    positions from a torch generator seeded with `seed` on `device`.  The
+    bytes are deterministic for a given device and software stack but are not
+    the bytes make_image returns.  Returns a uint8 [H, W, 3] CUDA tensor."""
+    import torch
+    rng = np.random.default_rng(seed)
+    acc = torch.zeros((height, width, 3), dtype=torch.float32, device=device)
+    for _ in range(n_blobs):
+        cx = rng.uniform(0, width)
+        cy = rng.uniform(0, height)
+        s = rng.uniform(sigma[0], sigma[1])
+        amp = torch.tensor(rng.uniform(0, 255, size=3), dtype=torch.float32, device=device)
+        x0 = max(0, int(math.floor(cx - 4 * s)))
+        x1 = min(width, int(math.ceil(cx + 4 * s)) + 1)
+        y0 = max(0, int(math.floor(cy - 4 * s)))
+        y1 = min(height, int(math.ceil(cy + 4 * s)) + 1)
+        if x0 >= x1 or y0 >= y1:
+            continue
+        gx = torch.exp(-((torch.arange(x0, x1, device=device, dtype=torch.float32) - cx) ** 2) / (2 * s * s))
+        gy = torch.exp(-((torch.arange(y0, y1, device=device, dtype=torch.float32) - cy) ** 2) / (2 * s * s))
+        acc[y0:y1, x0:x1, :] += gy[:, None, None] * gx[None, :, None] * amp[None, None, :]
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    img = torch.round(acc).to(torch.int16)
+    del acc
+    if noise > 0:
+        img += torch.randint(-noise, noise + 1, img.shape, generator=g, device=device, dtype=torch.int16)
+    out = img.clamp_(0, 255).to(torch.uint8)
+    del img
+    if salt_pepper > 0:
+        npx = width * height
+        m = int(round(salt_pepper * npx))
+        idx = torch.randperm(npx, generator=g, device=device)[:m]
+        flat = out.view(-1, 3)
+        half = m // 2
+        flat[idx[:half]] = 0
+        flat[idx[half:]] = 255
+    return out
+
+
 def make_random(width: int, height: int, seed: int) -> np.ndarray:
     """Uniform random bytes: the worst case for level agreement."""
     rng = np.random.default_rng(seed)
@@ -128,9 +173,14 @@ def batch_items(n: int = 64, seed: int = 4) -> list[BatchItem]:
     return items
 
 
-def batch_image(item: BatchItem) -> np.ndarray:
+def batch_image(item: BatchItem, device: str | None = "cuda"):
+    """The item's image: images below 0.5 MP use the small-image blob
+    parameters, the rest the large-image ones.  Rendered on `device` (a CUDA
+    tensor) or, with device=None, by make_image (a numpy array)."""
     blobs = SMALL_BLOBS if item.width * item.height < 500_000 else LARGE_BLOBS
-    return make_image(item.width, item.height, seed=item.seed, **blobs)
+    if device is None:
+        return make_image(item.width, item.height, seed=item.seed, **blobs)
+    return make_image_device(item.width, item.height, seed=item.seed, device=device, **blobs)
 
 
 @dataclass
@@ -149,9 +199,11 @@ class Request:
 @dataclass
 class ServeWorkload:
     requests: list[Request]
-    canvases: list[np.ndarray] = field(default_factory=list)
+    canvases: list = field(default_factory=list)   # uint8 [H, W, 3] CUDA tensors
 
-    def image(self, req: Request) -> np.ndarray:
+    def image(self, req: Request):
+        """The request's image: a strided view into its canvas (row stride =
+        the canvas's)."""
         c = self.canvases[req.canvas]
         return c[req.y0:req.y0 + req.height, req.x0:req.x0 + req.width, :]
 
@@ -185,5 +237,5 @@ def serve_workload(n: int = 2000, rate: float = 200.0, seed: int = 5,
         reqs.append(Request(i, t, w, h, r, lv, c, x0, y0))
     wl = ServeWorkload(reqs)
     if with_canvases:
-        wl.canvases = [make_image(cw, ch, seed=seed * 100 + k, **LARGE_BLOBS) for k in range(n_canvas)]
+        wl.canvases = [make_image_device(cw, ch, seed=seed * 100 + k, **LARGE_BLOBS) for k in range(n_canvas)]
     return wl

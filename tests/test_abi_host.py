@@ -1,0 +1,92 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every function include/oilpaint.h declares, and its pure-host argument
+validation returns the documented status codes."""
+import ctypes
+
+import pytest
+
+from paper_1405_1020_amd import binding as B
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = B.lib()
+    names = B.header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding knows every one of them, with the same names
+    assert set(names) == set(B._SIGS)
+
+
+def test_version_and_strerror():
+    assert B.version() == 1
+    for st in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert B.strerror(st) and B.strerror(st) != "unknown status"
+    assert B.strerror(-99) == "unknown status"
+
+
+BASE = 1 << 32  # fake, never dereferenced: validation is pure host
+
+
+def v(src=BASE, dst=BASE + (1 << 30), w=64, h=48, s=192, r=2, L=20):
+    return B.validate(src, dst, w, h, s, r, L)
+
+
+def test_validate_ok_and_noop_sizes():
+    assert v() == B.OK
+    assert v(w=0) == B.OK
+    assert v(h=0) == B.OK
+    assert v(w=0, h=0, s=0) == B.OK
+    assert v(r=0) == B.OK and v(r=65535) == B.OK
+    assert v(L=1) == B.OK and v(L=256) == B.OK
+    assert v(s=193) == B.OK
+
+
+def test_validate_null():
+    assert v(src=0) == B.ERR_NULL
+    assert v(dst=0) == B.ERR_NULL
+    assert v(src=0, w=0) == B.ERR_NULL
+
+
+@pytest.mark.parametrize("kw", [dict(w=-1), dict(h=-1), dict(r=-1), dict(r=65536), dict(L=0),
+                                dict(L=257), dict(s=191), dict(s=-3), dict(w=1 << 30, s=1 << 30)])
+def test_validate_bad_args(kw):
+    assert v(**kw) == B.ERR_ARG
+
+
+def test_validate_overlap():
+    span = 47 * 192 + 192
+    assert v(src=BASE, dst=BASE) == B.ERR_OVERLAP
+    assert v(src=BASE, dst=BASE + span - 1) == B.ERR_OVERLAP
+    assert v(src=BASE + span - 1, dst=BASE) == B.ERR_OVERLAP
+    assert v(src=BASE, dst=BASE + span) == B.OK
+    # the padding of the last row is not part of the range
+    assert v(src=BASE, dst=BASE + 47 * 200 + 192, s=200) == B.OK
+
+
+def test_pick_variant_shapes():
+    # the choice is pure host logic once the device facts are cached; without
+    # a GPU it falls back to nominal facts
+    vv = B.pick_variant(1920, 1080, 5, 20)
+    assert vv.hist == B.HIST_PACKED and vv.lanes in (16, 32, 64) and 1 <= vv.waves <= 16 and vv.rows >= 1
+    assert B.pick_variant(1920, 1080, 16, 20).hist == B.HIST_WIDE
+    assert B.pick_variant(1920, 1080, 5, 256).hist == B.HIST_WIDE
+    # a radius beyond the image behaves as the image size
+    assert B.pick_variant(12, 10, 1000, 20).hist == B.HIST_PACKED
+    assert B.pick_variant(20, 10, 1000, 20).hist == B.HIST_WIDE
+
+
+def test_kernel_integer_identities():
+    # facts the kernels' integer arithmetic relies on, checked exhaustively
+    # over their whole domains (no GPU, no oracle involved)
+    assert all(((s * 43691) >> 17) == s // 3 for s in range(766))
+    assert all(((x * 5614337) >> 32) == x // 765 for x in range(765 * 256 + 1))
+    for n in range(2, 962):
+        m = -(-(1 << 32) // n)
+        for s in range(0, 255 * n + 1, max(1, n // 7)):
+            assert ((s * m) >> 32) == s // n
+        s = 255 * n
+        assert ((s * m) >> 32) == s // n and (((s - 1) * m) >> 32) == (s - 1) // n
+    for L in range(1, 257):
+        for s in range(766):
+            assert int(((s * L) / 3.0) / 255.0) == (s * L) // 765

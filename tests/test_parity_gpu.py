@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path, called through the C-ABI, against the CPU oracle.
+
+The bar is bit-exact equality (all arithmetic is integer).  Sizes span
+several tiles with ragged tails; the benchmark images (256x256 r=2 L=20,
+1920x1080 over the r/L sweep, 4000x3000 r=10 L=32) are compared in full.
+"""
+import numpy as np
+import pytest
+
+from paper_1405_1020_amd import binding as B
+from paper_1405_1020_amd import synth
+from gpu_util import (to_device, empty_like_device, from_device, padding_bytes, ref, ref_pixel,
+                      first_mismatch, torch_mod)
+
+pytestmark = pytest.mark.gpu
+
+
+def run_plain(img, r, L, pad=0, variant=None):
+    torch = torch_mod()
+    h, w, _ = img.shape
+    src, sbuf = to_device(img, pad=pad, seed=3)
+    dst, dbuf = empty_like_device(img, pad=pad, seed=5)
+    before = padding_bytes(dbuf, h, w, 3 * w + pad)
+    B.oilpaint_async(src, dst, r, L, variant=variant)
+    torch.cuda.synchronize()
+    after = padding_bytes(dbuf, h, w, 3 * w + pad)
+    assert np.array_equal(before, after), "dst padding was written"
+    return from_device(dst)
+
+
+def check(img, r, L, **kw):
+    got = run_plain(img, r, L, **kw)
+    want = ref(img, r, L)
+    mm = first_mismatch(got, want)
+    assert mm is None, ("mismatch (y, x, got, want, count)", mm, img.shape, r, L, kw)
+
+
+def test_small_case_exact():
+    img, r, L = synth.small_case()
+    print("small case 256x256", r, L, flush=True)
+    check(img, r, L)
+
+
+@pytest.mark.parametrize("r,L", synth.FHD_SWEEP)
+def test_fhd_sweep_exact(r, L):
+    print("fhd", r, L, flush=True)
+    check(synth.fhd_image(), r, L)
+
+
+def test_camera_exact():
+    img = synth.camera_image()
+    r, L = synth.CAMERA_RL
+    print("camera 4000x3000", r, L, flush=True)
+    check(img, r, L)
+
+
+RAGGED = [(1, 1), (1, 7), (7, 1), (2, 3), (63, 5), (64, 64), (65, 17), (129, 70), (200, 33), (31, 300)]
+
+
+@pytest.mark.parametrize("w,h", RAGGED)
+def test_ragged_sizes(w, h):
+    rng = np.random.default_rng(w * 1000 + h)
+    img = synth.make_image(w, h, seed=w + h, n_blobs=4, sigma=(2, 20)) if w * h > 100 else \
+        synth.make_random(w, h, seed=w + h)
+    for r in (0, 1, 2, 5, 15):
+        L = int(rng.choice([1, 2, 8, 20, 32, 64, 255]))
+        print("ragged", w, h, r, L, flush=True)
+        check(img, r, L, pad=int(rng.integers(0, 9)))
+
+
+@pytest.mark.parametrize("r,L", [(16, 20), (20, 8), (40, 32), (3, 256), (1, 256), (60, 64)])
+def test_wide_layout(r, L):
+    img = synth.make_image(150, 97, seed=r + L, n_blobs=5, sigma=(5, 30))
+    print("wide", r, L, flush=True)
+    check(img, r, L, pad=5)
+
+
+def test_radius_larger_than_image():
+    img = synth.make_random(9, 6, seed=2)
+    for r in (8, 9, 100, 5000, 65535):
+        check(img, r, 20)
+
+
+def test_every_variant_same_bytes():
+    img = synth.make_image(333, 211, seed=77, n_blobs=8, sigma=(4, 40))
+    for r, L in [(2, 20), (7, 64), (15, 8)]:
+        want = ref(img, r, L)
+        for rows in (1, 3, 8, 16, 64):
+            for waves in (1, 2, 4, 8):
+                for lanes in (16, 32, 64):
+                    for hist in (B.HIST_PACKED, B.HIST_WIDE):
+                        v = B.Variant(rows, waves, hist, lanes)
+                        try:
+                            got = run_plain(img, r, L, pad=3, variant=v)
+                        except B.OilpaintError as e:
+                            assert e.status == B.ERR_UNSUPPORTED, (v, e)
+                            continue
+                        mm = first_mismatch(got, want)
+                        assert mm is None, (r, L, v, mm)
+
+
+def test_repeat_is_deterministic():
+    img = synth.fhd_image()
+    a = run_plain(img, 10, 20)
+    b = run_plain(img, 10, 20)
+    assert np.array_equal(a, b)
+
+
+def test_errors_leave_dst_untouched():
+    torch = torch_mod()
+    img = synth.make_random(40, 30, seed=9)
+    src, _ = to_device(img)
+    dst, dbuf = empty_like_device(img)
+    before = dbuf.cpu().numpy().copy()
+    with pytest.raises(B.OilpaintError) as e:
+        B.oilpaint_async(src, dst, -1, 20)
+    assert e.value.status == B.ERR_ARG
+    with pytest.raises(B.OilpaintError) as e:
+        B.oilpaint_async(src, dst, 2, 0)
+    assert e.value.status == B.ERR_ARG
+    # src and dst overlapping: the same buffer
+    with pytest.raises(B.OilpaintError) as e:
+        B.oilpaint_async(src, src, 2, 20)
+    assert e.value.status == B.ERR_OVERLAP
+    # host memory is rejected
+    lib = B.lib()
+    host = np.zeros(40 * 30 * 3, np.uint8)
+    import ctypes
+    st = lib.oilpaint_async(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(host.ctypes.data), 40, 30, 120, 2,
+                            20, None)
+    assert st == B.ERR_NOT_DEVICE
+    torch.cuda.synchronize()
+    assert np.array_equal(before, dbuf.cpu().numpy())
+
+
+def test_sync_entry_point():
+    torch = torch_mod()
+    import ctypes
+    img = synth.make_image(300, 200, seed=4, n_blobs=5, sigma=(5, 40))
+    src, _ = to_device(img)
+    dst, _ = empty_like_device(img)
+    st = B.lib().oilpaint(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), 300, 200, 900, 3, 16)
+    assert st == B.OK
+    assert first_mismatch(from_device(dst), ref(img, 3, 16)) is None
+    torch.cuda.synchronize()
+
+
+def test_empty_images_noop():
+    torch = torch_mod()
+    import ctypes
+    for (w, h) in [(0, 5), (5, 0)]:
+        src = torch.zeros((h, w, 3), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros((h, w, 3), dtype=torch.uint8, device="cuda")
+        B.oilpaint_async(src, dst, 2, 20)
+    # through the C-ABI with real pointers and a zero size
+    a = torch.full((64,), 9, dtype=torch.uint8, device="cuda")
+    b = torch.full((64,), 9, dtype=torch.uint8, device="cuda")
+    for (w, h) in [(0, 5), (5, 0), (0, 0)]:
+        st = B.lib().oilpaint_async(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), w, h, 15, 2, 20,
+                                    None)
+        assert st == B.OK
+    torch.cuda.synchronize()
+    assert int(b.eq(9).all()) == 1
+
+
+def test_sampled_pixels_full_size_camera():
+    # the camera image in the launch configuration the benchmark uses, with
+    # oracle values computed pixel by pixel at sampled positions (borders,
+    # corners and random interior points)
+    img = synth.camera_image()
+    r, L = synth.CAMERA_RL
+    got = run_plain(img, r, L)
+    h, w, _ = img.shape
+    rng = np.random.default_rng(0)
+    pts = [(0, 0), (w - 1, 0), (0, h - 1), (w - 1, h - 1), (r, r), (w // 2, h // 2)]
+    pts += [(int(x), int(y)) for x, y in zip(rng.integers(0, w, 200), rng.integers(0, h, 200))]
+    for x, y in pts:
+        assert tuple(got[y, x]) == tuple(ref_pixel(img, x, y, r, L)), (x, y)
