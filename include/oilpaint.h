@@ -23,10 +23,12 @@
  *
  * Conventions shared by every entry point:
  *   - Images are `height` rows of `width` pixels; a pixel is 3 bytes
- *     (c0, c1, c2), and row y starts at byte y * stride.  One `stride`
- *     (bytes, >= 3 * width) serves src and dst.  Bytes [3*width, stride) of
- *     a row are neither read nor written.  Channel order does not matter:
- *     the filter commutes with any permutation of the three channels.
+ *     (c0, c1, c2), and row y starts at byte y * stride.  In the
+ *     single-image calls one `stride` (bytes, >= 3 * width) serves src and
+ *     dst; descriptors (oilpaint_desc) may give dst its own stride.  Bytes
+ *     [3*width, stride) of a row are neither read nor written.  Channel order
+ *     does not matter: the filter commutes with any permutation of the three
+ *     channels.
  *   - src and dst are device pointers (hipMalloc'd, or any memory the
  *     current device can access) owned by the caller; the library keeps no
  *     reference to them after the work completes.  src and dst must not
@@ -153,11 +155,22 @@ int oilpaint_async_variant(const uint8_t *src, uint8_t *dst, int width, int heig
 typedef struct oilpaint_desc {
     const uint8_t *src;    /* device pointer, image as above */
     uint8_t *dst;          /* device pointer, disjoint from src */
-    int32_t width, height, stride, radius, levels;
+    int32_t width, height;
+    int32_t stride;        /* row stride of src in bytes (>= 3 * width) */
+    int32_t dst_stride;    /* row stride of dst in bytes; 0 means `stride` */
+    int32_t radius, levels;
     int32_t row_begin;     /* compute output rows [row_begin, row_end) only; */
     int32_t row_end;       /* row_begin = row_end = 0 selects every row      */
     uint32_t flags;        /* OILPAINT_FLAG_* */
+    uint32_t reserved;     /* must be 0 */
 } oilpaint_desc;
+
+/* Filter one descriptor asynchronously on `stream` with the plain kernel
+ * (one workgroup per tile, the library's launch shape).  Unlike
+ * oilpaint_async it takes separate src and dst strides -- for example a
+ * crop of a larger resident image written to a dense output -- a row band
+ * and flags.  Validation as oilpaint_batch for one item. */
+int oilpaint_run(const oilpaint_desc *desc, void *stream);
 
 /* Validate all n descriptors (all or nothing: on error *bad_index, if not
  * NULL, receives the first failing index and nothing is enqueued), then

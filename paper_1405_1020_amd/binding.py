@@ -53,10 +53,11 @@ class Variant(ctypes.Structure):
 
 class Desc(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
-                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("stride", ctypes.c_int32), ("dst_stride", ctypes.c_int32),
                 ("radius", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("row_begin", ctypes.c_int32), ("row_end", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -73,6 +74,7 @@ _SIGS = {
     "oilpaint_clear_variants": ([], ctypes.c_int),
     "oilpaint_async_variant": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5
                                + [ctypes.POINTER(Variant), ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_run": ([ctypes.POINTER(Desc), ctypes.c_void_p], ctypes.c_int),
     "oilpaint_batch": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
                        ctypes.c_int),
     "oilpaint_plan_create": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p,
@@ -231,13 +233,25 @@ class Item:
 
 
 def make_desc(it: Item) -> Desc:
+    """Descriptor of an Item; src and dst may have different row strides."""
     _require_cuda(it.src, it.dst)
     w, h, s = image_geometry(it.src)
     w2, h2, s2 = image_geometry(it.dst)
-    if (w, h) != (w2, h2) or (h > 1 and s != s2):
-        raise ValueError("src and dst must have the same width, height and row stride")
-    return Desc(it.src.data_ptr(), it.dst.data_ptr(), w, h, s, it.radius, it.levels,
-                it.row_begin, it.row_end, it.flags)
+    if (w, h) != (w2, h2):
+        raise ValueError("src and dst must have the same width and height")
+    return Desc(it.src.data_ptr(), it.dst.data_ptr(), w, h, s, s2, it.radius, it.levels,
+                it.row_begin, it.row_end, it.flags, 0)
+
+
+def run(item, stream=None) -> None:
+    """oilpaint_run: the plain kernel on one descriptor (own dst stride, row
+    band and flags)."""
+    if isinstance(item, Item):
+        w, h, _ = image_geometry(item.src)
+        if w == 0 or h == 0:
+            return
+    d = item if isinstance(item, Desc) else make_desc(item)
+    _check(lib().oilpaint_run(ctypes.byref(d), _stream_ptr(stream)), "oilpaint_run")
 
 
 def _desc_array(items):

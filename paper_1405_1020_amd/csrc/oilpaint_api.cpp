@@ -64,9 +64,9 @@ int effective_radius(int width, int height, int radius) {
     return std::min(radius, std::max(span, 0));
 }
 
-bool ranges_overlap(const uint8_t* a, const uint8_t* b, size_t len) {
+bool ranges_overlap(const uint8_t* a, size_t alen, const uint8_t* b, size_t blen) {
     const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
-    return pa < pb + len && pb < pa + len;
+    return pa < pb + blen && pb < pa + alen;
 }
 
 std::mutex g_tune_mu;
@@ -77,6 +77,22 @@ bool packed_ok(int reff, int levels, bool paper) {
 }
 
 }  // namespace
+
+// The checks of oilpaint_validate with separate src and dst strides.
+int validate2(const uint8_t* src, int sstride, const uint8_t* dst, int dstride, int width, int height, int radius,
+              int levels) {
+    if (!src || !dst) return OILPAINT_ERR_NULL;
+    if (width < 0 || height < 0 || radius < 0 || radius > 65535) return OILPAINT_ERR_ARG;
+    if (levels < 1 || levels > 256) return OILPAINT_ERR_ARG;
+    if (width > INT_MAX / 3) return OILPAINT_ERR_ARG;
+    if (sstride < 3 * width || dstride < 3 * width) return OILPAINT_ERR_ARG;
+    if (width == 0 || height == 0) return OILPAINT_OK;
+    const size_t sspan = (size_t)(height - 1) * (size_t)sstride + 3 * (size_t)width;
+    const size_t dspan = (size_t)(height - 1) * (size_t)dstride + 3 * (size_t)width;
+    if ((uintptr_t)src + sspan < (uintptr_t)src || (uintptr_t)dst + dspan < (uintptr_t)dst) return OILPAINT_ERR_ARG;
+    if (ranges_overlap(src, sspan, dst, dspan)) return OILPAINT_ERR_OVERLAP;
+    return OILPAINT_OK;
+}
 
 // Fill the launch-shape fields of `j` from `v`.  Returns OK or UNSUPPORTED.
 int apply_variant(Job& j, const oilpaint_variant& v, int device) {
@@ -162,9 +178,10 @@ oilpaint_variant choose_variant(int width, int height, int reff, int levels, boo
 // Validate a descriptor and build its Job (shape from `v`, or the library's
 // choice when v is NULL).  Pure host work apart from device facts.
 int make_job(const oilpaint_desc& d, const oilpaint_variant* v, int device, Job& j, bool& empty) {
-    const int st = oilpaint_validate(d.src, d.dst, d.width, d.height, d.stride, d.radius, d.levels);
+    const int dst_stride = d.dst_stride ? d.dst_stride : d.stride;
+    const int st = validate2(d.src, d.stride, d.dst, dst_stride, d.width, d.height, d.radius, d.levels);
     if (st != OILPAINT_OK) return st;
-    if (d.flags & ~OILPAINT_FLAG_PAPER) return OILPAINT_ERR_ARG;
+    if ((d.flags & ~OILPAINT_FLAG_PAPER) || d.reserved != 0) return OILPAINT_ERR_ARG;
     int rb = d.row_begin, re = d.row_end;
     if (rb == 0 && re == 0) re = d.height;
     if (rb < 0 || re < rb || re > d.height) return OILPAINT_ERR_ARG;
@@ -175,6 +192,7 @@ int make_job(const oilpaint_desc& d, const oilpaint_variant* v, int device, Job&
     j.width = d.width;
     j.height = d.height;
     j.stride = d.stride;
+    j.dst_stride = dst_stride;
     j.radius = effective_radius(d.width, d.height, d.radius);
     j.levels = d.levels;
     j.row_begin = rb;
@@ -226,22 +244,25 @@ const char* oilpaint_strerror(int status) {
 
 int oilpaint_validate(const uint8_t* src, const uint8_t* dst, int width, int height, int stride, int radius,
                       int levels) {
-    if (!src || !dst) return OILPAINT_ERR_NULL;
-    if (width < 0 || height < 0 || radius < 0 || radius > 65535) return OILPAINT_ERR_ARG;
-    if (levels < 1 || levels > 256) return OILPAINT_ERR_ARG;
-    if (width > INT_MAX / 3) return OILPAINT_ERR_ARG;
-    if (stride < 3 * width) return OILPAINT_ERR_ARG;
-    if (width == 0 || height == 0) return OILPAINT_OK;
-    const size_t span = (size_t)(height - 1) * (size_t)stride + 3 * (size_t)width;
-    if ((uintptr_t)src + span < (uintptr_t)src || (uintptr_t)dst + span < (uintptr_t)dst) return OILPAINT_ERR_ARG;
-    if (ranges_overlap(src, dst, span)) return OILPAINT_ERR_OVERLAP;
+    return validate2(src, stride, dst, stride, width, height, radius, levels);
+}
+
+static int launch_desc(const oilpaint_desc& d, const oilpaint_variant* v, hipStream_t stream) {
+    int device = 0;
+    if (note_hip("hipGetDevice", hipGetDevice(&device)) != hipSuccess) return OILPAINT_ERR_HIP;
+    Job j;
+    bool empty = false;
+    int st = make_job(d, v, device, j, empty);
+    if (st != OILPAINT_OK || empty) return st;
+    if ((st = check_device_ptr(d.src)) != OILPAINT_OK) return st;
+    if ((st = check_device_ptr(d.dst)) != OILPAINT_OK) return st;
+    const size_t lds = lds_bytes(j);
+    if (launch_plain(j, j.waves, lds, stream) != hipSuccess) return OILPAINT_ERR_HIP;
     return OILPAINT_OK;
 }
 
 static int launch_one(const uint8_t* src, uint8_t* dst, int width, int height, int stride, int radius, int levels,
                       const oilpaint_variant* v, hipStream_t stream) {
-    int device = 0;
-    if (hipGetDevice(&device) != hipSuccess) return OILPAINT_ERR_HIP;
     oilpaint_desc d{};
     d.src = src;
     d.dst = dst;
@@ -250,15 +271,12 @@ static int launch_one(const uint8_t* src, uint8_t* dst, int width, int height, i
     d.stride = stride;
     d.radius = radius;
     d.levels = levels;
-    Job j;
-    bool empty = false;
-    int st = make_job(d, v, device, j, empty);
-    if (st != OILPAINT_OK || empty) return st;
-    if ((st = check_device_ptr(src)) != OILPAINT_OK) return st;
-    if ((st = check_device_ptr(dst)) != OILPAINT_OK) return st;
-    const size_t lds = lds_bytes(j);
-    if (launch_plain(j, j.waves, lds, stream) != hipSuccess) return OILPAINT_ERR_HIP;
-    return OILPAINT_OK;
+    return launch_desc(d, v, stream);
+}
+
+int oilpaint_run(const oilpaint_desc* desc, void* stream) {
+    if (!desc) return OILPAINT_ERR_NULL;
+    return launch_desc(*desc, nullptr, (hipStream_t)stream);
 }
 
 int oilpaint_async(const uint8_t* src, uint8_t* dst, int width, int height, int stride, int radius, int levels,

@@ -24,7 +24,9 @@ constexpr int kPackedMaxCount = 961;
 struct Job {
     const uint8_t* src;
     uint8_t* dst;
-    int32_t width, height, stride;
+    int32_t width, height;
+    int32_t stride;     // src row stride, bytes
+    int32_t dst_stride; // dst row stride, bytes
     int32_t radius;     // effective radius (clamped to max(width, height) - 1)
     int32_t levels;
     int32_t row_begin, row_end;
@@ -35,7 +37,6 @@ struct Job {
     int32_t tiles_x;    // tiles across the image
     int32_t tiles_y;    // tiles down the row band
     int32_t waves;      // wavefronts per tile that compute (<= the workgroup's)
-    int32_t pad0;
 };
 
 // Work-queue form of a batch: jobs[] in queue order, first_tile[i] the

@@ -182,7 +182,7 @@ __device__ void tile_packed(const Job& j, int tile, uint8_t* lds) {
             bool store = x < j.width;
             if (paper) store = store && n > 0 && x >= r && x < j.width - r && y >= r && y < j.height - r;
             if (store) {
-                uint8_t* o = j.dst + (size_t)y * (size_t)j.stride + 3 * x;
+                uint8_t* o = j.dst + (size_t)y * (size_t)j.dst_stride + 3 * x;
                 o[0] = (uint8_t)div_packed(s0, n);
                 o[1] = (uint8_t)div_packed(s1, n);
                 o[2] = (uint8_t)div_packed(s2, n);
@@ -274,7 +274,7 @@ __device__ void tile_wide(const Job& j, int tile, uint8_t* lds) {
             // s < 2^32 and n < 2^25, so s/n is at least 1/n away from the
             // next integer, far more than the rounding error.
             const double dn = (double)n;
-            uint8_t* o = j.dst + (size_t)y * (size_t)j.stride + 3 * x;
+            uint8_t* o = j.dst + (size_t)y * (size_t)j.dst_stride + 3 * x;
             o[0] = (uint8_t)(uint32_t)((double)(uint32_t)(a >> 32) / dn);
             o[1] = (uint8_t)(uint32_t)((double)(uint32_t)b / dn);
             o[2] = (uint8_t)(uint32_t)((double)(uint32_t)(b >> 32) / dn);
