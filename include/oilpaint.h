@@ -126,7 +126,7 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
 
 typedef struct oilpaint_variant {
     int32_t rows;   /* output rows per lane, >= 1 */
-    int32_t waves;  /* wavefronts per workgroup, 1..16 */
+    int32_t waves;  /* wavefronts per workgroup, 1..8 */
     int32_t hist;   /* OILPAINT_HIST_* */
     int32_t lanes;  /* active lanes (= output columns) per wavefront: 64, 32 or 16 */
 } oilpaint_variant;

@@ -45,7 +45,7 @@ DeviceInfo device_info(int device) {
 
 size_t lds_bytes(const Job& j) {
     const int waves = j.waves;
-    const size_t nb = (size_t)hist_bins(j);
+    const size_t nb = (size_t)j.bins;
     const size_t lanes = (size_t)j.lanes;
     if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
     const size_t tw = lanes + 2 * (size_t)j.radius;
@@ -96,7 +96,7 @@ int validate2(const uint8_t* src, int sstride, const uint8_t* dst, int dstride, 
 
 // Fill the launch-shape fields of `j` from `v`.  Returns OK or UNSUPPORTED.
 int apply_variant(Job& j, const oilpaint_variant& v, int device) {
-    if (v.rows < 1 || v.rows > 4096 || v.waves < 1 || v.waves > 16) return OILPAINT_ERR_UNSUPPORTED;
+    if (v.rows < 1 || v.rows > 4096 || v.waves < 1 || v.waves > 8) return OILPAINT_ERR_UNSUPPORTED;
     if (v.lanes != 64 && v.lanes != 32 && v.lanes != 16) return OILPAINT_ERR_UNSUPPORTED;
     if (v.hist == OILPAINT_HIST_PACKED) {
         if (!packed_ok(j.radius, j.levels, j.paper != 0)) return OILPAINT_ERR_UNSUPPORTED;
@@ -109,6 +109,7 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     j.lanes = v.lanes;
     j.hist = v.hist;
     j.waves = v.waves;
+    set_layout(j);
     const DeviceInfo d = device_info(device);
     const size_t limit = d.ok ? d.lds_per_block : 65536;
     if (lds_bytes(j) + kStaticLds > limit) return OILPAINT_ERR_UNSUPPORTED;
@@ -153,6 +154,7 @@ oilpaint_variant default_variant(int width, int height, int reff, int levels, bo
         j.lanes = v.lanes;
         j.hist = v.hist;
         j.waves = v.waves;
+        set_layout(j);
         if (lds_bytes(j) <= limit) break;
         if (v.waves > 1)
             v.waves >>= 1;

@@ -37,6 +37,13 @@ struct Job {
     int32_t tiles_x;    // tiles across the image
     int32_t tiles_y;    // tiles down the row band
     int32_t waves;      // wavefronts per tile that compute (<= the workgroup's)
+    // histogram layout, decided on the host (set_layout)
+    int32_t fast;       // 1: compile-time-radius path (PACKED, 64 lanes, scan <= 64)
+    int32_t scan;       // bins the mode search scans (levels, or levels rounded up to 8)
+    int32_t white;      // bin of the paper form's extra pure-white level
+    int32_t trash;      // bin of pixels outside the image
+    int32_t bins;       // bins per lane
+    int32_t pad0;
 };
 
 // Work-queue form of a batch: jobs[] in queue order, first_tile[i] the
@@ -53,10 +60,17 @@ struct BatchArgs {
 // wavefronts).
 size_t lds_bytes(const Job& j);
 
-// Number of histogram bins a job keeps per lane (levels, plus the extra
-// white level of the paper form, plus one bin that absorbs pixels outside
-// the image).
-inline int hist_bins(const Job& j) { return j.levels + (j.paper ? 1 : 0) + 1; }
+// Fill the histogram-layout fields of `j` from its shape (hist, lanes,
+// radius, levels, paper): the levels 0..L-1 first -- rounded up to a multiple
+// of 8 empty bins on the fast path -- then the paper form's white level,
+// then the bin for pixels outside the image.
+inline void set_layout(Job& j) {
+    j.fast = (j.hist == OILPAINT_HIST_PACKED && j.lanes == 64 && j.radius <= kPackedMaxRadius && j.levels <= 64) ? 1 : 0;
+    j.scan = j.fast ? (j.levels + 7) / 8 * 8 : j.levels;
+    j.white = j.scan;
+    j.trash = j.scan + (j.paper ? 1 : 0);
+    j.bins = j.trash + 1;
+}
 
 // Kernel launches (oilpaint_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream);
