@@ -118,10 +118,15 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *                         18-bit channel sums), the tile and its halo staged
  *                         on chip; windows up to 31 x 31 (radius <= 15) and
  *                         levels <= 255 (<= 254 with OILPAINT_FLAG_PAPER)
+ *   OILPAINT_HIST_STREAM  the PACKED bins with only the 2r+2 image rows the
+ *                         windows span kept on chip, fetched as the run
+ *                         advances; one wavefront of 64 lanes per workgroup
+ *                         (waves = 1, lanes = 64), radius <= 15, levels <= 64
  *   OILPAINT_HIST_WIDE    32-bit count and sums, pixels read from device
  *                         memory; any level count and radius up to 2051
  * ------------------------------------------------------------------------- */
 #define OILPAINT_HIST_PACKED 0
+#define OILPAINT_HIST_STREAM 1
 #define OILPAINT_HIST_WIDE   2
 
 typedef struct oilpaint_variant {

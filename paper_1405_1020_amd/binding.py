@@ -27,6 +27,7 @@ ERR_FULL = -7
 ERR_UNSUPPORTED = -8
 
 HIST_PACKED = 0
+HIST_STREAM = 1
 HIST_WIDE = 2
 FLAG_PAPER = 1
 

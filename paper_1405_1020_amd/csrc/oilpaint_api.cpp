@@ -48,6 +48,10 @@ size_t lds_bytes(const Job& j) {
     const size_t nb = (size_t)j.bins;
     const size_t lanes = (size_t)j.lanes;
     if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
+    if (j.hist == OILPAINT_HIST_STREAM) {
+        const size_t tw = 64 + 2 * (size_t)j.radius;
+        return nb * 64 * 8 + (2 * (size_t)j.radius + 4) * tw * 4 + 192;
+    }
     const size_t tw = lanes + 2 * (size_t)j.radius;
     const size_t th = (size_t)waves * (size_t)j.rows + 2 * (size_t)j.radius;
     const size_t tile = (tw * th * 4 + 15) & ~(size_t)15;
@@ -100,6 +104,9 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     if (v.lanes != 64 && v.lanes != 32 && v.lanes != 16) return OILPAINT_ERR_UNSUPPORTED;
     if (v.hist == OILPAINT_HIST_PACKED) {
         if (!packed_ok(j.radius, j.levels, j.paper != 0)) return OILPAINT_ERR_UNSUPPORTED;
+    } else if (v.hist == OILPAINT_HIST_STREAM) {
+        if (j.radius > kPackedMaxRadius || j.levels > 64 || v.waves != 1 || v.lanes != 64)
+            return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_WIDE) {
         if (j.radius > kWideMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
     } else {
@@ -123,6 +130,21 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
 // The built-in launch shape for an image (before any tuning result).
 oilpaint_variant default_variant(int width, int height, int reff, int levels, bool paper, int device) {
     oilpaint_variant v;
+    if (reff <= kPackedMaxRadius && levels <= 64) {
+        // streamed rows, one wavefront per workgroup: runs as long as the
+        // image allows while keeping about eight workgroups per CU busy
+        const DeviceInfo d = device_info(device);
+        const long cus = d.ok ? d.cus : 256;
+        const long strips = (width + 63) / 64;
+        const long want = 8L * cus;
+        long rows = (strips * (long)height + want - 1) / want;
+        rows = std::max(16L, std::min(rows, 256L));
+        v.rows = (int)rows;
+        v.waves = 1;
+        v.lanes = 64;
+        v.hist = OILPAINT_HIST_STREAM;
+        return v;
+    }
     v.lanes = 64;
     v.waves = 4;
     v.hist = packed_ok(reff, levels, paper) ? OILPAINT_HIST_PACKED : OILPAINT_HIST_WIDE;

@@ -1,0 +1,751 @@
+// Device code of the oil-paint filter (gfx950), shared by the kernel
+// translation units.
+//
+// The method (Section 4 of the paper: histogram-based oil paint, its serial
+// listing; Section 5: the same body run row-parallel): for each output
+// pixel, bin the pixels of its (2r+1)^2 window by intensity level, keep per
+// level a pixel count and three channel sums, pick the most populated level
+// (lowest on ties) and output that level's channel sums divided by its count.
+//
+// How it is laid out on the GPU (the paper rebuilds the whole window for
+// every pixel; none of the structure below is in the paper):
+//   * A workgroup computes one tile: `lanes` output columns by
+//     waves * rows output rows.  Lane l of wavefront w owns column x0 + l and
+//     output rows [y0 + w*rows, y0 + (w+1)*rows).
+//   * PACKED layout: the tile plus an r-pixel halo is staged once into LDS,
+//     one 32-bit word per pixel {c0, c1, c2, level}; the level is computed
+//     once per staged pixel.  Pixels outside the image get a spare level
+//     (the "trash" bin) that the mode search never scans, so the window needs
+//     no clipping logic.  Each lane keeps its window histogram in LDS, one
+//     64-bit word per level (count:10 | sum2:18 | sum1:18 | sum0:18), bins
+//     interleaved across lanes (bin k of lane l at k*lanes*8 + l*8), which
+//     keeps every lane on its own bank whatever level it touches.  Moving
+//     one row down removes the leaving row and adds the entering row of the
+//     window: 2(2r+1) 64-bit LDS atomics instead of a (2r+1)^2 rebuild.
+//     No field can carry into the next: each stays within its range.
+//   * The mode search scans the lane's bins with the key
+//     (count << 22) | (255 - level), whose maximum is the most populated
+//     level with the lowest index among ties.
+//   * The division is exact (see div_exact).
+//   * WIDE layout (windows wider than 31 or more than 255 levels): two
+//     64-bit words per level with 32-bit count and sums, pixels read from
+//     device memory.
+#pragma once
+
+#include <type_traits>
+
+#include "oilpaint_internal.h"
+
+namespace oilpaint_impl {
+namespace dev {
+
+// floor(s / n) for 1 <= n <= 961 and s <= 255 n, without a divide: the float
+// estimate s * (1/n) is within 1e-4 of s/n (s < 2^18, relative error of the
+// reciprocal and the product a few ulp), and s/n lies at least 1/961 below
+// the next integer, so truncating the estimate gives floor(s/n) or one less;
+// the integer checks correct either way.
+__device__ __forceinline__ uint32_t div_exact(uint32_t s, uint32_t n, float rn) {
+    uint32_t q = (uint32_t)((float)s * rn);
+    q += ((q + 1u) * n <= s) ? 1u : 0u;
+    q -= (q * n > s) ? 1u : 0u;
+    return q;
+}
+
+// Intensity level of a pixel with channel sum s (Section 4 listing, level
+// step).  Default reading: ((s / 3) * L) / 256, truncating, with
+// s / 3 == (s * 43691) >> 17 for s <= 765.  Paper form: floor(s * L / 765)
+// (equal to the listing's double expression for every s <= 765, L <= 256),
+// with floor(x / 765) == mulhi(x, 5614337) for x <= 765 * 256.
+__device__ __forceinline__ uint32_t level_of(uint32_t s, uint32_t L, bool paper) {
+    if (paper) return __umulhi(s * L, 5614337u);
+    return (((s * 43691u) >> 17) * L) >> 8;
+}
+
+// Image pointers as global-address-space pointers, so loads and stores are
+// global_* instructions (flat ones would also count against the LDS wait
+// counter and serialize with the histogram traffic).
+typedef const __attribute__((address_space(1))) uint8_t* gsrc_t;
+typedef __attribute__((address_space(1))) uint8_t* gdst_t;
+__device__ __forceinline__ gsrc_t gsrc(const uint8_t* p) { return (gsrc_t)p; }
+__device__ __forceinline__ gdst_t gdst(uint8_t* p) { return (gdst_t)p; }
+
+// Compiler-only ordering point for LDS traffic shared between the lanes of
+// one wavefront: the hardware already executes a wavefront's LDS operations
+// in order, so no wait is needed, only that the compiler keep program order.
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void lds_sub(T* p, T v) {
+    __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// 64-bit packed bin increment for a staged word {c0, c1, c2, level}.
+__device__ __forceinline__ uint64_t packed_value(uint32_t w) {
+    const uint32_t lo = (w & 0xFFu) | (((w >> 8) & 0xFFu) << 18);
+    const uint32_t hi = (((w >> 16) & 0xFFu) << 4) | (1u << 22);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bin formats of the streamed layout (one 64-bit word per level):
+//   F18: count:10 @54 | sum2:18 @36 | sum1:18 @18 | sum0:18 @0  -- windows
+//        up to 31 x 31 (count <= 961, sums <= 245,055)
+//   F16: count:8 @48 | sum2:16 @32 | sum1:16 @16 | sum0:16 @0   -- windows
+//        up to 15 x 15 (count <= 225, sums <= 57,375); byte-aligned fields,
+//        so the increment of a staged word {c0, c1, c2, level} is two byte
+//        permutes.
+template <bool F16>
+struct BinFmt;
+
+template <>
+struct BinFmt<false> {
+    static constexpr uint32_t kCountMask = 0xFFC00000u;  // count bits in the high word
+    static constexpr int kCountShift = 22;
+    static __device__ __forceinline__ uint64_t inc(uint32_t w) { return packed_value(w); }
+    static __device__ __forceinline__ void sums(uint64_t b, uint32_t& s0, uint32_t& s1, uint32_t& s2) {
+        const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+        s0 = lo & 0x3FFFFu;
+        s1 = (lo >> 18) | ((hi & 0xFu) << 14);
+        s2 = (hi >> 4) & 0x3FFFFu;
+    }
+};
+
+template <>
+struct BinFmt<true> {
+    static constexpr uint32_t kCountMask = 0x00FF0000u;
+    static constexpr int kCountShift = 16;
+    static __device__ __forceinline__ uint64_t inc(uint32_t w) {
+        const uint32_t lo = __builtin_amdgcn_perm(0u, w, 0x0C010C00u);  // c0 | c1 << 16
+        const uint32_t hi = __builtin_amdgcn_perm(1u, w, 0x0C040C02u);  // c2 | 1 << 16
+        return ((uint64_t)hi << 32) | lo;
+    }
+    static __device__ __forceinline__ void sums(uint64_t b, uint32_t& s0, uint32_t& s1, uint32_t& s2) {
+        const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+        s0 = lo & 0xFFFFu;
+        s1 = lo >> 16;
+        s2 = hi & 0xFFFFu;
+    }
+};
+
+struct TileGeom {
+    int x0, y0, yend;   // first column, first and one-past-last output row
+    int tw, th;         // staged columns and rows (tile + halo)
+};
+
+__device__ __forceinline__ TileGeom tile_geom(const Job& j, int tile) {
+    TileGeom g;
+    const int tx = tile % j.tiles_x;
+    const int ty = tile / j.tiles_x;
+    g.x0 = tx * j.lanes;
+    g.y0 = j.row_begin + ty * j.waves * j.rows;
+    g.yend = min(g.y0 + j.waves * j.rows, j.row_end);
+    g.tw = j.lanes + 2 * j.radius;
+    g.th = (g.yend - g.y0) + 2 * j.radius;
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// PACKED layout
+// ---------------------------------------------------------------------------
+
+// Staged word of an in-image pixel.
+__device__ __forceinline__ uint32_t staged_word(uint32_t c0, uint32_t c1, uint32_t c2, const Job& j) {
+    uint32_t lev = level_of(c0 + c1 + c2, (uint32_t)j.levels, j.paper != 0);
+    if (lev >= (uint32_t)j.levels) lev = (uint32_t)j.white;  // paper form: pure white
+    return c0 | (c1 << 8) | (c2 << 16) | (lev << 24);
+}
+
+// Stage the tile and its r-pixel halo into LDS.  Every thread of the
+// workgroup takes part; pixels are visited in chunks of 8 per thread so that
+// 24 byte loads are in flight before any is used.  TW is the staged width
+// when known at compile time (0: g.tw).  The caller synchronizes.
+template <int TW = 0>
+__device__ __forceinline__ void stage_packed(const Job& j, const TileGeom& g, uint32_t* tw32) {
+    constexpr int CH = 8;
+    const int r = j.radius;
+    const int tw = TW ? TW : g.tw;
+    const int npx = tw * g.th;
+    const int nthr = blockDim.x;
+    const uint32_t trash_word = (uint32_t)j.trash << 24;
+    for (int base = threadIdx.x; base < npx; base += CH * nthr) {
+        uint32_t c[CH][3];
+        bool in[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int p = base + i * nthr;
+            const int row = p / tw;
+            const int col = p - row * tw;
+            const int gy = g.y0 - r + row;
+            const int gx = g.x0 - r + col;
+            in[i] = p < npx && gy >= 0 && gy < j.height && gx >= 0 && gx < j.width;
+            c[i][0] = c[i][1] = c[i][2] = 0;
+            if (in[i]) {
+                gsrc_t q = gsrc(j.src) + (size_t)gy * (size_t)j.stride + 3 * gx;
+                c[i][0] = q[0];
+                c[i][1] = q[1];
+                c[i][2] = q[2];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int p = base + i * nthr;
+            if (p < npx) tw32[p] = in[i] ? staged_word(c[i][0], c[i][1], c[i][2], j) : trash_word;
+        }
+    }
+}
+
+// Output of one pixel from its winning bin word (packed layout).
+__device__ __forceinline__ void store_packed(const Job& j, int x, int y, uint32_t n, uint64_t b) {
+    bool store = x < j.width;
+    if (j.paper) store = store && n > 0 && x >= j.radius && x < j.width - j.radius && y >= j.radius &&
+                         y < j.height - j.radius;
+    if (!store) return;
+    const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+    const uint32_t s0 = lo & 0x3FFFFu;
+    const uint32_t s1 = (lo >> 18) | ((hi & 0xFu) << 14);
+    const uint32_t s2 = (hi >> 4) & 0x3FFFFu;
+    const float rn = __frcp_rn((float)n);
+    gdst_t o = gdst(j.dst) + (size_t)y * (size_t)j.dst_stride + 3 * x;
+    o[0] = (uint8_t)div_exact(s0, n, rn);
+    o[1] = (uint8_t)div_exact(s1, n, rn);
+    o[2] = (uint8_t)div_exact(s2, n, rn);
+}
+
+// The three output bytes of a pixel from its winning bin word, packed as
+// c0 | c1 << 8 | c2 << 16.
+template <bool F16>
+__device__ __forceinline__ uint32_t finalize_packed(uint32_t n, uint64_t b) {
+    uint32_t s0, s1, s2;
+    BinFmt<F16>::sums(b, s0, s1, s2);
+    const uint32_t nn = n ? n : 1u;
+    const float rn = __frcp_rn((float)nn);
+    return div_exact(s0, nn, rn) | (div_exact(s1, nn, rn) << 8) | (div_exact(s2, nn, rn) << 16);
+}
+
+// Mode search over bins 0 .. scan-1 of one lane (scan a multiple of 8, at
+// most SB): the reads are issued by mode_load, in groups of eight, as full
+// 64-bit words (whole 8-byte slots keep the 64 lanes on distinct banks; a
+// read of the high halves alone would pair lanes on a bank), and reduced by
+// mode_reduce to the key (count << kCountShift) | (63 - level), whose
+// maximum is the most populated level, the lowest among equals.
+template <int SB>
+struct ModeBins {
+    uint64_t v[SB];
+};
+
+template <int SB>
+__device__ __forceinline__ void mode_load(ModeBins<SB>& m, const uint8_t* hl, int scan) {
+#pragma unroll
+    for (int g = 0; g < SB / 8; ++g)
+        if (g * 8 < scan) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) m.v[g * 8 + i] = *reinterpret_cast<const uint64_t*>(hl + (g * 8 + i) * 512);
+        }
+}
+
+template <int SB, bool F16>
+__device__ __forceinline__ uint32_t mode_reduce(const ModeBins<SB>& m, int scan) {
+    static_assert(SB <= 64, "level index must fit 6 bits");
+    constexpr uint32_t M = BinFmt<F16>::kCountMask;
+    uint32_t best = 0;
+#pragma unroll
+    for (int g = 0; g < SB / 8; ++g)
+        if (g * 8 < scan) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) asm volatile("" ::"v"((uint32_t)m.v[g * 8 + i]));  // keep whole-word reads
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                const uint32_t k = (uint32_t)(g * 8 + i);
+                best = max(best, max(((uint32_t)(m.v[k] >> 32) & M) | (63u - k),
+                                     ((uint32_t)(m.v[k + 1] >> 32) & M) | (62u - k)));
+            }
+        }
+    return best;
+}
+
+// Store one output row of a 64-column strip.  A full strip goes through a
+// 192-byte LDS row buffer and leaves as 48 dword stores; a partial strip (or
+// the paper form, which writes only part of a row) stores per pixel.
+__device__ __forceinline__ void store_row(const Job& j, int x0, int y, uint32_t n, uint32_t px, uint8_t* obuf) {
+    const int lane = threadIdx.x & 63;
+    const int x = x0 + lane;
+    gdst_t row = gdst(j.dst) + (size_t)y * (size_t)j.dst_stride;
+    if (x0 + 64 <= j.width && !j.paper) {
+        obuf[3 * lane] = (uint8_t)px;
+        obuf[3 * lane + 1] = (uint8_t)(px >> 8);
+        obuf[3 * lane + 2] = (uint8_t)(px >> 16);
+        lds_order();
+        if (lane < 48) {
+            const uint32_t w = reinterpret_cast<const uint32_t*>(obuf)[lane];
+            *reinterpret_cast<__attribute__((address_space(1))) uint32_t*>(row + 3 * x0 + 4 * lane) = w;
+        }
+        lds_order();
+        return;
+    }
+    bool store = x < j.width;
+    if (j.paper) store = store && n > 0 && x >= j.radius && x < j.width - j.radius && y >= j.radius &&
+                         y < j.height - j.radius;
+    if (store) {
+        row[3 * x] = (uint8_t)px;
+        row[3 * x + 1] = (uint8_t)(px >> 8);
+        row[3 * x + 2] = (uint8_t)(px >> 16);
+    }
+}
+
+// Any radius <= 15, lane count and level count: runtime loops.
+__device__ __forceinline__ void tile_packed(const Job& j, int tile, uint8_t* lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = j.waves;
+    const int r = j.radius;
+    const TileGeom g = tile_geom(j, tile);
+    uint32_t* tw32 = reinterpret_cast<uint32_t*>(lds);
+    stage_packed(j, g, tw32);
+    __syncthreads();
+
+    const int yw0 = g.y0 + wave * j.rows;
+    if (wave >= nw || lane >= j.lanes || yw0 >= g.yend) return;
+    const int yw1 = min(yw0 + j.rows, g.yend);
+    const size_t tile_bytes = ((size_t)g.tw * (size_t)(nw * j.rows + 2 * r) * 4 + 15) & ~(size_t)15;
+    const uint32_t binstride = (uint32_t)j.lanes * 8u;
+    uint8_t* hl = lds + tile_bytes + (size_t)wave * j.bins * binstride + lane * 8;
+    for (int k = 0; k < j.bins; ++k) *reinterpret_cast<uint64_t*>(hl + k * binstride) = 0;
+
+    const int x = g.x0 + lane;
+    const int span = 2 * r + 1;
+    const uint32_t* t = tw32 + (yw0 - g.y0) * g.tw + lane;
+    for (int dy = 0; dy < span; ++dy, t += g.tw)
+        for (int dx = 0; dx < span; ++dx) {
+            const uint32_t w = t[dx];
+            lds_add(reinterpret_cast<uint64_t*>(hl + (w >> 24) * binstride), packed_value(w));
+        }
+    for (int y = yw0; y < yw1; ++y) {
+        if (y > yw0) {
+            // leaving image row y-1-r is staged row y-1-y0; entering row y+r is y+2r-y0
+            const uint32_t* to = tw32 + (y - 1 - g.y0) * g.tw + lane;
+            const uint32_t* tn = tw32 + (y + 2 * r - g.y0) * g.tw + lane;
+            for (int dx = 0; dx < span; ++dx) {
+                const uint32_t wo = to[dx];
+                const uint32_t wn = tn[dx];
+                lds_sub(reinterpret_cast<uint64_t*>(hl + (wo >> 24) * binstride), packed_value(wo));
+                lds_add(reinterpret_cast<uint64_t*>(hl + (wn >> 24) * binstride), packed_value(wn));
+            }
+        }
+        uint32_t best = 0;
+        for (int k = 0; k < j.scan; ++k) {
+            const uint32_t hi = (uint32_t)(*reinterpret_cast<const uint64_t*>(hl + k * binstride) >> 32);
+            best = max(best, (hi & 0xFFC00000u) | (255u - (uint32_t)k));
+        }
+        const uint32_t kbest = 255u - (best & 0xFFu);
+        store_packed(j, x, y, best >> 22, *reinterpret_cast<const uint64_t*>(hl + kbest * binstride));
+    }
+}
+
+// Fast path: 64 lanes, a compile-time radius R <= 15 and at most 64 scanned
+// levels (the level count rounded up to a multiple of 8; the extra bins stay
+// empty and the trash bin sits after them).  Ordering within a lane's loop:
+//   atomics of step y -> loads of step y+1's words -> mode-search reads of
+//   row y+1 -> (consume) row y's winning bin, divide, store,
+// so every LDS round trip overlaps other LDS traffic of the same wavefront.
+template <int R, int SB>
+__device__ __forceinline__ void tile_packed_fast(const Job& j, int tile, uint8_t* lds) {
+    constexpr int SPAN = 2 * R + 1;
+    constexpr int TW = 64 + 2 * R;
+    constexpr uint32_t BS = 64u * 8u;  // bin stride
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = j.waves;
+    const int scan = j.scan;  // multiple of 8, <= SB
+    const TileGeom g = tile_geom(j, tile);
+    uint32_t* tw32 = reinterpret_cast<uint32_t*>(lds);
+    stage_packed<TW>(j, g, tw32);
+    __syncthreads();
+
+    const int yw0 = g.y0 + wave * j.rows;
+    if (wave >= nw || yw0 >= g.yend) return;
+    const int yw1 = min(yw0 + j.rows, g.yend);
+    const size_t tile_bytes = ((size_t)TW * (size_t)(nw * j.rows + 2 * R) * 4 + 15) & ~(size_t)15;
+    uint8_t* hl = lds + tile_bytes + (size_t)wave * j.bins * BS + lane * 8;
+    for (int k = 0; k < j.bins; ++k) *reinterpret_cast<uint64_t*>(hl + k * BS) = 0;
+    const int x = g.x0 + lane;
+
+    // first window, one staged row at a time, the next row's words loaded
+    // before the current row's atomics
+    const uint32_t* t = tw32 + (yw0 - g.y0) * TW + lane;
+    uint32_t w[SPAN];
+#pragma unroll
+    for (int i = 0; i < SPAN; ++i) w[i] = t[i];
+#pragma unroll 1
+    for (int dy = 0; dy < SPAN; ++dy) {
+        uint32_t cur[SPAN];
+#pragma unroll
+        for (int i = 0; i < SPAN; ++i) cur[i] = w[i];
+        t += TW;
+        if (dy + 1 < SPAN) {
+#pragma unroll
+            for (int i = 0; i < SPAN; ++i) w[i] = t[i];
+        }
+#pragma unroll
+        for (int i = 0; i < SPAN; ++i)
+            lds_add(reinterpret_cast<uint64_t*>(hl + (cur[i] >> 24) * BS), packed_value(cur[i]));
+    }
+
+    // words of the step yw0 -> yw0+1
+    uint32_t wo[SPAN], wn[SPAN];
+    if (yw0 + 1 < yw1) {
+        const uint32_t* to = tw32 + (yw0 - g.y0) * TW + lane;
+        const uint32_t* tn = tw32 + (yw0 + 1 + 2 * R - g.y0) * TW + lane;
+#pragma unroll
+        for (int i = 0; i < SPAN; ++i) {
+            wo[i] = to[i];
+            wn[i] = tn[i];
+        }
+    }
+    // mode-search reads of row yw0 (high words: count and sum2 bits)
+    uint32_t hb[SB];
+#pragma unroll
+    for (int k = 0; k < SB; ++k)
+        if (k < scan) hb[k] = (uint32_t)(*reinterpret_cast<const uint64_t*>(hl + k * BS) >> 32);
+
+#pragma unroll 1
+    for (int y = yw0; y < yw1; ++y) {
+        // reduce row y's keys
+        uint32_t best = 0;
+#pragma unroll
+        for (int k = 0; k < SB; k += 2)
+            if (k < scan)
+                best = max(best, max((hb[k] & 0xFFC00000u) | (255u - (uint32_t)k),
+                                     (hb[k + 1] & 0xFFC00000u) | (254u - (uint32_t)k)));
+        const uint32_t kbest = 255u - (best & 0xFFu);
+        const uint64_t win = *reinterpret_cast<const uint64_t*>(hl + kbest * BS);
+        if (y + 1 < yw1) {
+            // step y -> y+1
+#pragma unroll
+            for (int i = 0; i < SPAN; ++i) {
+                lds_sub(reinterpret_cast<uint64_t*>(hl + (wo[i] >> 24) * BS), packed_value(wo[i]));
+                lds_add(reinterpret_cast<uint64_t*>(hl + (wn[i] >> 24) * BS), packed_value(wn[i]));
+            }
+            if (y + 2 < yw1) {
+                // step y+1 -> y+2 removes image row y+1-R (staged row y+1-y0)
+                // and adds image row y+2+R (staged row y+2+2R-y0)
+                const uint32_t* to = tw32 + (y + 1 - g.y0) * TW + lane;
+                const uint32_t* tn = tw32 + (y + 2 + 2 * R - g.y0) * TW + lane;
+#pragma unroll
+                for (int i = 0; i < SPAN; ++i) {
+                    wo[i] = to[i];
+                    wn[i] = tn[i];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < SB; ++k)
+                if (k < scan) hb[k] = (uint32_t)(*reinterpret_cast<const uint64_t*>(hl + k * BS) >> 32);
+        }
+        store_packed(j, x, y, best >> 22, win);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// WIDE layout: 32-bit count and sums in two 64-bit words per level
+// (A = count | sum0 << 32, B = sum1 | sum2 << 32); pixels read from memory.
+// ---------------------------------------------------------------------------
+struct WidePix {
+    uint32_t lev;
+    uint64_t a, b;
+};
+
+__device__ __forceinline__ WidePix wide_pixel(const Job& j, int gx, int gy) {
+    WidePix p;
+    if (gx >= 0 && gx < j.width && gy >= 0 && gy < j.height) {
+        gsrc_t q = gsrc(j.src) + (size_t)gy * (size_t)j.stride + 3 * gx;
+        const uint32_t c0 = q[0], c1 = q[1], c2 = q[2];
+        p.lev = level_of(c0 + c1 + c2, (uint32_t)j.levels, j.paper != 0);
+        if (p.lev >= (uint32_t)j.levels) p.lev = (uint32_t)j.white;
+        p.a = 1ull | ((uint64_t)c0 << 32);
+        p.b = (uint64_t)c1 | ((uint64_t)c2 << 32);
+    } else {
+        p.lev = (uint32_t)j.trash;
+        p.a = 0;
+        p.b = 0;
+    }
+    return p;
+}
+
+__device__ __forceinline__ void tile_wide(const Job& j, int tile, uint8_t* lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = j.radius;
+    const TileGeom g = tile_geom(j, tile);
+    const int yw0 = g.y0 + wave * j.rows;
+    if (wave >= j.waves || lane >= j.lanes || yw0 >= g.yend) return;
+    const int yw1 = min(yw0 + j.rows, g.yend);
+    const uint32_t binstride = (uint32_t)j.lanes * 8u;
+    uint8_t* ha = lds + (size_t)wave * 2 * j.bins * binstride + lane * 8;
+    uint8_t* hb = ha + (size_t)j.bins * binstride;
+    for (int k = 0; k < j.bins; ++k) {
+        *reinterpret_cast<uint64_t*>(ha + k * binstride) = 0;
+        *reinterpret_cast<uint64_t*>(hb + k * binstride) = 0;
+    }
+    const int x = g.x0 + lane;
+    const int span = 2 * r + 1;
+    for (int dy = 0; dy < span; ++dy) {
+        for (int dx = 0; dx < span; ++dx) {
+            const WidePix p = wide_pixel(j, x - r + dx, yw0 - r + dy);
+            lds_add(reinterpret_cast<uint64_t*>(ha + p.lev * binstride), p.a);
+            lds_add(reinterpret_cast<uint64_t*>(hb + p.lev * binstride), p.b);
+        }
+    }
+    for (int y = yw0; y < yw1; ++y) {
+        if (y > yw0) {
+            for (int dx = 0; dx < span; ++dx) {
+                const WidePix po = wide_pixel(j, x - r + dx, y - 1 - r);
+                const WidePix pn = wide_pixel(j, x - r + dx, y + r);
+                lds_sub(reinterpret_cast<uint64_t*>(ha + po.lev * binstride), po.a);
+                lds_sub(reinterpret_cast<uint64_t*>(hb + po.lev * binstride), po.b);
+                lds_add(reinterpret_cast<uint64_t*>(ha + pn.lev * binstride), pn.a);
+                lds_add(reinterpret_cast<uint64_t*>(hb + pn.lev * binstride), pn.b);
+            }
+        }
+        uint32_t bestc = 0, bestk = 0;
+        for (int k = 0; k < j.scan; ++k) {
+            const uint32_t c = (uint32_t)*reinterpret_cast<const uint64_t*>(ha + k * binstride);
+            if (c > bestc) {
+                bestc = c;
+                bestk = (uint32_t)k;
+            }
+        }
+        const uint64_t a = *reinterpret_cast<const uint64_t*>(ha + bestk * binstride);
+        const uint64_t b = *reinterpret_cast<const uint64_t*>(hb + bestk * binstride);
+        const uint32_t n = (uint32_t)a;
+        bool store = x < j.width;
+        if (j.paper) store = store && n > 0 && x >= r && x < j.width - r && y >= r && y < j.height - r;
+        if (store && n > 0) {
+            // floor of the correctly rounded double quotient is exact here:
+            // s < 2^32 and n < 2^25, so s/n is at least 1/n away from the
+            // next integer, far more than the rounding error.
+            const double dn = (double)n;
+            gdst_t o = gdst(j.dst) + (size_t)y * (size_t)j.dst_stride + 3 * x;
+            o[0] = (uint8_t)(uint32_t)((double)(uint32_t)(a >> 32) / dn);
+            o[1] = (uint8_t)(uint32_t)((double)(uint32_t)b / dn);
+            o[2] = (uint8_t)(uint32_t)((double)(uint32_t)(b >> 32) / dn);
+        }
+    }
+}
+
+// STREAM layout: one wavefront per workgroup, 64 output columns, a run of
+// `rows` output rows.  Same packed bins as the fast path, but only the
+// 2r+4 image rows around the window are staged, in a ring, so the
+// LDS a workgroup needs is its histogram plus a few KB: several wavefronts
+// fit on a CU and runs can be long (the (2r+1)^2 first window is paid once
+// per run).  Image rows are fetched two rows ahead into registers.
+//   LDS: [histogram: bins x 64 lanes x 8 B][ring: (2R+4) rows x (64+2R) words]
+//        [output row buffer: 192 B]
+//   Ring slot of image row g: (g - (ya - R)) mod (2R+4).
+// Ring rows beyond the 2r+1 of a window: the entering row and the two rows
+// fetched ahead.
+constexpr int kStreamRingExtra = 4;
+
+struct RowBytes {
+    uint32_t a0, a1, a2, b0, b1, b2;  // pixels at columns lane and lane + 64
+    bool ina, inb;                    // real pixels (else: outside the image)
+};
+
+// Bytes of image row gy at columns x0-R+lane and x0-R+lane+64.  The loads
+// are unconditional -- coordinates are clamped into the image and a flag
+// records whether the pixel is real -- so that no branch surrounds them and
+// the wait for their data can be placed exactly, two steps later.
+template <int R>
+__device__ __forceinline__ void stream_load_row(const Job& j, int x0, int gy, RowBytes& rb) {
+    const int lane = threadIdx.x & 63;
+    const bool row_in = gy >= 0 && gy < j.height;
+    const int gxa = x0 - R + lane;
+    const int gxb = gxa + 64;
+    const int gyc = min(max(gy, 0), j.height - 1);
+    const int xa = min(max(gxa, 0), j.width - 1);
+    const int xb = min(gxb, j.width - 1);
+    gsrc_t row = gsrc(j.src) + (size_t)gyc * (size_t)j.stride;
+    rb.a0 = row[3 * xa];
+    rb.a1 = row[3 * xa + 1];
+    rb.a2 = row[3 * xa + 2];
+    rb.ina = row_in && gxa >= 0 && gxa < j.width;
+    if (R > 0) {
+        rb.b0 = row[3 * xb];
+        rb.b1 = row[3 * xb + 1];
+        rb.b2 = row[3 * xb + 2];
+        rb.inb = row_in && lane < 2 * R && gxb < j.width;
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void stream_write_row(const Job& j, uint32_t* slot, const RowBytes& rb) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t trash_word = (uint32_t)j.trash << 24;
+    slot[lane] = rb.ina ? staged_word(rb.a0, rb.a1, rb.a2, j) : trash_word;
+    if (R > 0 && lane < 2 * R) slot[lane + 64] = rb.inb ? staged_word(rb.b0, rb.b1, rb.b2, j) : trash_word;
+}
+
+template <int R, int SB>
+__device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds) {
+    constexpr int SPAN = 2 * R + 1;
+    constexpr int TW = 64 + 2 * R;
+    constexpr int RB = kStreamRingExtra + 2 * R;  // ring rows
+    constexpr uint32_t BS = 64u * 8u;
+    constexpr bool F16 = R <= 7;
+    using Fmt = BinFmt<F16>;
+    const int lane = threadIdx.x & 63;
+    const int scan = j.scan;
+    const int tx = unit % j.tiles_x;
+    const int ty = unit / j.tiles_x;
+    const int x0 = tx * 64;
+    const int ya = j.row_begin + ty * j.rows;
+    const int yb = min(ya + j.rows, j.row_end);
+    uint8_t* hl = lds + lane * 8;
+    uint32_t* ring = reinterpret_cast<uint32_t*>(lds + (size_t)j.bins * BS);
+    uint8_t* obuf = reinterpret_cast<uint8_t*>(ring + RB * TW);  // one output row, 192 bytes
+    auto slot = [&](int g) { return ring + ((g - (ya - R)) % RB) * TW; };
+
+    // rows ya-R .. ya+R+1 (ring slots 0 .. 2R+1)
+    {
+        TileGeom g;
+        g.x0 = x0;
+        g.y0 = ya;
+        g.yend = ya + 2 * R + 2;
+        g.tw = TW;
+        g.th = 2 * R + 2;
+        stage_packed<TW>(j, g, ring);
+    }
+    for (int k = 0; k < j.bins; ++k) *reinterpret_cast<uint64_t*>(hl + k * BS) = 0;
+    // the ring is read across lanes: keep every read after every write (one
+    // wavefront, and LDS executes its operations in issue order)
+    lds_order();
+    // rows ya+2+R and ya+3+R are fetched now and staged at the top of the
+    // first loop iteration
+    RowBytes q0, q1;
+    stream_load_row<R>(j, x0, ya + 2 + R, q0);
+    stream_load_row<R>(j, x0, ya + 3 + R, q1);
+
+    // first window: slots 0 .. 2R
+    {
+        const uint32_t* t = ring + lane;
+        uint32_t w[SPAN];
+#pragma unroll
+        for (int i = 0; i < SPAN; ++i) w[i] = t[i];
+#pragma unroll 1
+        for (int dy = 0; dy < SPAN; ++dy) {
+            uint32_t cur[SPAN];
+#pragma unroll
+            for (int i = 0; i < SPAN; ++i) cur[i] = w[i];
+            t += TW;
+            if (dy + 1 < SPAN) {
+#pragma unroll
+                for (int i = 0; i < SPAN; ++i) w[i] = t[i];
+            }
+#pragma unroll
+            for (int i = 0; i < SPAN; ++i)
+                lds_add(reinterpret_cast<uint64_t*>(hl + (cur[i] >> 24) * BS), Fmt::inc(cur[i]));
+        }
+    }
+    // words of the step ya -> ya+1: leaving row ya-R, entering row ya+1+R
+    uint32_t wo[SPAN], wn[SPAN];
+    {
+        const uint32_t* so = slot(ya - R) + lane;
+        const uint32_t* sn = slot(ya + 1 + R) + lane;
+#pragma unroll
+        for (int i = 0; i < SPAN; ++i) {
+            wo[i] = so[i];
+            wn[i] = sn[i];
+        }
+    }
+    ModeBins<SB> mb;
+    mode_load<SB>(mb, hl, scan);
+
+    // One output row y, then the step y -> y+1 and the words of the next step.
+    auto row_step = [&](int y, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        const uint32_t best = mode_reduce<SB, F16>(mb, scan);
+        const uint32_t kbest = 63u - (best & 63u);
+        const uint32_t n = best >> Fmt::kCountShift;
+        const uint64_t win = *reinterpret_cast<const uint64_t*>(hl + kbest * BS);
+        if (FULL || y + 1 < yb) {
+#pragma unroll
+            for (int i = 0; i < SPAN; ++i) {
+                lds_sub(reinterpret_cast<uint64_t*>(hl + (wo[i] >> 24) * BS), Fmt::inc(wo[i]));
+                lds_add(reinterpret_cast<uint64_t*>(hl + (wn[i] >> 24) * BS), Fmt::inc(wn[i]));
+            }
+            if (FULL || y + 2 < yb) {
+                // step y+1 -> y+2 removes row y+1-R and adds row y+2+R
+                const uint32_t* so = slot(y + 1 - R) + lane;
+                const uint32_t* sn = slot(y + 2 + R) + lane;
+#pragma unroll
+                for (int i = 0; i < SPAN; ++i) {
+                    wo[i] = so[i];
+                    wn[i] = sn[i];
+                }
+            }
+            mode_load<SB>(mb, hl, scan);
+        }
+        store_row(j, x0, y, n, finalize_packed<F16>(n, win), obuf);
+    };
+    // Two output rows per iteration.  At the top, rows y+2+R and y+3+R
+    // (fetched one iteration earlier) enter the ring -- into the slots of rows
+    // y-R-2 and y-R-1, which no window needs any more -- and rows y+4+R and
+    // y+5+R are fetched for the next iteration.
+    using Full = std::true_type;
+    using Tail = std::false_type;
+    int y = ya;
+#pragma unroll 1
+    for (; y + 5 < yb; y += 2) {
+        stream_write_row<R>(j, slot(y + 2 + R), q0);
+        stream_write_row<R>(j, slot(y + 3 + R), q1);
+        lds_order();
+        stream_load_row<R>(j, x0, y + 4 + R, q0);
+        stream_load_row<R>(j, x0, y + 5 + R, q1);
+        row_step(y, Full{});
+        row_step(y + 1, Full{});
+    }
+#pragma unroll 1
+    for (; y < yb; y += 2) {
+        if (y + 2 < yb) stream_write_row<R>(j, slot(y + 2 + R), q0);
+        if (y + 3 < yb) stream_write_row<R>(j, slot(y + 3 + R), q1);
+        lds_order();
+        if (y + 4 < yb) stream_load_row<R>(j, x0, y + 4 + R, q0);
+        if (y + 5 < yb) stream_load_row<R>(j, x0, y + 5 + R, q1);
+        row_step(y, Tail{});
+        if (y + 1 < yb) row_step(y + 1, Tail{});
+    }
+}
+
+// Batch form: the streamed, generic packed and wide layouts in one kernel,
+// selected per tile (a batch job of the tile-staged fast layout runs as
+// generic packed).
+__device__ __forceinline__ void run_tile(const Job& j, int tile, uint8_t* lds) {
+    if (j.hist == OILPAINT_HIST_WIDE) {
+        tile_wide(j, tile, lds);
+        return;
+    }
+    if (j.hist == OILPAINT_HIST_STREAM) {
+        const bool small = j.scan <= 32;
+        switch (j.radius) {
+#define OILPAINT_STREAM_CASE(R)               \
+    case R:                                   \
+        if (small)                            \
+            tile_stream<R, 32>(j, tile, lds); \
+        else                                  \
+            tile_stream<R, 64>(j, tile, lds); \
+        return;
+            OILPAINT_STREAM_CASE(0) OILPAINT_STREAM_CASE(1) OILPAINT_STREAM_CASE(2) OILPAINT_STREAM_CASE(3)
+            OILPAINT_STREAM_CASE(4) OILPAINT_STREAM_CASE(5) OILPAINT_STREAM_CASE(6) OILPAINT_STREAM_CASE(7)
+            OILPAINT_STREAM_CASE(8) OILPAINT_STREAM_CASE(9) OILPAINT_STREAM_CASE(10) OILPAINT_STREAM_CASE(11)
+            OILPAINT_STREAM_CASE(12) OILPAINT_STREAM_CASE(13) OILPAINT_STREAM_CASE(14) OILPAINT_STREAM_CASE(15)
+#undef OILPAINT_STREAM_CASE
+            default: break;
+        }
+        return;
+    }
+    tile_packed(j, tile, lds);
+}
+
+}  // namespace dev
+}  // namespace oilpaint_impl

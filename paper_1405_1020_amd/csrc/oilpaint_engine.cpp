@@ -23,7 +23,7 @@ oilpaint_variant choose_variant(int width, int height, int reff, int levels, boo
 
 namespace {
 
-constexpr int kBatchWaves = 4;
+constexpr int kBatchWaves = 1;
 
 // Launch shape of a job inside a persistent launch of `waves` wavefronts per
 // workgroup: the job's own choice with at most `waves` computing

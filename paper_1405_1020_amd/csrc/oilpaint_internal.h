@@ -65,12 +65,21 @@ size_t lds_bytes(const Job& j);
 // of 8 empty bins on the fast path -- then the paper form's white level,
 // then the bin for pixels outside the image.
 inline void set_layout(Job& j) {
-    j.fast = (j.hist == OILPAINT_HIST_PACKED && j.lanes == 64 && j.radius <= kPackedMaxRadius && j.levels <= 64) ? 1 : 0;
+    j.fast = ((j.hist == OILPAINT_HIST_PACKED || j.hist == OILPAINT_HIST_STREAM) && j.lanes == 64 &&
+              j.radius <= kPackedMaxRadius && j.levels <= 64) ? 1 : 0;
     j.scan = j.fast ? (j.levels + 7) / 8 * 8 : j.levels;
     j.white = j.scan;
     j.trash = j.scan + (j.paper ? 1 : 0);
     j.bins = j.trash + 1;
 }
+
+// Per-radius kernels (oilpaint_k_fast_*.hip, oilpaint_k_stream_*.hip):
+// [radius - 0 or 8][scan bucket].
+typedef void (*PlainKernel)(Job);
+extern const PlainKernel kFast_lo[8][3];
+extern const PlainKernel kFast_hi[8][3];
+extern const PlainKernel kStream_lo[8][2];
+extern const PlainKernel kStream_hi[8][2];
 
 // Kernel launches (oilpaint_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream);

@@ -68,11 +68,13 @@ def test_pick_variant_shapes():
     # the choice is pure host logic once the device facts are cached; without
     # a GPU it falls back to nominal facts
     vv = B.pick_variant(1920, 1080, 5, 20)
-    assert vv.hist == B.HIST_PACKED and vv.lanes in (16, 32, 64) and 1 <= vv.waves <= 16 and vv.rows >= 1
+    assert vv.hist == B.HIST_STREAM and vv.lanes == 64 and vv.waves == 1 and vv.rows >= 1
+    vv = B.pick_variant(1920, 1080, 5, 100)
+    assert vv.hist == B.HIST_PACKED and vv.lanes in (16, 32, 64) and 1 <= vv.waves <= 8 and vv.rows >= 1
     assert B.pick_variant(1920, 1080, 16, 20).hist == B.HIST_WIDE
     assert B.pick_variant(1920, 1080, 5, 256).hist == B.HIST_WIDE
     # a radius beyond the image behaves as the image size
-    assert B.pick_variant(12, 10, 1000, 20).hist == B.HIST_PACKED
+    assert B.pick_variant(12, 10, 1000, 20).hist == B.HIST_STREAM
     assert B.pick_variant(20, 10, 1000, 20).hist == B.HIST_WIDE
 
 

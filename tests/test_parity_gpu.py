@@ -88,7 +88,7 @@ def test_every_variant_same_bytes():
         for rows in (1, 3, 8, 16, 64):
             for waves in (1, 2, 4, 8):
                 for lanes in (16, 32, 64):
-                    for hist in (B.HIST_PACKED, B.HIST_WIDE):
+                    for hist in (B.HIST_PACKED, B.HIST_STREAM, B.HIST_WIDE):
                         v = B.Variant(rows, waves, hist, lanes)
                         try:
                             got = run_plain(img, r, L, pad=3, variant=v)
@@ -97,6 +97,22 @@ def test_every_variant_same_bytes():
                             continue
                         mm = first_mismatch(got, want)
                         assert mm is None, (r, L, v, mm)
+
+
+@pytest.mark.parametrize("r", list(range(16)))
+def test_stream_every_radius(r):
+    # the streamed-row kernels, one per radius, on sizes around the strip
+    # width and the ring height, several run lengths and level counts
+    for (w, h) in [(1, 1), (63, 2 * r + 1), (65, 2 * r + 3), (130, 57)]:
+        img = synth.make_image(w, h, seed=100 + r + w, n_blobs=4, sigma=(2, 15)) if w * h > 100 else \
+            synth.make_random(w, h, seed=100 + r + w)
+        want = {L: ref(img, r, L) for L in (1, 8, 20, 33, 64)}
+        for rows in (1, 2, 5, 16, 300):
+            for L in (1, 8, 20, 33, 64):
+                v = B.Variant(rows, 1, B.HIST_STREAM, 64)
+                got = run_plain(img, r, L, pad=(w + rows) % 5, variant=v)
+                mm = first_mismatch(got, want[L])
+                assert mm is None, (w, h, r, L, rows, mm)
 
 
 def test_repeat_is_deterministic():
