@@ -51,12 +51,22 @@ def lds_bytes_per_pixel(r: int, L: int) -> int:
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1405_1020_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".cpp", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
+    from paper_1405_1020_amd import tune
+    return tune.code_hash()
+
+
+def autotune(synth, quick: bool) -> dict:
+    """Tune the launch shape of every (r, L) the workloads use, each on an
+    image of the size it is used at (a few ms of GPU time per pair)."""
+    from paper_1405_1020_amd import tune
+    out = {}
+    out.update(tune.ensure(synth.FHD_SWEEP, 1920, 1080))
+    if not quick:
+        out.update(tune.ensure([synth.CAMERA_RL], 4000, 3000))
+        out.update(tune.ensure([(2, 20)], 256, 256))
+        out.update(tune.ensure([(r, L) for r in (2, 3, 5, 8) for L in (16, 20, 32)], 2048, 1536))
+        out.update(tune.ensure([(r, L) for r in range(1, 16) for L in (8, 16, 20, 32, 64)], 2400, 1800))
+    return {k: v["variant"] for k, v in out.items()}
 
 
 class Timer:
@@ -273,6 +283,8 @@ def main():
         return
 
     timer = Timer(torch)
+    log("autotune ...")
+    tuned = autotune(synth, args.quick)
     log("plain sweep ...")
     img, src, ms_step, mp_step, per, achieved = bench_plain(torch, B, synth, timer, args.steps, args.warmup)
     value = mp_step / (ms_step / 1e3)
@@ -291,6 +303,7 @@ def main():
                        "traffic": hbm_traffic(None), "kernel": "k_plain",
                        "avg_launch_ms": round(launch_ms, 5)}
     res["sweep"] = per
+    res["tuned_variants"] = tuned
     if not args.quick:
         small_img, r, L = synth.small_case()
         res["small_256x256_r2_L20"] = bench_single(torch, B, timer, small_img, r, L, 50)

@@ -130,14 +130,18 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
 #define OILPAINT_HIST_WIDE   2
 
 typedef struct oilpaint_variant {
-    int32_t rows;   /* output rows per lane, >= 1 */
+    int32_t rows;   /* output rows per lane, >= 1; 0: derived from per_cu */
     int32_t waves;  /* wavefronts per workgroup, 1..8 */
     int32_t hist;   /* OILPAINT_HIST_* */
     int32_t lanes;  /* active lanes (= output columns) per wavefront: 64, 32 or 16 */
+    int32_t per_cu; /* with rows = 0: rows are chosen so that an image yields about
+                       per_cu workgroups per compute unit (1..64), then halved
+                       while the on-chip footprint does not fit */
 } oilpaint_variant;
 
 /* The variant oilpaint_async would use for (radius, levels) and an image of
- * the given size.  Returns OK or ERR_ARG / ERR_NULL. */
+ * the given size, with `rows` resolved for that size.  Returns OK or
+ * ERR_ARG / ERR_NULL. */
 int oilpaint_pick_variant(int width, int height, int radius, int levels, oilpaint_variant *out);
 
 /* Install `v` as the choice for (radius, levels) (the autotuner's result).
@@ -152,6 +156,18 @@ int oilpaint_clear_variants(void);
 /* Filter one image with an explicit variant (for tuning and tests). */
 int oilpaint_async_variant(const uint8_t *src, uint8_t *dst, int width, int height, int stride,
                            int radius, int levels, const oilpaint_variant *v, void *stream);
+
+/* Time n candidate variants for (radius, levels) on a width x height image
+ * that the library allocates and fills with a fixed pseudo-random pattern
+ * (the filter's cost does not depend on the pixel values' distribution in
+ * any way the candidates differ by).  Each candidate is run once untimed,
+ * then `reps` times between HIP events on `stream`; ms_out[i] receives its
+ * average milliseconds per launch, or -1 if it cannot run (radius, levels).
+ * Synchronizes `stream`.  Returns OK, ERR_NULL, ERR_ARG, ERR_NOMEM or
+ * ERR_HIP.  The autotuner (paper_1405_1020_amd/tune.py) installs the winner
+ * with oilpaint_set_variant. */
+int oilpaint_tune(int width, int height, int radius, int levels, const oilpaint_variant *candidates,
+                  int n, int reps, void *stream, float *ms_out);
 
 /* ---------------------------------------------------------------------------
  * Batches: many images of uneven size, radius and level count in ONE

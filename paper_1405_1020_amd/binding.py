@@ -43,13 +43,16 @@ class OilpaintError(RuntimeError):
 
 class Variant(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("hist", ctypes.c_int32), ("lanes", ctypes.c_int32)]
+                ("hist", ctypes.c_int32), ("lanes", ctypes.c_int32), ("per_cu", ctypes.c_int32)]
+
+    def __init__(self, rows=0, waves=1, hist=0, lanes=64, per_cu=8):
+        super().__init__(rows, waves, hist, lanes, per_cu)
 
     def as_tuple(self):
-        return (self.rows, self.waves, self.hist, self.lanes)
+        return (self.rows, self.waves, self.hist, self.lanes, self.per_cu)
 
     def __repr__(self):
-        return "Variant(rows=%d, waves=%d, hist=%d, lanes=%d)" % self.as_tuple()
+        return "Variant(rows=%d, waves=%d, hist=%d, lanes=%d, per_cu=%d)" % self.as_tuple()
 
 
 class Desc(ctypes.Structure):
@@ -76,6 +79,8 @@ _SIGS = {
     "oilpaint_async_variant": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5
                                + [ctypes.POINTER(Variant), ctypes.c_void_p], ctypes.c_int),
     "oilpaint_run": ([ctypes.POINTER(Desc), ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_tune": ([ctypes.c_int] * 4 + [ctypes.POINTER(Variant), ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                       ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "oilpaint_batch": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
                        ctypes.c_int),
     "oilpaint_plan_create": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p,
@@ -219,6 +224,18 @@ def set_variant(radius: int, levels: int, v: Variant) -> int:
 
 def clear_variants():
     lib().oilpaint_clear_variants()
+
+
+def tune_times(width: int, height: int, radius: int, levels: int, candidates, reps: int = 5,
+               stream=None) -> list[float]:
+    """oilpaint_tune: average ms per launch of each candidate (-1 when it
+    cannot run this (radius, levels))."""
+    n = len(candidates)
+    arr = (Variant * n)(*candidates)
+    out = (ctypes.c_float * n)()
+    _check(lib().oilpaint_tune(width, height, radius, levels, arr, n, reps, _stream_ptr(stream), out),
+           "oilpaint_tune")
+    return [float(v) for v in out]
 
 
 @dataclass

@@ -98,9 +98,25 @@ int validate2(const uint8_t* src, int sstride, const uint8_t* dst, int dstride, 
     return OILPAINT_OK;
 }
 
-// Fill the launch-shape fields of `j` from `v`.  Returns OK or UNSUPPORTED.
+// Rows per lane for a variant whose rows are 0: about per_cu workgroups per
+// CU over the job's row band (long runs amortise the (2r+1)^2 first window,
+// short runs give more workgroups).
+int auto_rows(const Job& j, const oilpaint_variant& v, int device) {
+    const DeviceInfo d = device_info(device);
+    const long cus = d.ok ? d.cus : 256;
+    const long strips = (j.width + v.lanes - 1) / v.lanes;
+    const long band = j.row_end - j.row_begin;
+    const long want = (long)std::max(v.per_cu, 1) * cus;
+    long rows = (strips * band + want * v.waves - 1) / (want * v.waves);
+    return (int)std::max(8L, std::min(rows, 1024L));
+}
+
+// Fill the launch-shape fields of `j` from `v`.  With v.rows == 0 the rows
+// are derived from v.per_cu and halved while the on-chip footprint does not
+// fit.  Returns OK or UNSUPPORTED.
 int apply_variant(Job& j, const oilpaint_variant& v, int device) {
-    if (v.rows < 1 || v.rows > 4096 || v.waves < 1 || v.waves > 8) return OILPAINT_ERR_UNSUPPORTED;
+    if (v.rows < 0 || v.rows > 4096 || v.waves < 1 || v.waves > 8) return OILPAINT_ERR_UNSUPPORTED;
+    if (v.rows == 0 && (v.per_cu < 1 || v.per_cu > 64)) return OILPAINT_ERR_UNSUPPORTED;
     if (v.lanes != 64 && v.lanes != 32 && v.lanes != 16) return OILPAINT_ERR_UNSUPPORTED;
     if (v.hist == OILPAINT_HIST_PACKED) {
         if (!packed_ok(j.radius, j.levels, j.paper != 0)) return OILPAINT_ERR_UNSUPPORTED;
@@ -112,14 +128,17 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     } else {
         return OILPAINT_ERR_UNSUPPORTED;
     }
-    j.rows = v.rows;
+    j.rows = v.rows ? v.rows : auto_rows(j, v, device);
     j.lanes = v.lanes;
     j.hist = v.hist;
     j.waves = v.waves;
     set_layout(j);
     const DeviceInfo d = device_info(device);
     const size_t limit = d.ok ? d.lds_per_block : 65536;
-    if (lds_bytes(j) + kStaticLds > limit) return OILPAINT_ERR_UNSUPPORTED;
+    while (lds_bytes(j) + kStaticLds > limit) {
+        if (v.rows != 0 || j.rows == 1) return OILPAINT_ERR_UNSUPPORTED;
+        j.rows = std::max(1, j.rows / 2);
+    }
     const int band = j.row_end - j.row_begin;
     j.tiles_x = (j.width + j.lanes - 1) / j.lanes;
     const long per_tile = (long)v.waves * j.rows;
@@ -127,41 +146,24 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     return OILPAINT_OK;
 }
 
-// The built-in launch shape for an image (before any tuning result).
+// The built-in launch shape (before any tuning result): streamed rows with
+// about eight one-wavefront workgroups per CU when the window and level
+// count allow it; otherwise tiles of four wavefronts, about two per CU, or
+// the wide layout; shrunk until the on-chip footprint fits.
 oilpaint_variant default_variant(int width, int height, int reff, int levels, bool paper, int device) {
     oilpaint_variant v;
+    v.rows = 0;
+    v.lanes = 64;
     if (reff <= kPackedMaxRadius && levels <= 64) {
-        // streamed rows, one wavefront per workgroup: runs as long as the
-        // image allows while keeping about eight workgroups per CU busy
-        const DeviceInfo d = device_info(device);
-        const long cus = d.ok ? d.cus : 256;
-        const long strips = (width + 63) / 64;
-        const long want = 8L * cus;
-        long rows = (strips * (long)height + want - 1) / want;
-        rows = std::max(16L, std::min(rows, 256L));
-        v.rows = (int)rows;
         v.waves = 1;
-        v.lanes = 64;
         v.hist = OILPAINT_HIST_STREAM;
+        v.per_cu = 8;
         return v;
     }
-    v.lanes = 64;
     v.waves = 4;
+    v.per_cu = 2;
     v.hist = packed_ok(reff, levels, paper) ? OILPAINT_HIST_PACKED : OILPAINT_HIST_WIDE;
-    const DeviceInfo d = device_info(device);
-    const int cus = d.ok ? d.cus : 256;
-    // rows per lane: long runs amortise the (2r+1)^2 first window, short
-    // runs give more workgroups; aim for about two tiles per CU.
-    const long strips = (width + 63) / 64;
-    const long want = 2L * cus;
-    long rows = (strips * (long)height + want * v.waves - 1) / (want * v.waves);
-    const long cap = reff <= 2 ? 16 : reff <= 6 ? 32 : 64;
-    rows = std::max(8L, std::min(rows, cap));
-    v.rows = (int)rows;
-    if (v.hist == OILPAINT_HIST_WIDE) {
-        v.rows = std::min(v.rows, 16);
-    }
-    // shrink until the on-chip footprint fits
+    if (v.hist == OILPAINT_HIST_WIDE) v.rows = 16;
     Job j{};
     j.width = width;
     j.height = height;
@@ -170,18 +172,11 @@ oilpaint_variant default_variant(int width, int height, int reff, int levels, bo
     j.paper = paper ? 1 : 0;
     j.row_begin = 0;
     j.row_end = height;
-    const size_t limit = (d.ok ? d.lds_per_block : 65536) - kStaticLds;
     for (;;) {
-        j.rows = v.rows;
-        j.lanes = v.lanes;
-        j.hist = v.hist;
-        j.waves = v.waves;
-        set_layout(j);
-        if (lds_bytes(j) <= limit) break;
+        Job t = j;
+        if (apply_variant(t, v, device) == OILPAINT_OK) break;
         if (v.waves > 1)
             v.waves >>= 1;
-        else if (v.rows > 8)
-            v.rows >>= 1;
         else if (v.lanes > 16)
             v.lanes >>= 1;
         else
@@ -321,13 +316,79 @@ int oilpaint(const uint8_t* src, uint8_t* dst, int width, int height, int stride
     return OILPAINT_OK;
 }
 
+int oilpaint_tune(int width, int height, int radius, int levels, const oilpaint_variant* cands, int n, int reps,
+                  void* stream_, float* ms_out) {
+    if (!cands || !ms_out) return OILPAINT_ERR_NULL;
+    if (width < 1 || height < 1 || width > (1 << 16) || height > (1 << 16) || radius < 0 || radius > 65535 ||
+        levels < 1 || levels > 256 || n < 1 || reps < 1)
+        return OILPAINT_ERR_ARG;
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t bytes = (size_t)width * (size_t)height * 3;
+    uint8_t* src = nullptr;
+    uint8_t* dst = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st = OILPAINT_OK;
+    if (hipMalloc(&src, bytes) != hipSuccess || hipMalloc(&dst, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        st = OILPAINT_ERR_NOMEM;
+    }
+    if (st == OILPAINT_OK && (note_hip("hipEventCreate", hipEventCreate(&e0)) != hipSuccess ||
+                              note_hip("hipEventCreate", hipEventCreate(&e1)) != hipSuccess))
+        st = OILPAINT_ERR_HIP;
+    if (st == OILPAINT_OK && launch_fill(src, bytes, stream) != hipSuccess) st = OILPAINT_ERR_HIP;
+    for (int i = 0; st == OILPAINT_OK && i < n; ++i) {
+        ms_out[i] = -1.0f;
+        const int s0 = oilpaint_async_variant(src, dst, width, height, 3 * width, radius, levels, &cands[i], stream);
+        if (s0 == OILPAINT_ERR_UNSUPPORTED) continue;
+        if (s0 != OILPAINT_OK) {
+            st = s0;
+            break;
+        }
+        if (note_hip("hipEventRecord", hipEventRecord(e0, stream)) != hipSuccess) {
+            st = OILPAINT_ERR_HIP;
+            break;
+        }
+        for (int r = 0; r < reps && st == OILPAINT_OK; ++r)
+            st = oilpaint_async_variant(src, dst, width, height, 3 * width, radius, levels, &cands[i], stream);
+        if (st != OILPAINT_OK) break;
+        float ms = 0.0f;
+        if (note_hip("hipEventRecord", hipEventRecord(e1, stream)) != hipSuccess ||
+            note_hip("hipEventSynchronize", hipEventSynchronize(e1)) != hipSuccess ||
+            note_hip("hipEventElapsedTime", hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+            st = OILPAINT_ERR_HIP;
+            break;
+        }
+        ms_out[i] = ms / (float)reps;
+    }
+    if (stream) (void)hipStreamSynchronize(stream);
+    else (void)hipDeviceSynchronize();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (src) (void)hipFree(src);
+    if (dst) (void)hipFree(dst);
+    return st;
+}
+
 int oilpaint_pick_variant(int width, int height, int radius, int levels, oilpaint_variant* out) {
     if (!out) return OILPAINT_ERR_NULL;
     if (width < 0 || height < 0 || radius < 0 || radius > 65535 || levels < 1 || levels > 256)
         return OILPAINT_ERR_ARG;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) device = 0;
-    *out = choose_variant(width, height, effective_radius(width, height, radius), levels, false, device);
+    const int reff = effective_radius(width, height, radius);
+    oilpaint_variant v = choose_variant(width, height, reff, levels, false, device);
+    if (width > 0 && height > 0) {
+        // report the rows this image would get
+        Job j{};
+        j.width = width;
+        j.height = height;
+        j.radius = reff;
+        j.levels = levels;
+        j.row_begin = 0;
+        j.row_end = height;
+        if (apply_variant(j, v, device) == OILPAINT_OK) v.rows = j.rows;
+    }
+    *out = v;
     return OILPAINT_OK;
 }
 

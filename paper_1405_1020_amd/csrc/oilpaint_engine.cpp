@@ -29,9 +29,23 @@ constexpr int kBatchWaves = 1;
 // workgroup: the job's own choice with at most `waves` computing
 // wavefronts, shrunk (computing wavefronts, then rows, then lanes) until its
 // on-chip footprint fits.
-int batch_shape(Job& j, int waves, int device) {
+int batch_shape(Job& j, int waves, int device, int njobs) {
     oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
-    v.waves = std::min(std::max(v.waves, 1), waves);
+    if (v.waves > waves) {
+        // a shape wider than the batch workgroup: the streamed layout when it
+        // applies, else the same layout with fewer wavefronts
+        if (j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
+            v.hist = OILPAINT_HIST_STREAM;
+            v.lanes = 64;
+            v.rows = 0;
+            v.per_cu = 8;
+        }
+        v.waves = waves;
+    }
+    if (v.rows == 0) {
+        // the batch supplies the parallelism: longer runs per image
+        v.per_cu = std::max(1, (v.per_cu * 4 + njobs - 1) / std::max(njobs, 1));
+    }
     for (;;) {
         const int st = apply_variant(j, v, device);
         if (st == OILPAINT_OK) return st;
@@ -205,7 +219,7 @@ int collect_jobs(const oilpaint_desc* descs, int n, int device, std::vector<Job>
         Job j;
         bool empty = false;
         int st = make_job(descs[i], nullptr, device, j, empty);
-        if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, device);
+        if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, device, n);
         if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.src);
         if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.dst);
         if (st != OILPAINT_OK) {
@@ -467,7 +481,7 @@ int oilpaint_queue_push(oilpaint_queue* q, const oilpaint_desc* desc, uint64_t* 
     Job j;
     bool empty = false;
     int st = make_job(*desc, nullptr, q->device, j, empty);
-    if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, q->device);
+    if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, q->device, 4);
     if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.src);
     if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.dst);
     if (st != OILPAINT_OK) return st;

@@ -85,6 +85,7 @@ extern const PlainKernel kStream_hi[8][2];
 hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream);
 hipError_t launch_batch(const BatchArgs& a, int waves, size_t lds, int grid, hipStream_t stream);
 hipError_t launch_reset_counter(uint32_t* counter, hipStream_t stream);
+hipError_t launch_fill(uint8_t* p, size_t n, hipStream_t stream);
 
 // Record a failed HIP call (text readable through oilpaint_last_error) and
 // clear the runtime's sticky last-error state.  Returns `e`.

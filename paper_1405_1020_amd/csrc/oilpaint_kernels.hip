@@ -42,6 +42,17 @@ __global__ __launch_bounds__(64) void k_batch(BatchArgs a) {
     }
 }
 
+// Fixed pseudo-random bytes (a 32-bit integer hash of the index).
+__global__ void k_fill(uint8_t* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 2654435761u;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        p[i] = (uint8_t)h;
+    }
+}
+
 __global__ void k_reset(uint32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
@@ -102,6 +113,11 @@ hipError_t launch_batch(const BatchArgs& a, int waves, size_t lds, int grid, hip
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(64 * waves), lds, stream, a);
     return note_hip("k_batch launch", hipGetLastError());
+}
+
+hipError_t launch_fill(uint8_t* p, size_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, stream, p, n);
+    return note_hip("k_fill launch", hipGetLastError());
 }
 
 hipError_t launch_reset_counter(uint32_t* counter, hipStream_t stream) {

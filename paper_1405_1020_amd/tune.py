@@ -1,0 +1,124 @@
+"""Autotuner: the launch shape per (radius, levels).
+
+For each (radius, levels) the candidates -- streamed rows with several
+workgroup densities, tile-staged workgroups of 2 or 4 wavefronts with
+several densities -- are timed by the library itself (oilpaint_tune, HIP
+events around repeated launches on a representative image) and the fastest
+is installed with oilpaint_set_variant, so that oilpaint_async, batches and
+the request queue use it.  Shapes whose rows are derived from a workgroup
+density (rows = 0, per_cu) adapt to the image size they are used on.
+
+Results are cached as JSON, keyed by the GPU architecture and a hash of the
+kernel sources, in $OILPAINT_TUNE_CACHE or ~/.cache/oilpaint/tune.json.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+from . import binding as B
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def code_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def cache_path() -> str:
+    return os.environ.get("OILPAINT_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "oilpaint", "tune.json"))
+
+
+def candidates(radius: int, levels: int) -> list[B.Variant]:
+    out = []
+    if radius <= 15 and levels <= 64:
+        for per_cu in (2, 4, 8, 16, 32):
+            out.append(B.Variant(0, 1, B.HIST_STREAM, 64, per_cu))
+    if radius <= 15 and levels <= 255:
+        for waves in (2, 4):
+            for per_cu in (1, 2, 4, 8):
+                out.append(B.Variant(0, waves, B.HIST_PACKED, 64, per_cu))
+    if not out:
+        for per_cu in (1, 2, 4):
+            out.append(B.Variant(0, 2, B.HIST_WIDE, 64, per_cu))
+    return out
+
+
+def _key(radius: int, levels: int) -> str:
+    return "%d,%d" % (radius, levels)
+
+
+def _load_file() -> dict:
+    try:
+        d = json.load(open(cache_path()))
+    except (OSError, ValueError):
+        return {}
+    if d.get("arch") != arch() or d.get("code") != code_hash():
+        return {}
+    return d.get("entries", {})
+
+
+def _save_file(entries: dict):
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp%d" % os.getpid()
+        json.dump({"arch": arch(), "code": code_hash(), "entries": entries}, open(tmp, "w"), indent=1)
+        os.replace(tmp, p)
+    except OSError:
+        pass
+
+
+def install(entries: dict) -> int:
+    n = 0
+    for k, e in entries.items():
+        r, L = (int(v) for v in k.split(","))
+        if B.set_variant(r, L, B.Variant(*e["variant"])) == B.OK:
+            n += 1
+    return n
+
+
+def load() -> int:
+    """Install every cached result for this GPU and kernel source."""
+    return install(_load_file())
+
+
+def tune(radius: int, levels: int, width: int = 1920, height: int = 1080, reps: int = 5) -> dict:
+    """Time the candidates for (radius, levels) on a width x height image and
+    return {"variant": [...], "ms": best, "all": [(variant, ms), ...]}."""
+    cands = candidates(radius, levels)
+    times = B.tune_times(width, height, radius, levels, cands, reps=reps)
+    ok = [(c, t) for c, t in zip(cands, times) if t > 0]
+    if not ok:
+        raise B.OilpaintError(B.ERR_UNSUPPORTED, "no candidate runs (r=%d, L=%d)" % (radius, levels))
+    best, ms = min(ok, key=lambda ct: ct[1])
+    return {"variant": list(best.as_tuple()), "ms": ms, "size": [width, height],
+            "all": [(list(c.as_tuple()), t) for c, t in zip(cands, times)]}
+
+
+def ensure(pairs, width: int = 1920, height: int = 1080, reps: int = 5, retune: bool = False) -> dict:
+    """Make sure every (radius, levels) in `pairs` has a tuned shape
+    installed: taken from the cache, or tuned now and added to it."""
+    entries = {} if retune else _load_file()
+    changed = False
+    for r, L in pairs:
+        k = _key(r, L)
+        if k not in entries:
+            entries[k] = tune(r, L, width, height, reps)
+            changed = True
+    if changed:
+        _save_file(entries)
+    install({k: entries[k] for k in (_key(r, L) for r, L in pairs)})
+    return {k: entries[k] for k in (_key(r, L) for r, L in pairs)}
