@@ -195,30 +195,39 @@ int oilpaint_run(const oilpaint_desc *desc, void *stream);
 
 /* Validate all n descriptors (all or nothing: on error *bad_index, if not
  * NULL, receives the first failing index and nothing is enqueued), then
- * enqueue one persistent launch on `stream` that computes every image.
- * The descriptor array is copied; it may be reused when the call returns. */
+ * enqueue the persistent launch on `stream` that computes every image.  The
+ * images are grouped into kernel classes (streamed layout: one class per
+ * radius and level bucket; every other layout: one generic class); each
+ * class is one persistent kernel over its own flattened tile queue, sized
+ * by its own registers and LDS, and the classes run concurrently on up to
+ * four streams forked from and joined back into `stream`.  The descriptor
+ * array is copied; it may be reused when the call returns. */
 int oilpaint_batch(const oilpaint_desc *descs, int n, void *stream, int *bad_index);
 
-/* A batch plan: the descriptors are validated and laid out once (tile queue
+/* A batch plan: the descriptors are validated and laid out once (tile queues
  * in device memory, ordered by estimated cost) and the launch -- a counter
- * reset kernel plus the persistent kernel -- is captured in a hipGraph that
- * oilpaint_plan_launch replays.  Replays compute the same descriptors; the
+ * reset kernel, then the classes' persistent kernels as parallel graph
+ * branches -- is captured in a hipGraph that oilpaint_plan_launch replays.  Replays compute the same descriptors; the
  * caller may change the CONTENTS of the src images between replays. */
 typedef struct oilpaint_plan oilpaint_plan;
 int oilpaint_plan_create(const oilpaint_desc *descs, int n, void *stream, oilpaint_plan **out,
                          int *bad_index);
 int oilpaint_plan_launch(oilpaint_plan *plan, void *stream);
-/* Number of tiles and of workgroups of the persistent launch. */
+/* Number of tiles and of workgroups over all classes' persistent kernels. */
 int oilpaint_plan_info(const oilpaint_plan *plan, int *tiles, int *workgroups);
 int oilpaint_plan_destroy(oilpaint_plan *plan);
 
 /* ---------------------------------------------------------------------------
  * Continuous batching.  A queue accepts filter requests at any time; each
- * oilpaint_queue_step (also run by push and poll) packs the work that is
- * waiting -- new requests and the unfinished rows of running ones -- into
- * one persistent launch of at most `step_pixels` output pixels, keeping at
- * most two launches in flight on the queue's stream, so that requests that
- * arrive while others are on the GPU share the next launch with them.
+ * oilpaint_queue_step (also run by push, poll and completed) packs the work
+ * that is waiting -- new requests and the unfinished rows of running ones,
+ * an equal share of the launch's pixels each, in whole tile rows -- into one
+ * batch launch, keeping at most four launches in flight on the queue's
+ * stream, so that requests that arrive while others are on the GPU share
+ * the next launch with them.  A launch covers `step_pixels` output pixels,
+ * or a quarter of the waiting pixels when that is more (at most 16 x
+ * step_pixels).  A lone request with nothing in flight is launched whole
+ * with the plain kernel and its own launch shape.
  * ------------------------------------------------------------------------- */
 typedef struct oilpaint_queue oilpaint_queue;
 
@@ -236,6 +245,11 @@ int oilpaint_queue_step(oilpaint_queue *q);
  * to later work on any stream), 0 if not yet, ERR_ARG for an unknown ticket.
  * Once poll has returned 1 for a ticket the queue forgets it. */
 int oilpaint_queue_poll(oilpaint_queue *q, uint64_t ticket);
+/* Tickets of requests completed since they were last reported (by poll or
+ * by this call), in completion order: at most `max` are written to
+ * `tickets`, and those are forgotten.  Returns the number written, or an
+ * error code.  One call replaces a poll per request. */
+int oilpaint_queue_completed(oilpaint_queue *q, uint64_t *tickets, int max);
 /* Block until every pushed request is complete. */
 int oilpaint_queue_drain(oilpaint_queue *q);
 /* The queue's stream (hipStream_t as void*). */

@@ -94,6 +94,7 @@ _SIGS = {
                             ctypes.c_int),
     "oilpaint_queue_step": ([ctypes.c_void_p], ctypes.c_int),
     "oilpaint_queue_poll": ([ctypes.c_void_p, ctypes.c_uint64], ctypes.c_int),
+    "oilpaint_queue_completed": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int], ctypes.c_int),
     "oilpaint_queue_drain": ([ctypes.c_void_p], ctypes.c_int),
     "oilpaint_queue_stream": ([ctypes.c_void_p], ctypes.c_void_p),
     "oilpaint_queue_destroy": ([ctypes.c_void_p], ctypes.c_int),
@@ -356,6 +357,15 @@ class Queue:
         if st < 0:
             raise OilpaintError(st, "oilpaint_queue_poll")
         return st == 1
+
+    def completed(self, max_tickets: int = 4096) -> list[int]:
+        """Tickets completed since last reported (each reported once)."""
+        if getattr(self, "_buf", None) is None or len(self._buf) < max_tickets:
+            self._buf = (ctypes.c_uint64 * max_tickets)()
+        n = lib().oilpaint_queue_completed(self._h, self._buf, max_tickets)
+        if n < 0:
+            raise OilpaintError(n, "oilpaint_queue_completed")
+        return list(self._buf[:n])
 
     def drain(self):
         _check(lib().oilpaint_queue_drain(self._h), "oilpaint_queue_drain")

@@ -717,34 +717,40 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
     }
 }
 
-// Batch form: the streamed, generic packed and wide layouts in one kernel,
-// selected per tile (a batch job of the tile-staged fast layout runs as
-// generic packed).
-__device__ __forceinline__ void run_tile(const Job& j, int tile, uint8_t* lds) {
-    if (j.hist == OILPAINT_HIST_WIDE) {
-        tile_wide(j, tile, lds);
-        return;
+// Persistent batch kernels: the next tile of a class's queue, taken by the
+// workgroup's first lane (one wavefront per workgroup) and broadcast.  The
+// compiler barrier keeps the previous tile's LDS accesses before it; one
+// wavefront's LDS operations execute in issue order.
+__device__ __forceinline__ int32_t next_tile_wave(uint32_t* counter) {
+    lds_order();
+    uint32_t t = 0;
+    if ((threadIdx.x & 63) == 0) t = atomicAdd(counter, 1u);
+    return (int32_t)__builtin_amdgcn_readfirstlane(t);
+}
+
+// Job holding queue index t (uniform): the last i with first_tile[i] <= t.
+__device__ __forceinline__ int job_of(const BatchArgs& a, int32_t t) {
+    int lo = 0, hi = a.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.first_tile[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
-    if (j.hist == OILPAINT_HIST_STREAM) {
-        const bool small = j.scan <= 32;
-        switch (j.radius) {
-#define OILPAINT_STREAM_CASE(R)               \
-    case R:                                   \
-        if (small)                            \
-            tile_stream<R, 32>(j, tile, lds); \
-        else                                  \
-            tile_stream<R, 64>(j, tile, lds); \
-        return;
-            OILPAINT_STREAM_CASE(0) OILPAINT_STREAM_CASE(1) OILPAINT_STREAM_CASE(2) OILPAINT_STREAM_CASE(3)
-            OILPAINT_STREAM_CASE(4) OILPAINT_STREAM_CASE(5) OILPAINT_STREAM_CASE(6) OILPAINT_STREAM_CASE(7)
-            OILPAINT_STREAM_CASE(8) OILPAINT_STREAM_CASE(9) OILPAINT_STREAM_CASE(10) OILPAINT_STREAM_CASE(11)
-            OILPAINT_STREAM_CASE(12) OILPAINT_STREAM_CASE(13) OILPAINT_STREAM_CASE(14) OILPAINT_STREAM_CASE(15)
-#undef OILPAINT_STREAM_CASE
-            default: break;
-        }
-        return;
+    return lo;
+}
+
+// One class of a batch in the streamed layout (radius R, scan bucket SB).
+template <int R, int SB>
+__device__ __forceinline__ void batch_stream(const BatchArgs& a, uint8_t* lds) {
+    for (;;) {
+        const int32_t t = next_tile_wave(a.counter);
+        if (t >= a.ntiles) break;
+        const int i = job_of(a, t);
+        const Job jb = a.jobs[i];
+        tile_stream<R, SB>(jb, t - a.first_tile[i], lds);
     }
-    tile_packed(j, tile, lds);
 }
 
 }  // namespace dev

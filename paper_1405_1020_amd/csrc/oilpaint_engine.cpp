@@ -28,7 +28,10 @@ constexpr int kBatchWaves = 1;
 // Launch shape of a job inside a persistent launch of `waves` wavefronts per
 // workgroup: the job's own choice with at most `waves` computing
 // wavefronts, shrunk (computing wavefronts, then rows, then lanes) until its
-// on-chip footprint fits.
+// on-chip footprint fits.  Runs are at least about 5(2r+1) rows (or the
+// whole band): the batch, not the single image, supplies the parallelism,
+// and the (2r+1)^2 first window of a run then costs at most ~10 % of its
+// sliding updates.
 int batch_shape(Job& j, int waves, int device, int njobs) {
     oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
     if (v.waves > waves) {
@@ -48,7 +51,7 @@ int batch_shape(Job& j, int waves, int device, int njobs) {
     }
     for (;;) {
         const int st = apply_variant(j, v, device);
-        if (st == OILPAINT_OK) return st;
+        if (st == OILPAINT_OK) break;
         if (v.waves > 1)
             v.waves >>= 1;
         else if (v.rows > 8)
@@ -58,6 +61,15 @@ int batch_shape(Job& j, int waves, int device, int njobs) {
         else
             return st;
     }
+    const int band = j.row_end - j.row_begin;
+    const int min_rows = std::min(std::min(band, 5 * (2 * j.radius + 1)), 1024);
+    if (j.rows * j.waves < min_rows) {
+        Job t = j;
+        oilpaint_variant w = v;
+        w.rows = (min_rows + w.waves - 1) / w.waves;
+        if (apply_variant(t, w, device) == OILPAINT_OK) j = t;
+    }
+    return OILPAINT_OK;
 }
 
 // Relative cost of one tile: window updates plus the mode search per output
@@ -68,53 +80,169 @@ double tile_cost(const Job& j) {
     return px * (2.0 * span + j.levels * 0.5 + 4.0) + (double)j.lanes * j.waves * span * span;
 }
 
-struct Layout {
+// One kernel class of a batch (batch_class): its jobs in queue order and
+// its flattened tile queue.
+struct ClassLayout {
+    int cls = kGenericClass;
     std::vector<Job> jobs;        // queue order
     std::vector<int32_t> first;   // njobs + 1
     size_t lds = 0;
     int ntiles = 0;
+    double cost = 0;              // total tile cost
+    size_t first_off = 0, jobs_off = 0;  // offsets in the argument block
 };
 
-// Order jobs by tile cost (costliest first, so the long tiles start early
-// and the cheap ones fill the tail) and lay out the flattened tile queue.
-void build_layout(std::vector<Job>& jobs, Layout& out) {
-    std::stable_sort(jobs.begin(), jobs.end(),
-                     [&](const Job& a, const Job& b) { return tile_cost(a) > tile_cost(b); });
-    out.jobs = jobs;
-    out.first.assign(jobs.size() + 1, 0);
-    long total = 0;
-    size_t lds = 0;
-    for (size_t i = 0; i < jobs.size(); ++i) {
-        out.first[i] = (int32_t)total;
-        total += (long)jobs[i].tiles_x * jobs[i].tiles_y;
-        lds = std::max(lds, lds_bytes(jobs[i]));
-    }
-    out.first[jobs.size()] = (int32_t)total;
-    out.ntiles = (int)total;
-    out.lds = lds;
-}
+// Argument block: [counters, one per class, kCounterWords apart][first_tile
+// arrays][job arrays].
+constexpr int kCounterWords = 32;  // 128 bytes: one counter per cache line
+constexpr int kMaxBranches = 4;    // classes run on at most this many streams
 
-// Bytes of the device argument block: counter, first_tile[], jobs[].
-size_t args_bytes(size_t njobs) {
-    return 256 + ((sizeof(int32_t) * (njobs + 1) + 255) & ~(size_t)255) + sizeof(Job) * njobs;
+struct Layout {
+    std::vector<ClassLayout> classes;  // costliest first
+    size_t bytes = 0;
+    int ntiles = 0;
+};
+
+// Group jobs by kernel class, order each class's jobs by tile cost
+// (costliest first, so that long tiles start early and cheap ones fill the
+// tail) and lay out the argument block.
+void build_layout(const std::vector<Job>& jobs, Layout& out) {
+    std::map<int, ClassLayout> by;
+    for (const Job& j : jobs) {
+        ClassLayout& c = by[batch_class(j)];
+        c.cls = batch_class(j);
+        c.jobs.push_back(j);
+    }
+    out = Layout();
+    for (auto& kv : by) out.classes.push_back(std::move(kv.second));
+    for (ClassLayout& c : out.classes) {
+        std::stable_sort(c.jobs.begin(), c.jobs.end(),
+                         [&](const Job& a, const Job& b) { return tile_cost(a) > tile_cost(b); });
+        c.first.assign(c.jobs.size() + 1, 0);
+        long total = 0;
+        for (size_t i = 0; i < c.jobs.size(); ++i) {
+            const long t = (long)c.jobs[i].tiles_x * c.jobs[i].tiles_y;
+            c.first[i] = (int32_t)total;
+            total += t;
+            c.lds = std::max(c.lds, lds_bytes(c.jobs[i]));
+            c.cost += tile_cost(c.jobs[i]) * (double)t;
+        }
+        c.first[c.jobs.size()] = (int32_t)total;
+        c.ntiles = (int)total;
+        out.ntiles += c.ntiles;
+    }
+    std::stable_sort(out.classes.begin(), out.classes.end(),
+                     [](const ClassLayout& a, const ClassLayout& b) { return a.cost > b.cost; });
+    size_t off = ((size_t)kCounterWords * 4 * out.classes.size() + 255) & ~(size_t)255;
+    for (ClassLayout& c : out.classes) {
+        c.first_off = off;
+        off += (sizeof(int32_t) * c.first.size() + 15) & ~(size_t)15;
+    }
+    off = (off + 255) & ~(size_t)255;
+    for (ClassLayout& c : out.classes) {
+        c.jobs_off = off;
+        off += sizeof(Job) * c.jobs.size();
+    }
+    out.bytes = off;
 }
 
 void pack_args(const Layout& L, uint8_t* host) {
-    std::memset(host, 0, 256);
-    const size_t fbytes = (sizeof(int32_t) * (L.jobs.size() + 1) + 255) & ~(size_t)255;
-    std::memcpy(host + 256, L.first.data(), sizeof(int32_t) * L.first.size());
-    std::memcpy(host + 256 + fbytes, L.jobs.data(), sizeof(Job) * L.jobs.size());
+    std::memset(host, 0, L.bytes);
+    for (const ClassLayout& c : L.classes) {
+        std::memcpy(host + c.first_off, c.first.data(), sizeof(int32_t) * c.first.size());
+        std::memcpy(host + c.jobs_off, c.jobs.data(), sizeof(Job) * c.jobs.size());
+    }
 }
 
-BatchArgs args_at(const Layout& L, uint8_t* dev) {
-    const size_t fbytes = (sizeof(int32_t) * (L.jobs.size() + 1) + 255) & ~(size_t)255;
+BatchArgs class_args(const Layout& L, size_t k, uint8_t* dev) {
+    const ClassLayout& c = L.classes[k];
     BatchArgs a;
-    a.counter = reinterpret_cast<uint32_t*>(dev);
-    a.first_tile = reinterpret_cast<const int32_t*>(dev + 256);
-    a.jobs = reinterpret_cast<const Job*>(dev + 256 + fbytes);
-    a.njobs = (int32_t)L.jobs.size();
-    a.ntiles = L.ntiles;
+    a.counter = reinterpret_cast<uint32_t*>(dev) + k * kCounterWords;
+    a.first_tile = reinterpret_cast<const int32_t*>(dev + c.first_off);
+    a.jobs = reinterpret_cast<const Job*>(dev + c.jobs_off);
+    a.njobs = (int32_t)c.jobs.size();
+    a.ntiles = c.ntiles;
     return a;
+}
+
+// Side streams and events that spread a batch's classes over concurrent
+// branches.  Branch 0 is the caller's stream; branch b > 0 runs on side[b-1],
+// which waits for the caller's stream at the fork and is waited for by it at
+// the join.  Inside a stream capture the branches become parallel graph
+// branches.
+struct Branches {
+    hipStream_t side[kMaxBranches - 1] = {};
+    hipEvent_t join[kMaxBranches - 1] = {};
+    hipEvent_t fork = nullptr;
+    int made = 0;
+
+    Branches() = default;
+    Branches(const Branches&) = delete;
+    Branches& operator=(const Branches&) = delete;
+    ~Branches() {
+        for (int b = 0; b < made; ++b) {
+            (void)hipStreamSynchronize(side[b]);
+            (void)hipStreamDestroy(side[b]);
+            (void)hipEventDestroy(join[b]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+    }
+    // Make sure branches 0 .. n-1 exist.
+    bool ensure(int n) {
+        if (!fork && hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return false;
+        while (made < n - 1) {
+            if (hipStreamCreateWithFlags(&side[made], hipStreamNonBlocking) != hipSuccess) return false;
+            if (hipEventCreateWithFlags(&join[made], hipEventDisableTiming) != hipSuccess) {
+                (void)hipStreamDestroy(side[made]);
+                return false;
+            }
+            ++made;
+        }
+        return true;
+    }
+};
+
+// Enqueue the counter reset and every class's persistent kernel, the
+// classes spread over branches by total cost (each to the least loaded).
+// Returns the number of workgroups launched in `workgroups`.
+int enqueue_classes(const Layout& L, uint8_t* dev, int device, Branches& br, hipStream_t stream,
+                    int* workgroups) {
+    const int nc = (int)L.classes.size();
+    if (workgroups) *workgroups = 0;
+    if (L.ntiles == 0) return OILPAINT_OK;
+    if (launch_reset_counters(reinterpret_cast<uint32_t*>(dev), nc, kCounterWords, stream) != hipSuccess)
+        return OILPAINT_ERR_HIP;
+    const int nb = std::min(nc, kMaxBranches);
+    if (!br.ensure(nb)) {
+        (void)note_hip("branch streams", hipGetLastError());
+        return OILPAINT_ERR_HIP;
+    }
+    if (nb > 1) {
+        if (note_hip("hipEventRecord", hipEventRecord(br.fork, stream)) != hipSuccess) return OILPAINT_ERR_HIP;
+        for (int b = 1; b < nb; ++b)
+            if (note_hip("hipStreamWaitEvent", hipStreamWaitEvent(br.side[b - 1], br.fork, 0)) != hipSuccess)
+                return OILPAINT_ERR_HIP;
+    }
+    double load[kMaxBranches] = {};
+    int total = 0;
+    for (int k = 0; k < nc; ++k) {
+        const ClassLayout& c = L.classes[k];
+        if (c.ntiles == 0) continue;
+        const int b = (int)(std::min_element(load, load + nb) - load);
+        load[b] += c.cost;
+        const int grid = std::min(batch_grid(device, c.cls, kBatchWaves, c.lds), c.ntiles);
+        const hipStream_t s = b == 0 ? stream : br.side[b - 1];
+        if (launch_batch(class_args(L, (size_t)k, dev), c.cls, kBatchWaves, c.lds, grid, s) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+        total += grid;
+    }
+    for (int b = 1; b < nb; ++b) {
+        if (note_hip("hipEventRecord", hipEventRecord(br.join[b - 1], br.side[b - 1])) != hipSuccess ||
+            note_hip("hipStreamWaitEvent", hipStreamWaitEvent(stream, br.join[b - 1], 0)) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+    }
+    if (workgroups) *workgroups = total;
+    return OILPAINT_OK;
 }
 
 // A small ring of (pinned host, device) argument buffers.  A slot is reused
@@ -173,20 +301,17 @@ class ArgRing {
     size_t next_ = 0;
 };
 
-// Upload `L` through `ring` and enqueue reset + persistent kernel.
-int enqueue_layout(const Layout& L, int waves, int device, ArgRing& ring, hipStream_t stream) {
+// Upload `L` through `ring` and enqueue its classes.
+int enqueue_layout(const Layout& L, int device, ArgRing& ring, Branches& br, hipStream_t stream) {
     if (L.ntiles == 0) return OILPAINT_OK;
-    const size_t bytes = args_bytes(L.jobs.size());
-    ArgSlot* s = ring.acquire(bytes);
+    ArgSlot* s = ring.acquire(L.bytes);
     if (!s) return OILPAINT_ERR_NOMEM;
     pack_args(L, s->host);
-    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(s->dev, s->host, bytes, hipMemcpyHostToDevice, stream)) !=
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(s->dev, s->host, L.bytes, hipMemcpyHostToDevice, stream)) !=
         hipSuccess)
         return OILPAINT_ERR_HIP;
-    const BatchArgs a = args_at(L, s->dev);
-    const int grid = std::min(batch_grid(device, waves, L.lds), L.ntiles);
-    if (launch_reset_counter(a.counter, stream) != hipSuccess) return OILPAINT_ERR_HIP;
-    if (launch_batch(a, waves, L.lds, grid, stream) != hipSuccess) return OILPAINT_ERR_HIP;
+    const int st = enqueue_classes(L, s->dev, device, br, stream, nullptr);
+    if (st != OILPAINT_OK) return st;
     ring.release(s, stream);
     return OILPAINT_OK;
 }
@@ -197,6 +322,15 @@ ArgRing& device_ring(int device) {
     std::lock_guard<std::mutex> lock(mu);
     auto& p = rings[device];
     if (!p) p.reset(new ArgRing(8));
+    return *p;
+}
+
+Branches& device_branches(int device) {
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<Branches>> m;
+    std::lock_guard<std::mutex> lock(mu);
+    auto& p = m[device];
+    if (!p) p.reset(new Branches);
     return *p;
 }
 
@@ -246,15 +380,18 @@ struct oilpaint_plan {
     uint8_t* dev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int grid = 0;
+    int grid = 0;  // workgroups over all classes
 };
 
 // ---------------------------------------------------------------------------
 // Queue
 // ---------------------------------------------------------------------------
+constexpr int kQueueDepth = 4;  // launches in flight on a queue's stream
+
 struct QueueReq {
-    Job job;          // whole request (row_begin .. row_end)
-    int next_row;     // first output row not yet launched
+    Job job;              // whole request (row_begin .. row_end), batch shape
+    oilpaint_desc desc;   // as pushed: a lone request runs as a plain launch
+    int next_row;         // first output row not yet launched
     int launches_left = 0;
     bool all_launched = false;
     bool done = false;
@@ -276,7 +413,10 @@ struct oilpaint_queue {
     std::deque<Inflight> inflight;
     std::vector<hipEvent_t> free_events;
     std::unique_ptr<ArgRing> ring;
-    size_t held = 0;  // requests not yet reported complete
+    std::unique_ptr<Branches> branches;
+    std::deque<uint64_t> finished;  // completed, in completion order (may hold
+                                    // tickets already reported by poll)
+    size_t held = 0;  // requests not yet complete
 };
 
 namespace {
@@ -301,6 +441,7 @@ void retire(oilpaint_queue* q, bool block) {
             if (--r.launches_left == 0 && r.all_launched && !r.done) {
                 r.done = true;
                 --q->held;
+                q->finished.push_back(t);
             }
         }
         q->free_events.push_back(f.ev);
@@ -310,14 +451,25 @@ void retire(oilpaint_queue* q, bool block) {
 }
 
 // Pack waiting work into one launch.  Every waiting request gets an equal
-// share of the pixel budget (at least one tile row of its own shape), so a
-// small request that arrives behind a large one finishes in the next launch
-// instead of waiting for the large one to drain.
+// share of the launch's pixels (at least one tile row of its own shape), so
+// a small request that arrives behind a large one finishes in the next
+// launch instead of waiting for the large one to drain.  The launch covers
+// step_pixels, or a quarter of the waiting pixels when the backlog is larger
+// (at most 16 x step_pixels), so that a backlog keeps enough work in flight;
+// a lone request with nothing in flight runs whole.  A launch of a single
+// band uses the plain kernel with the request's own launch shape.
 int launch_step(oilpaint_queue* q) {
     if (q->waiting.empty()) return 0;
+    int64_t waiting_px = 0;
+    for (uint64_t t : q->waiting) {
+        const QueueReq& r = q->reqs[t];
+        waiting_px += (int64_t)(r.job.row_end - r.next_row) * r.job.width;
+    }
+    const bool lone = q->waiting.size() == 1 && q->inflight.empty();
+    int64_t budget = lone ? waiting_px
+                          : std::max(q->step_pixels, std::min(16 * q->step_pixels, waiting_px / 4));
     std::vector<Job> jobs;
     std::vector<uint64_t> tickets;
-    int64_t budget = q->step_pixels;
     const int64_t share = std::max<int64_t>(1, budget / (int64_t)q->waiting.size());
     std::deque<uint64_t> still;
     for (uint64_t t : q->waiting) {
@@ -350,9 +502,21 @@ int launch_step(oilpaint_queue* q) {
     }
     q->waiting.swap(still);
     if (jobs.empty()) return 0;
-    Layout L;
-    build_layout(jobs, L);
-    int st = enqueue_layout(L, kBatchWaves, q->device, *q->ring, q->stream);
+    int st = OILPAINT_OK;
+    if (jobs.size() == 1) {
+        oilpaint_desc d = q->reqs[tickets[0]].desc;
+        d.row_begin = jobs[0].row_begin;
+        d.row_end = jobs[0].row_end;
+        Job pj;
+        bool empty = false;
+        st = make_job(d, nullptr, q->device, pj, empty);
+        if (st == OILPAINT_OK && !empty && launch_plain(pj, pj.waves, lds_bytes(pj), q->stream) != hipSuccess)
+            st = OILPAINT_ERR_HIP;
+    } else {
+        Layout L;
+        build_layout(jobs, L);
+        st = enqueue_layout(L, q->device, *q->ring, *q->branches, q->stream);
+    }
     if (st != OILPAINT_OK) return st;
     hipEvent_t ev;
     if (!q->free_events.empty()) {
@@ -372,7 +536,7 @@ int launch_step(oilpaint_queue* q) {
 int queue_progress(oilpaint_queue* q) {
     retire(q, false);
     int launched = 0;
-    while (q->inflight.size() < 2 && !q->waiting.empty()) {
+    while (q->inflight.size() < (size_t)kQueueDepth && !q->waiting.empty()) {
         const int st = launch_step(q);
         if (st < 0) return st;
         if (st == 0) break;
@@ -394,7 +558,7 @@ int oilpaint_batch(const oilpaint_desc* descs, int n, void* stream, int* bad_ind
     Layout L;
     build_layout(jobs, L);
     std::lock_guard<std::mutex> lock(ring_mutex(device));
-    return enqueue_layout(L, kBatchWaves, device, device_ring(device), (hipStream_t)stream);
+    return enqueue_layout(L, device, device_ring(device), device_branches(device), (hipStream_t)stream);
 }
 
 int oilpaint_plan_create(const oilpaint_desc* descs, int n, void* stream, oilpaint_plan** out, int* bad_index) {
@@ -408,22 +572,23 @@ int oilpaint_plan_create(const oilpaint_desc* descs, int n, void* stream, oilpai
     std::unique_ptr<oilpaint_plan> p(new oilpaint_plan);
     p->device = device;
     build_layout(jobs, p->layout);
-    const size_t bytes = args_bytes(p->layout.jobs.size());
+    const size_t bytes = std::max<size_t>(p->layout.bytes, 256);
     if (hipMalloc(&p->dev, bytes) != hipSuccess) return OILPAINT_ERR_NOMEM;
     std::vector<uint8_t> host(bytes);
     pack_args(p->layout, host.data());
-    if (hipMemcpy(p->dev, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return OILPAINT_ERR_HIP;
-    p->grid = std::min(batch_grid(device, kBatchWaves, p->layout.lds), std::max(p->layout.ntiles, 1));
+    if (hipMemcpy(p->dev, host.data(), p->layout.bytes, hipMemcpyHostToDevice) != hipSuccess) return OILPAINT_ERR_HIP;
     if (p->layout.ntiles > 0) {
         hipStream_t cap;
         if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return OILPAINT_ERR_HIP;
-        const BatchArgs a = args_at(p->layout, p->dev);
-        bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        // the counter is cleared by a kernel, not a memset node
-        ok = ok && launch_reset_counter(a.counter, cap) == hipSuccess;
-        ok = ok && launch_batch(a, kBatchWaves, p->layout.lds, p->grid, cap) == hipSuccess;
         hipGraph_t g = nullptr;
-        const bool ended = hipStreamEndCapture(cap, &g) == hipSuccess;
+        bool ok = false, ended = false;
+        {
+            Branches br;
+            ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            // counters are cleared by a kernel, not a memset node
+            ok = ok && enqueue_classes(p->layout, p->dev, device, br, cap, &p->grid) == OILPAINT_OK;
+            ended = hipStreamEndCapture(cap, &g) == hipSuccess;
+        }
         (void)hipStreamDestroy(cap);
         if (!ok || !ended || !g) {
             if (g) (void)hipGraphDestroy(g);
@@ -469,7 +634,8 @@ int oilpaint_queue_create(int capacity, int64_t step_pixels, oilpaint_queue** ou
     if (hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking) != hipSuccess) return OILPAINT_ERR_HIP;
     q->capacity = capacity;
     q->step_pixels = step_pixels > 0 ? step_pixels : (int64_t)8 << 20;
-    q->ring.reset(new ArgRing(4));
+    q->ring.reset(new ArgRing(kQueueDepth + 2));
+    q->branches.reset(new Branches);
     *out = q.release();
     return OILPAINT_OK;
 }
@@ -488,6 +654,7 @@ int oilpaint_queue_push(oilpaint_queue* q, const oilpaint_desc* desc, uint64_t* 
     const uint64_t t = q->next_ticket++;
     QueueReq r;
     r.job = j;
+    r.desc = *desc;
     r.next_row = j.row_begin;
     r.all_launched = empty;
     r.done = empty;
@@ -495,6 +662,8 @@ int oilpaint_queue_push(oilpaint_queue* q, const oilpaint_desc* desc, uint64_t* 
     if (!empty) {
         q->waiting.push_back(t);
         ++q->held;
+    } else {
+        q->finished.push_back(t);
     }
     *ticket = t;
     st = queue_progress(q);
@@ -517,7 +686,30 @@ int oilpaint_queue_poll(oilpaint_queue* q, uint64_t ticket) {
     }
     // reported complete: the ticket is forgotten
     q->reqs.erase(it);
+    if (q->finished.size() > 2 * (size_t)q->capacity + 1024) {
+        std::deque<uint64_t> keep;
+        for (uint64_t t : q->finished)
+            if (q->reqs.count(t)) keep.push_back(t);
+        q->finished.swap(keep);
+    }
     return 1;
+}
+
+int oilpaint_queue_completed(oilpaint_queue* q, uint64_t* tickets, int max) {
+    if (!q || (!tickets && max > 0)) return OILPAINT_ERR_NULL;
+    if (max < 0) return OILPAINT_ERR_ARG;
+    const int st = queue_progress(q);
+    if (st < 0) return st;
+    int n = 0;
+    while (n < max && !q->finished.empty()) {
+        const uint64_t t = q->finished.front();
+        q->finished.pop_front();
+        auto it = q->reqs.find(t);
+        if (it == q->reqs.end()) continue;  // already reported by poll
+        tickets[n++] = t;
+        q->reqs.erase(it);
+    }
+    return n;
 }
 
 int oilpaint_queue_drain(oilpaint_queue* q) {
@@ -538,6 +730,7 @@ int oilpaint_queue_destroy(oilpaint_queue* q) {
     for (auto& f : q->inflight) (void)hipEventDestroy(f.ev);
     for (auto e : q->free_events) (void)hipEventDestroy(e);
     q->ring.reset();
+    q->branches.reset();
     (void)hipStreamDestroy(q->stream);
     delete q;
     return OILPAINT_OK;

@@ -81,10 +81,30 @@ extern const PlainKernel kFast_hi[8][3];
 extern const PlainKernel kStream_lo[8][2];
 extern const PlainKernel kStream_hi[8][2];
 
+// Persistent batch kernels of the streamed layout (oilpaint_k_batch_*.hip),
+// indexed like kStream_*.
+typedef void (*BatchKernel)(BatchArgs);
+extern const BatchKernel kBatchStream_lo[8][2];
+extern const BatchKernel kBatchStream_hi[8][2];
+
+// Kernel class of a batch job: 2 * radius + scan bucket (0: scan <= 32,
+// 1: scan <= 64) for the streamed layout, kGenericClass for every other
+// job (generic tile-staged and wide layouts, one kernel for all).  A batch
+// launches one persistent kernel per class present.
+constexpr int kGenericClass = 2 * (kPackedMaxRadius + 1);
+constexpr int kBatchClasses = kGenericClass + 1;
+inline int batch_class(const Job& j) {
+    if (j.hist == OILPAINT_HIST_STREAM && j.radius >= 0 && j.radius <= kPackedMaxRadius && j.scan <= 64)
+        return 2 * j.radius + (j.scan <= 32 ? 0 : 1);
+    return kGenericClass;
+}
+
 // Kernel launches (oilpaint_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream);
-hipError_t launch_batch(const BatchArgs& a, int waves, size_t lds, int grid, hipStream_t stream);
-hipError_t launch_reset_counter(uint32_t* counter, hipStream_t stream);
+hipError_t launch_batch(const BatchArgs& a, int cls, int waves, size_t lds, int grid, hipStream_t stream);
+// Clear n counters, stride_words apart (a kernel, so that a captured graph
+// holds no memset node).
+hipError_t launch_reset_counters(uint32_t* counters, int n, int stride_words, hipStream_t stream);
 hipError_t launch_fill(uint8_t* p, size_t n, hipStream_t stream);
 
 // Record a failed HIP call (text readable through oilpaint_last_error) and
@@ -99,7 +119,8 @@ struct DeviceInfo {
 };
 DeviceInfo device_info(int device);
 
-// Most workgroups of the persistent kernel that can be resident at once.
-int batch_grid(int device, int waves, size_t lds);
+// Most workgroups of class `cls`'s persistent kernel that can be resident at
+// once.
+int batch_grid(int device, int cls, int waves, size_t lds);
 
 }  // namespace oilpaint_impl

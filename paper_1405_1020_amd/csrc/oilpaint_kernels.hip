@@ -17,8 +17,9 @@ __global__ __launch_bounds__(512) void k_plain(Job j) {
         tile_packed(j, blockIdx.x, lds);
 }
 
-// Persistent: workgroups pull tiles from a counter until the queue is empty.
-// One wavefront per workgroup: every job in a batch runs with waves = 1.
+// Persistent, the generic class of a batch (tile-staged and wide layouts):
+// workgroups pull tiles from a counter until the queue is empty.  The
+// streamed classes have kernels of their own (oilpaint_k_batch_*.hip).
 __global__ __launch_bounds__(64) void k_batch(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int32_t s_tile;
@@ -28,17 +29,12 @@ __global__ __launch_bounds__(64) void k_batch(BatchArgs a) {
         __syncthreads();
         const int32_t t = __builtin_amdgcn_readfirstlane(s_tile);
         if (t >= a.ntiles) break;
-        // job holding queue index t: last i with first_tile[i] <= t
-        int lo = 0, hi = a.njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.first_tile[mid] <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const Job jb = a.jobs[lo];
-        run_tile(jb, t - a.first_tile[lo], lds);
+        const int i = job_of(a, t);
+        const Job jb = a.jobs[i];
+        if (jb.hist == OILPAINT_HIST_WIDE)
+            tile_wide(jb, t - a.first_tile[i], lds);
+        else
+            tile_packed(jb, t - a.first_tile[i], lds);
     }
 }
 
@@ -53,8 +49,8 @@ __global__ void k_fill(uint8_t* p, size_t n) {
     }
 }
 
-__global__ void k_reset(uint32_t* counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+__global__ void k_reset(uint32_t* counters, int n, int stride_words) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counters[(size_t)i * stride_words] = 0u;
 }
 
 
@@ -83,6 +79,13 @@ namespace {
 int g_fast_lds_done[kPackedMaxRadius + 1][3];
 int g_stream_lds_done[kPackedMaxRadius + 1][2];
 int g_plain_lds_done;
+int g_batch_lds_done[kBatchClasses];
+
+BatchKernel batch_kernel(int cls) {
+    if (cls < 0 || cls >= kGenericClass) return k_batch;
+    const int r = cls >> 1, b = cls & 1;
+    return r <= 7 ? kBatchStream_lo[r][b] : kBatchStream_hi[r - 8][b];
+}
 }  // namespace
 
 hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream) {
@@ -106,13 +109,14 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
     return note_hip("k_plain launch", hipGetLastError());
 }
 
-hipError_t launch_batch(const BatchArgs& a, int waves, size_t lds, int grid, hipStream_t stream) {
-    static int lds_done = 0;
+hipError_t launch_batch(const BatchArgs& a, int cls, int waves, size_t lds, int grid, hipStream_t stream) {
     if (a.ntiles <= 0) return hipSuccess;
-    const hipError_t e = allow_lds(reinterpret_cast<const void*>(k_batch), lds, lds_done);
+    if (cls < 0 || cls >= kBatchClasses || (cls < kGenericClass && waves != 1)) return hipErrorInvalidValue;
+    const BatchKernel k = batch_kernel(cls);
+    const hipError_t e = allow_lds(reinterpret_cast<const void*>(k), lds, g_batch_lds_done[cls]);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(64 * waves), lds, stream, a);
-    return note_hip("k_batch launch", hipGetLastError());
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, stream, a);
+    return note_hip("batch kernel launch", hipGetLastError());
 }
 
 hipError_t launch_fill(uint8_t* p, size_t n, hipStream_t stream) {
@@ -120,15 +124,15 @@ hipError_t launch_fill(uint8_t* p, size_t n, hipStream_t stream) {
     return note_hip("k_fill launch", hipGetLastError());
 }
 
-hipError_t launch_reset_counter(uint32_t* counter, hipStream_t stream) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, counter);
+hipError_t launch_reset_counters(uint32_t* counters, int n, int stride_words, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, counters, n, stride_words);
     return note_hip("k_reset launch", hipGetLastError());
 }
 
-int batch_grid(int device, int waves, size_t lds) {
+int batch_grid(int device, int cls, int waves, size_t lds) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_batch), 64 * waves,
-                                                     lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(batch_kernel(cls)),
+                                                     64 * waves, lds) != hipSuccess ||
         per_cu < 1) {
         (void)hipGetLastError();
         per_cu = 1;

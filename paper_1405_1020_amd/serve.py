@@ -16,8 +16,10 @@ A `Server` holds:
     launch per request, in arrival order, on one stream.
   * per-request timestamps: latency = completion seen by the host - arrival.
 
-Executors only need submit(req) -> handle, poll(handle) -> bool and
-release(req), so the scheduling is testable on the CPU with a fake executor.
+Executors only need submit(req) -> handle and poll(handle) -> bool, so the
+scheduling is testable on the CPU with a fake executor.  An executor may also
+offer collect() -> set of handles completed since the last call; the server
+then makes one such call per step instead of a poll per running request.
 """
 from __future__ import annotations
 
@@ -145,9 +147,16 @@ class Server:
         self._admit()
         n = 0
         still = []
+        collect = getattr(self.ex, "collect", None)
+        completed = None
+        if collect is not None:
+            try:
+                completed = collect()
+            except Exception:  # fall back to polling: failures stay per request
+                completed = None
         for req in self.running:
             try:
-                done = self.ex.poll(req.handle)
+                done = (req.handle in completed) if completed is not None else self.ex.poll(req.handle)
             except Exception as e:
                 self._finish(req, failed=str(e))
                 n += 1
@@ -227,6 +236,14 @@ class QueueExecutor:
 
     def poll(self, ticket) -> bool:
         return self.q.poll(ticket)
+
+    def collect(self) -> set:
+        done = set()
+        while True:
+            got = self.q.completed()
+            done.update(got)
+            if len(got) < 4096:
+                return done
 
     def close(self):
         self.q.close()

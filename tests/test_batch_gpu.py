@@ -160,3 +160,32 @@ def test_queue_continuous_batching_matches_plain():
     with pytest.raises(B.OilpaintError):
         q.poll(next(iter(tickets)))
     q.close()
+
+
+@pytest.mark.gpu
+def test_queue_bulk_completion_and_lone_request():
+    """Completions reported in bulk (each ticket once), a lone request run
+    whole, and a backlog packed into growing launches: all equal the oracle."""
+    torch = torch_mod()
+    cases = small_batch(12, seed=11)
+    q = B.Queue(capacity=64, step_pixels=5000)
+    items, keep = device_items(cases)
+    # a lone request with nothing in flight
+    t0 = q.push(items[0])
+    seen = []
+    while not seen:
+        seen = q.completed()
+    assert seen == [t0]
+    # a backlog of the rest
+    tickets = {q.push(it): i for i, it in enumerate(items[1:], start=1)}
+    got = []
+    while len(got) < len(tickets):
+        got += q.completed()
+    assert sorted(got) == sorted(tickets) and len(set(got)) == len(got)
+    assert q.completed() == []
+    torch.cuda.synchronize()
+    for (img, r, L, _), it in zip(cases, items):
+        assert first_mismatch(from_device(it.dst), ref(img, r, L)) is None, (img.shape, r, L)
+    with pytest.raises(B.OilpaintError):
+        q.poll(t0)
+    q.close()

@@ -55,6 +55,31 @@ class FakeExecutor:
         return True
 
 
+class FakeCollectExecutor(FakeExecutor):
+    """Reports completions in bulk through collect(); poll must not be used."""
+
+    def __init__(self, polls=3):
+        super().__init__(polls=polls)
+        self.live = {}
+        self.next = 1
+
+    def submit(self, req):
+        h = super().submit(req)
+        t = self.next
+        self.next += 1
+        self.live[t] = h
+        return t
+
+    def poll(self, ticket):
+        raise AssertionError("poll used although collect exists")
+
+    def collect(self):
+        done = {t for t, h in self.live.items() if FakeExecutor.poll(self, h)}
+        for t in done:
+            del self.live[t]
+        return done
+
+
 def reqs(sizes, arrivals=None, r=2, L=20):
     out = []
     for i, (w, h) in enumerate(sizes):
@@ -90,6 +115,17 @@ def test_budget_back_pressure_and_results():
     assert ex.max_running == 2
     assert s.peak_used <= 2 * per
     assert s.used == 0
+    for q in rs:
+        assert np.array_equal(q.dst, oracle.oilpaint_ref(q.src, q.radius, q.levels))
+
+
+def test_bulk_completion_collect():
+    rs = reqs([(20, 10), (7, 9), (33, 4), (5, 5), (16, 16)])
+    ex = FakeCollectExecutor(polls=2)
+    s = serve.Server(ex, budget_bytes=3 * serve.request_bytes(rs[0]), allocate=np_alloc, clock=FakeClock())
+    s.start()
+    drain(s, rs)
+    assert s.stats()["completed"] == 5 and s.used == 0 and not ex.live
     for q in rs:
         assert np.array_equal(q.dst, oracle.oilpaint_ref(q.src, q.radius, q.levels))
 
