@@ -222,10 +222,12 @@ int oilpaint_plan_destroy(oilpaint_plan *plan);
  * oilpaint_queue_step (also run by push, poll and completed) packs the work
  * that is waiting -- new requests and the unfinished rows of running ones,
  * an equal share of the launch's pixels each, in whole tile rows -- into one
- * batch launch, keeping at most four launches in flight on the queue's
- * stream, so that requests that arrive while others are on the GPU share
- * the next launch with them.  A launch covers `step_pixels` output pixels,
- * or a quarter of the waiting pixels when that is more (at most 16 x
+ * batch launch, keeping at most four launches in flight, so that requests
+ * that arrive while others are on the GPU share the next launch with them.
+ * Launches run on the queue's side streams and do not wait for each other:
+ * the next launch's kernels start while the previous one's last tiles
+ * finish.  A launch covers `step_pixels` output pixels,
+ * or a quarter of the waiting pixels when that is more (at most 64 x
  * step_pixels).  A lone request with nothing in flight is launched whole
  * with the plain kernel and its own launch shape.
  * ------------------------------------------------------------------------- */
@@ -252,7 +254,9 @@ int oilpaint_queue_poll(oilpaint_queue *q, uint64_t ticket);
 int oilpaint_queue_completed(oilpaint_queue *q, uint64_t *tickets, int max);
 /* Block until every pushed request is complete. */
 int oilpaint_queue_drain(oilpaint_queue *q);
-/* The queue's stream (hipStream_t as void*). */
+/* The queue's control stream (hipStream_t as void*), which carries the
+ * uploads and counter resets; the filter kernels run on side streams.  Use
+ * poll or completed to learn that a request's output is ready. */
 void *oilpaint_queue_stream(oilpaint_queue *q);
 int oilpaint_queue_destroy(oilpaint_queue *q);
 

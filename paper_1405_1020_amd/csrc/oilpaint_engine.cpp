@@ -25,18 +25,14 @@ namespace {
 
 constexpr int kBatchWaves = 1;
 
-// Launch shape of a job inside a persistent launch of `waves` wavefronts per
-// workgroup: the job's own choice with at most `waves` computing
-// wavefronts, shrunk (computing wavefronts, then rows, then lanes) until its
-// on-chip footprint fits.  Runs are at least about 5(2r+1) rows (or the
-// whole band): the batch, not the single image, supplies the parallelism,
-// and the (2r+1)^2 first window of a run then costs at most ~10 % of its
-// sliding updates.
-int batch_shape(Job& j, int waves, int device, int njobs) {
+// Layout of a job inside a persistent launch of `waves` wavefronts per
+// workgroup: the job's own choice with at most `waves` computing wavefronts
+// (the streamed layout replaces a wider tile-staged one when it applies),
+// shrunk (wavefronts, then rows, then lanes) until its on-chip footprint
+// fits.  The rows are set afterwards for the whole launch (shape_rows).
+int batch_shape(Job& j, int waves, int device) {
     oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
     if (v.waves > waves) {
-        // a shape wider than the batch workgroup: the streamed layout when it
-        // applies, else the same layout with fewer wavefronts
         if (j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
             v.hist = OILPAINT_HIST_STREAM;
             v.lanes = 64;
@@ -45,13 +41,9 @@ int batch_shape(Job& j, int waves, int device, int njobs) {
         }
         v.waves = waves;
     }
-    if (v.rows == 0) {
-        // the batch supplies the parallelism: longer runs per image
-        v.per_cu = std::max(1, (v.per_cu * 4 + njobs - 1) / std::max(njobs, 1));
-    }
     for (;;) {
         const int st = apply_variant(j, v, device);
-        if (st == OILPAINT_OK) break;
+        if (st == OILPAINT_OK) return st;
         if (v.waves > 1)
             v.waves >>= 1;
         else if (v.rows > 8)
@@ -61,15 +53,48 @@ int batch_shape(Job& j, int waves, int device, int njobs) {
         else
             return st;
     }
-    const int band = j.row_end - j.row_begin;
-    const int min_rows = std::min(std::min(band, 5 * (2 * j.radius + 1)), 1024);
-    if (j.rows * j.waves < min_rows) {
+}
+
+// Shortest run worth a tile: about 5(2r+1) rows, so that the (2r+1)^2 first
+// window costs at most ~10 % of the run's sliding updates (or the whole
+// band when it is shorter).
+int min_run_rows(const Job& j) {
+    return std::max(1, std::min(j.row_end - j.row_begin, std::max(8, 5 * (2 * j.radius + 1))));
+}
+
+// Rows per tile for every job of one launch, from the launch's total work:
+// about kTilesPerSlot tiles per resident workgroup over the whole launch
+// (the batch, not a single image, supplies the parallelism; long runs pay
+// the first window and the per-tile prologue rarely), at least
+// min_run_rows and at most the band or 1024 rows.  A job whose layout does
+// not fit the new rows keeps its own.
+constexpr int kTilesPerSlot = 32;
+constexpr int kSlotsPerCu = 8;  // typical resident one-wavefront workgroups
+
+void shape_rows(std::vector<Job>& jobs, int device) {
+    const DeviceInfo d = device_info(device);
+    const double slots = (double)(d.ok ? d.cus : 256) * kSlotsPerCu;
+    double strip_rows = 0;
+    for (const Job& j : jobs)
+        strip_rows += (double)((j.width + j.lanes - 1) / j.lanes) * (j.row_end - j.row_begin);
+    const int target = (int)std::min(1024.0, std::ceil(strip_rows / (kTilesPerSlot * slots)));
+    for (Job& j : jobs) {
+        const int band = j.row_end - j.row_begin;
+        const int rows = std::max(min_run_rows(j), std::min(target, std::min(band, 1024)));
+        oilpaint_variant v;
+        v.waves = j.waves;
+        v.hist = j.hist;
+        v.lanes = j.lanes;
+        v.per_cu = 1;
+        v.rows = std::max(1, (rows + j.waves - 1) / j.waves);
         Job t = j;
-        oilpaint_variant w = v;
-        w.rows = (min_rows + w.waves - 1) / w.waves;
-        if (apply_variant(t, w, device) == OILPAINT_OK) j = t;
+        if (apply_variant(t, v, device) == OILPAINT_OK) {
+            j = t;
+        } else {  // own rows, tiles over this band
+            const long per_tile = (long)j.waves * j.rows;
+            j.tiles_y = (int)((band + per_tile - 1) / per_tile);
+        }
     }
-    return OILPAINT_OK;
 }
 
 // Relative cost of one tile: window updates plus the mode search per output
@@ -166,13 +191,11 @@ BatchArgs class_args(const Layout& L, size_t k, uint8_t* dev) {
 }
 
 // Side streams and events that spread a batch's classes over concurrent
-// branches.  Branch 0 is the caller's stream; branch b > 0 runs on side[b-1],
-// which waits for the caller's stream at the fork and is waited for by it at
-// the join.  Inside a stream capture the branches become parallel graph
+// streams.  Inside a stream capture the branches become parallel graph
 // branches.
 struct Branches {
-    hipStream_t side[kMaxBranches - 1] = {};
-    hipEvent_t join[kMaxBranches - 1] = {};
+    hipStream_t side[kMaxBranches] = {};
+    hipEvent_t join[kMaxBranches] = {};
     hipEvent_t fork = nullptr;
     int made = 0;
 
@@ -187,10 +210,10 @@ struct Branches {
         }
         if (fork) (void)hipEventDestroy(fork);
     }
-    // Make sure branches 0 .. n-1 exist.
+    // Make sure side streams 0 .. n-1 exist.
     bool ensure(int n) {
         if (!fork && hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return false;
-        while (made < n - 1) {
+        while (made < n) {
             if (hipStreamCreateWithFlags(&side[made], hipStreamNonBlocking) != hipSuccess) return false;
             if (hipEventCreateWithFlags(&join[made], hipEventDisableTiming) != hipSuccess) {
                 (void)hipStreamDestroy(side[made]);
@@ -204,23 +227,35 @@ struct Branches {
 
 // Enqueue the counter reset and every class's persistent kernel, the
 // classes spread over branches by total cost (each to the least loaded).
+//   join:      branch 0 is `stream` itself and the side branches join back
+//              into it, so the whole batch is ordered before later work on
+//              `stream` (batches and plans).
+//   detached:  every class runs on a side stream that waits for the reset
+//              on `stream`, and nothing joins back, so the next launch's
+//              classes start while this one's last tiles finish (the
+//              request queue).  The streams carrying work are returned in
+//              ends[0 .. *nends-1]; the caller records completion there.
 // Returns the number of workgroups launched in `workgroups`.
-int enqueue_classes(const Layout& L, uint8_t* dev, int device, Branches& br, hipStream_t stream,
-                    int* workgroups) {
+int enqueue_classes(const Layout& L, uint8_t* dev, int device, Branches& br, hipStream_t stream, bool join,
+                    int* workgroups, hipStream_t* ends, int* nends) {
     const int nc = (int)L.classes.size();
     if (workgroups) *workgroups = 0;
+    if (nends) *nends = 0;
     if (L.ntiles == 0) return OILPAINT_OK;
     if (launch_reset_counters(reinterpret_cast<uint32_t*>(dev), nc, kCounterWords, stream) != hipSuccess)
         return OILPAINT_ERR_HIP;
     const int nb = std::min(nc, kMaxBranches);
-    if (!br.ensure(nb)) {
+    const int nside = join ? nb - 1 : nb;
+    hipStream_t bs[kMaxBranches];
+    if (!br.ensure(nside)) {
         (void)note_hip("branch streams", hipGetLastError());
         return OILPAINT_ERR_HIP;
     }
-    if (nb > 1) {
+    for (int b = 0; b < nb; ++b) bs[b] = join ? (b == 0 ? stream : br.side[b - 1]) : br.side[b];
+    if (nside > 0) {
         if (note_hip("hipEventRecord", hipEventRecord(br.fork, stream)) != hipSuccess) return OILPAINT_ERR_HIP;
-        for (int b = 1; b < nb; ++b)
-            if (note_hip("hipStreamWaitEvent", hipStreamWaitEvent(br.side[b - 1], br.fork, 0)) != hipSuccess)
+        for (int b = 0; b < nside; ++b)
+            if (note_hip("hipStreamWaitEvent", hipStreamWaitEvent(br.side[b], br.fork, 0)) != hipSuccess)
                 return OILPAINT_ERR_HIP;
     }
     double load[kMaxBranches] = {};
@@ -231,28 +266,36 @@ int enqueue_classes(const Layout& L, uint8_t* dev, int device, Branches& br, hip
         const int b = (int)(std::min_element(load, load + nb) - load);
         load[b] += c.cost;
         const int grid = std::min(batch_grid(device, c.cls, kBatchWaves, c.lds), c.ntiles);
-        const hipStream_t s = b == 0 ? stream : br.side[b - 1];
-        if (launch_batch(class_args(L, (size_t)k, dev), c.cls, kBatchWaves, c.lds, grid, s) != hipSuccess)
+        if (launch_batch(class_args(L, (size_t)k, dev), c.cls, kBatchWaves, c.lds, grid, bs[b]) != hipSuccess)
             return OILPAINT_ERR_HIP;
         total += grid;
     }
-    for (int b = 1; b < nb; ++b) {
-        if (note_hip("hipEventRecord", hipEventRecord(br.join[b - 1], br.side[b - 1])) != hipSuccess ||
-            note_hip("hipStreamWaitEvent", hipStreamWaitEvent(stream, br.join[b - 1], 0)) != hipSuccess)
-            return OILPAINT_ERR_HIP;
+    if (join) {
+        for (int b = 0; b < nside; ++b) {
+            if (note_hip("hipEventRecord", hipEventRecord(br.join[b], br.side[b])) != hipSuccess ||
+                note_hip("hipStreamWaitEvent", hipStreamWaitEvent(stream, br.join[b], 0)) != hipSuccess)
+                return OILPAINT_ERR_HIP;
+        }
+        if (ends) ends[0] = stream;
+        if (nends) *nends = 1;
+    } else {
+        for (int b = 0; b < nb; ++b)
+            if (ends) ends[b] = bs[b];
+        if (nends) *nends = nb;
     }
     if (workgroups) *workgroups = total;
     return OILPAINT_OK;
 }
 
 // A small ring of (pinned host, device) argument buffers.  A slot is reused
-// only after the event recorded behind its last launch has completed.
+// only after the events recorded behind its last launch (one per stream that
+// carried it) have completed.
 struct ArgSlot {
     uint8_t* dev = nullptr;
     uint8_t* host = nullptr;
     size_t cap = 0;
-    hipEvent_t done = nullptr;
-    bool pending = false;
+    hipEvent_t done[kMaxBranches] = {};
+    int pending = 0;  // events recorded
 };
 
 class ArgRing {
@@ -260,21 +303,20 @@ class ArgRing {
     explicit ArgRing(int n) : slots_(n) {}
     ~ArgRing() {
         for (auto& s : slots_) {
-            if (s.pending) (void)hipEventSynchronize(s.done);
+            for (int i = 0; i < s.pending; ++i) (void)hipEventSynchronize(s.done[i]);
             if (s.dev) (void)hipFree(s.dev);
             if (s.host) (void)hipHostFree(s.host);
-            if (s.done) (void)hipEventDestroy(s.done);
+            for (hipEvent_t e : s.done)
+                if (e) (void)hipEventDestroy(e);
         }
     }
     // Returns a slot with at least `bytes` of capacity, or nullptr.
     ArgSlot* acquire(size_t bytes) {
         ArgSlot* s = &slots_[next_];
         next_ = (next_ + 1) % slots_.size();
-        if (s->pending) {
-            if (hipEventSynchronize(s->done) != hipSuccess) return nullptr;
-            s->pending = false;
-        }
-        if (!s->done && hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) return nullptr;
+        for (int i = 0; i < s->pending; ++i)
+            if (hipEventSynchronize(s->done[i]) != hipSuccess) return nullptr;
+        s->pending = 0;
         if (s->cap < bytes) {
             if (s->dev) (void)hipFree(s->dev);
             if (s->host) (void)hipHostFree(s->host);
@@ -292,8 +334,13 @@ class ArgRing {
         }
         return s;
     }
-    void release(ArgSlot* s, hipStream_t stream) {
-        if (hipEventRecord(s->done, stream) == hipSuccess) s->pending = true;
+    // The slot is in use by the work enqueued so far on streams[0 .. n-1].
+    void release(ArgSlot* s, const hipStream_t* streams, int n) {
+        for (int i = 0; i < n && i < kMaxBranches; ++i) {
+            if (!s->done[i] && hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming) != hipSuccess) break;
+            if (hipEventRecord(s->done[i], streams[i]) != hipSuccess) break;
+            s->pending = i + 1;
+        }
     }
 
   private:
@@ -301,8 +348,10 @@ class ArgRing {
     size_t next_ = 0;
 };
 
-// Upload `L` through `ring` and enqueue its classes.
-int enqueue_layout(const Layout& L, int device, ArgRing& ring, Branches& br, hipStream_t stream) {
+// Upload `L` through `ring` and enqueue its classes (see enqueue_classes).
+int enqueue_layout(const Layout& L, int device, ArgRing& ring, Branches& br, hipStream_t stream, bool join,
+                   hipStream_t* ends, int* nends) {
+    if (nends) *nends = 0;
     if (L.ntiles == 0) return OILPAINT_OK;
     ArgSlot* s = ring.acquire(L.bytes);
     if (!s) return OILPAINT_ERR_NOMEM;
@@ -310,9 +359,15 @@ int enqueue_layout(const Layout& L, int device, ArgRing& ring, Branches& br, hip
     if (note_hip("hipMemcpyAsync", hipMemcpyAsync(s->dev, s->host, L.bytes, hipMemcpyHostToDevice, stream)) !=
         hipSuccess)
         return OILPAINT_ERR_HIP;
-    const int st = enqueue_classes(L, s->dev, device, br, stream, nullptr);
+    hipStream_t es[kMaxBranches];
+    int ne = 0;
+    const int st = enqueue_classes(L, s->dev, device, br, stream, join, nullptr, es, &ne);
     if (st != OILPAINT_OK) return st;
-    ring.release(s, stream);
+    // every stream in es[] is ordered after the upload and the reset
+    ring.release(s, es, ne);
+    for (int i = 0; i < ne; ++i)
+        if (ends) ends[i] = es[i];
+    if (nends) *nends = ne;
     return OILPAINT_OK;
 }
 
@@ -353,7 +408,7 @@ int collect_jobs(const oilpaint_desc* descs, int n, int device, std::vector<Job>
         Job j;
         bool empty = false;
         int st = make_job(descs[i], nullptr, device, j, empty);
-        if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, device, n);
+        if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, device);
         if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.src);
         if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.dst);
         if (st != OILPAINT_OK) {
@@ -363,6 +418,7 @@ int collect_jobs(const oilpaint_desc* descs, int n, int device, std::vector<Job>
         if (!empty) jobs.push_back(j);
     }
     if (bad_index) *bad_index = -1;
+    shape_rows(jobs, device);
     return OILPAINT_OK;
 }
 
@@ -398,7 +454,7 @@ struct QueueReq {
 };
 
 struct Inflight {
-    hipEvent_t ev;
+    std::vector<hipEvent_t> evs;    // one per stream that carries the launch
     std::vector<uint64_t> tickets;  // requests with a band in this launch
 };
 
@@ -417,37 +473,48 @@ struct oilpaint_queue {
     std::deque<uint64_t> finished;  // completed, in completion order (may hold
                                     // tickets already reported by poll)
     size_t held = 0;  // requests not yet complete
+    unsigned next_side = 0;  // side stream of the next single-band launch
 };
 
 namespace {
 
-void retire(oilpaint_queue* q, bool block) {
-    while (!q->inflight.empty()) {
-        Inflight& f = q->inflight.front();
-        if (block) {
-            if (hipEventSynchronize(f.ev) != hipSuccess) return;
-        } else {
-            const hipError_t e = hipEventQuery(f.ev);
-            if (e == hipErrorNotReady) return;
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return;
+// Retire every launch that has completed (launches on different streams may
+// complete out of order); with `block`, first wait for the oldest.  A
+// request is complete when all launches holding one of its bands are.
+int retire(oilpaint_queue* q, bool block) {
+    if (block && !q->inflight.empty())
+        for (hipEvent_t e : q->inflight.front().evs)
+            if (note_hip("hipEventSynchronize", hipEventSynchronize(e)) != hipSuccess) return OILPAINT_ERR_HIP;
+    for (auto it = q->inflight.begin(); it != q->inflight.end();) {
+        bool done = true;
+        for (hipEvent_t e : it->evs) {
+            const hipError_t st = hipEventQuery(e);
+            if (st == hipSuccess) continue;
+            if (st != hipErrorNotReady) {
+                (void)note_hip("hipEventQuery", st);
+                return OILPAINT_ERR_HIP;
             }
+            done = false;
+            break;
         }
-        for (uint64_t t : f.tickets) {
-            auto it = q->reqs.find(t);
-            if (it == q->reqs.end()) continue;
-            QueueReq& r = it->second;
+        if (!done) {
+            ++it;
+            continue;
+        }
+        for (uint64_t t : it->tickets) {
+            auto r_it = q->reqs.find(t);
+            if (r_it == q->reqs.end()) continue;
+            QueueReq& r = r_it->second;
             if (--r.launches_left == 0 && r.all_launched && !r.done) {
                 r.done = true;
                 --q->held;
                 q->finished.push_back(t);
             }
         }
-        q->free_events.push_back(f.ev);
-        q->inflight.pop_front();
-        block = false;
+        for (hipEvent_t e : it->evs) q->free_events.push_back(e);
+        it = q->inflight.erase(it);
     }
+    return OILPAINT_OK;
 }
 
 // Pack waiting work into one launch.  Every waiting request gets an equal
@@ -455,7 +522,7 @@ void retire(oilpaint_queue* q, bool block) {
 // a small request that arrives behind a large one finishes in the next
 // launch instead of waiting for the large one to drain.  The launch covers
 // step_pixels, or a quarter of the waiting pixels when the backlog is larger
-// (at most 16 x step_pixels), so that a backlog keeps enough work in flight;
+// (at most 64 x step_pixels), so that a backlog keeps enough work in flight;
 // a lone request with nothing in flight runs whole.  A launch of a single
 // band uses the plain kernel with the request's own launch shape.
 int launch_step(oilpaint_queue* q) {
@@ -467,7 +534,7 @@ int launch_step(oilpaint_queue* q) {
     }
     const bool lone = q->waiting.size() == 1 && q->inflight.empty();
     int64_t budget = lone ? waiting_px
-                          : std::max(q->step_pixels, std::min(16 * q->step_pixels, waiting_px / 4));
+                          : std::max(q->step_pixels, std::min(64 * q->step_pixels, waiting_px / 4));
     std::vector<Job> jobs;
     std::vector<uint64_t> tickets;
     const int64_t share = std::max<int64_t>(1, budget / (int64_t)q->waiting.size());
@@ -479,17 +546,16 @@ int launch_step(oilpaint_queue* q) {
             continue;
         }
         const Job& w = r.job;
-        const int unit = std::max(1, w.waves * w.rows);  // rows per tile row
         const int64_t row_px = (int64_t)w.width;
-        int64_t want_rows = std::max<int64_t>(unit, std::min<int64_t>(share, budget) / std::max<int64_t>(row_px, 1));
-        want_rows = (want_rows + unit - 1) / unit * unit;
         const int rb = r.next_row;
-        const int re = (int)std::min<int64_t>(w.row_end, rb + want_rows);
         Job band = w;
         band.row_begin = rb;
+        band.row_end = w.row_end;
+        const int64_t unit = min_run_rows(band);  // shortest band worth a tile
+        const int64_t want_rows =
+            std::max<int64_t>(unit, std::min<int64_t>(share, budget) / std::max<int64_t>(row_px, 1));
+        const int re = (int)std::min<int64_t>(w.row_end, rb + want_rows);
         band.row_end = re;
-        const long per_tile = (long)band.waves * band.rows;
-        band.tiles_y = (int)((re - rb + per_tile - 1) / per_tile);
         jobs.push_back(band);
         tickets.push_back(t);
         r.next_row = re;
@@ -502,6 +568,14 @@ int launch_step(oilpaint_queue* q) {
     }
     q->waiting.swap(still);
     if (jobs.empty()) return 0;
+    // The work goes to side streams only, so that nothing on the queue's own
+    // stream (uploads, counter resets) waits for a running launch.
+    if (!q->branches->ensure(kMaxBranches)) {
+        (void)note_hip("branch streams", hipGetLastError());
+        return OILPAINT_ERR_HIP;
+    }
+    hipStream_t ends[kMaxBranches];
+    int nends = 0;
     int st = OILPAINT_OK;
     if (jobs.size() == 1) {
         oilpaint_desc d = q->reqs[tickets[0]].desc;
@@ -509,32 +583,39 @@ int launch_step(oilpaint_queue* q) {
         d.row_end = jobs[0].row_end;
         Job pj;
         bool empty = false;
+        const hipStream_t side = q->branches->side[q->next_side++ % kMaxBranches];
         st = make_job(d, nullptr, q->device, pj, empty);
-        if (st == OILPAINT_OK && !empty && launch_plain(pj, pj.waves, lds_bytes(pj), q->stream) != hipSuccess)
+        if (st == OILPAINT_OK && !empty && launch_plain(pj, pj.waves, lds_bytes(pj), side) != hipSuccess)
             st = OILPAINT_ERR_HIP;
+        ends[0] = side;
+        nends = 1;
     } else {
+        shape_rows(jobs, q->device);
         Layout L;
         build_layout(jobs, L);
-        st = enqueue_layout(L, q->device, *q->ring, *q->branches, q->stream);
+        st = enqueue_layout(L, q->device, *q->ring, *q->branches, q->stream, false, ends, &nends);
     }
     if (st != OILPAINT_OK) return st;
-    hipEvent_t ev;
-    if (!q->free_events.empty()) {
-        ev = q->free_events.back();
-        q->free_events.pop_back();
-    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-        return OILPAINT_ERR_HIP;
-    }
-    if (hipEventRecord(ev, q->stream) != hipSuccess) return OILPAINT_ERR_HIP;
     Inflight f;
-    f.ev = ev;
+    for (int i = 0; i < nends; ++i) {
+        hipEvent_t ev;
+        if (!q->free_events.empty()) {
+            ev = q->free_events.back();
+            q->free_events.pop_back();
+        } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            return OILPAINT_ERR_HIP;
+        }
+        f.evs.push_back(ev);
+        if (hipEventRecord(ev, ends[i]) != hipSuccess) return OILPAINT_ERR_HIP;
+    }
     f.tickets = tickets;
     q->inflight.push_back(f);
     return 1;
 }
 
 int queue_progress(oilpaint_queue* q) {
-    retire(q, false);
+    const int rs = retire(q, false);
+    if (rs != OILPAINT_OK) return rs;
     int launched = 0;
     while (q->inflight.size() < (size_t)kQueueDepth && !q->waiting.empty()) {
         const int st = launch_step(q);
@@ -558,7 +639,8 @@ int oilpaint_batch(const oilpaint_desc* descs, int n, void* stream, int* bad_ind
     Layout L;
     build_layout(jobs, L);
     std::lock_guard<std::mutex> lock(ring_mutex(device));
-    return enqueue_layout(L, device, device_ring(device), device_branches(device), (hipStream_t)stream);
+    return enqueue_layout(L, device, device_ring(device), device_branches(device), (hipStream_t)stream, true,
+                          nullptr, nullptr);
 }
 
 int oilpaint_plan_create(const oilpaint_desc* descs, int n, void* stream, oilpaint_plan** out, int* bad_index) {
@@ -586,7 +668,8 @@ int oilpaint_plan_create(const oilpaint_desc* descs, int n, void* stream, oilpai
             Branches br;
             ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
             // counters are cleared by a kernel, not a memset node
-            ok = ok && enqueue_classes(p->layout, p->dev, device, br, cap, &p->grid) == OILPAINT_OK;
+            ok = ok && enqueue_classes(p->layout, p->dev, device, br, cap, true, &p->grid, nullptr, nullptr) ==
+                           OILPAINT_OK;
             ended = hipStreamEndCapture(cap, &g) == hipSuccess;
         }
         (void)hipStreamDestroy(cap);
@@ -642,12 +725,13 @@ int oilpaint_queue_create(int capacity, int64_t step_pixels, oilpaint_queue** ou
 
 int oilpaint_queue_push(oilpaint_queue* q, const oilpaint_desc* desc, uint64_t* ticket) {
     if (!q || !desc || !ticket) return OILPAINT_ERR_NULL;
-    retire(q, false);
+    const int rs = retire(q, false);
+    if (rs != OILPAINT_OK) return rs;
     if ((int)q->held >= q->capacity) return OILPAINT_ERR_FULL;
     Job j;
     bool empty = false;
     int st = make_job(*desc, nullptr, q->device, j, empty);
-    if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, q->device, 4);
+    if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, q->device);
     if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.src);
     if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.dst);
     if (st != OILPAINT_OK) return st;
@@ -718,7 +802,8 @@ int oilpaint_queue_drain(oilpaint_queue* q) {
         const int st = queue_progress(q);
         if (st < 0) return st;
         if (q->inflight.empty() && q->waiting.empty()) return OILPAINT_OK;
-        retire(q, true);
+        const int rs = retire(q, true);
+        if (rs != OILPAINT_OK) return rs;
     }
 }
 
@@ -727,10 +812,11 @@ void* oilpaint_queue_stream(oilpaint_queue* q) { return q ? (void*)q->stream : n
 int oilpaint_queue_destroy(oilpaint_queue* q) {
     if (!q) return OILPAINT_OK;
     (void)hipStreamSynchronize(q->stream);
-    for (auto& f : q->inflight) (void)hipEventDestroy(f.ev);
+    q->branches.reset();  // synchronizes the side streams
+    for (auto& f : q->inflight)
+        for (hipEvent_t e : f.evs) (void)hipEventDestroy(e);
     for (auto e : q->free_events) (void)hipEventDestroy(e);
     q->ring.reset();
-    q->branches.reset();
     (void)hipStreamDestroy(q->stream);
     delete q;
     return OILPAINT_OK;
