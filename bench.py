@@ -22,7 +22,6 @@ usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -34,6 +33,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "megapixels/sec at (r, L), batched/served vs plain kernel; p50/p99 request latency"
+# How the HBM counter summary is made, from the repository root on the GPU
+# host (the first line fills the tuning cache so that the profiled runs
+# launch only the timed shapes).
+HBM_COMMANDS = [
+    "python3 bench.py --quick --steps 5 --warmup 2",
+    "cd /tmp && export TMPDIR=/tmp",
+    "timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/hbm/sweep_fetch --output-format csv -- "
+    "python3 $REPO/bench.py --quick --steps 5 --warmup 2",
+    "timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/hbm/sweep_write --output-format csv -- "
+    "python3 $REPO/bench.py --quick --steps 5 --warmup 2",
+    "timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/hbm/copy_fetch --output-format csv -- "
+    "python3 $REPO/bench.py --copy-ref",
+    "timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/hbm/copy_write --output-format csv -- "
+    "python3 $REPO/bench.py --copy-ref",
+    "cd $REPO && python3 bench.py --hbm-summary gpurun_out/hbm",
+]
 LDS_PEAK_GBS = 256 * 2.4e9 * 256 / 1e9  # 256 CUs x 2.4 GHz x 256 B/clk LDS read path
 
 
@@ -43,11 +58,25 @@ def log(*a):
 
 def lds_bytes_per_pixel(r: int, L: int) -> int:
     """Algorithmic LDS bytes per output pixel of the sliding-window method:
-    2(2r+1) window updates, each reading a 4-byte staged pixel and applying
-    one 8-byte bin update, plus the mode search reading L bins of 8 bytes and
-    the winning bin once more."""
+    U = 2(2r+1) window updates, each reading a 4-byte staged pixel and
+    reading and writing one 8-byte bin (20 B), plus the mode search reading
+    L bins of 8 bytes: 20 U + 8 L."""
     u = 2 * (2 * r + 1)
-    return u * (4 + 8) + (L + 1) * 8
+    return 20 * u + 8 * L
+
+
+HBM_PROFILE = os.path.join(ROOT, "profiles", "k_plain_fhd_sweep_hbm.json")
+
+
+def kernel_name(r: int, L: int, v) -> str:
+    """Name of the plain kernel a (radius, levels, variant) launch runs, as
+    the profiler reports it."""
+    scan = (L + 7) // 8 * 8
+    if v.hist == 1:  # streamed rows
+        return "k_plain_stream<%d, %d>" % (r, 32 if scan <= 32 else 64)
+    if v.hist == 0 and v.lanes == 64 and r <= 15 and L <= 64:
+        return "k_plain_fast<%d, %d>" % (r, 16 if scan <= 16 else 32 if scan <= 32 else 64)
+    return "k_plain"
 
 
 def kernel_source_hash() -> str:
@@ -106,9 +135,9 @@ def bench_plain(torch, B, synth, timer, steps, warmup):
     for r, L in runs:
         ms = timer.time(lambda: B.oilpaint_async(src, dst, r, L), max(steps, 10), 2)
         v = B.pick_variant(img.shape[1], img.shape[0], r, L)
-        per["r%d_L%d" % (r, L)] = {"ms": round(ms, 5), "mp_per_s": round(mp / (ms / 1e3), 1),
+        per["r%d_L%d" % (r, L)] = {"r": r, "L": L, "ms": round(ms, 5), "mp_per_s": round(mp / (ms / 1e3), 1),
                                    "lds_gbs": round(lds_bytes_per_pixel(r, L) * mp * 1e6 / (ms / 1e3) / 1e9, 1),
-                                   "variant": list(v.as_tuple())}
+                                   "kernel": kernel_name(r, L, v), "variant": list(v.as_tuple())}
     total_bytes = sum(lds_bytes_per_pixel(r, L) for r, L in runs) * mp * 1e6
     achieved = total_bytes / (ms_step / 1e3) / 1e9
     return img, src, ms_step, mp * len(runs), per, achieved
@@ -169,7 +198,9 @@ def bench_serving(torch, B, synth, serve, n_requests, oracle_mod):
             for q in rs:
                 q.arrival_s = 0.0
         ex = serve.QueueExecutor(capacity=4096, step_pixels=16 << 20) if kind == "queue" else serve.PlainExecutor()
-        alloc, free = serve.device_allocator(keep=(kind == "queue" and not saturate))
+        # light load: outputs allocated up front and kept (verification);
+        # saturation: allocated at admission, released at completion
+        alloc, free = serve.device_allocator(keep=not saturate, preallocate=None if saturate else rs)
         s = serve.Server(ex, budget_bytes=budget, capacity=4096, allocate=alloc, free=free)
         st = serve.run_open_loop(s, rs)
         ex.close()
@@ -178,17 +209,14 @@ def bench_serving(torch, B, synth, serve, n_requests, oracle_mod):
 
     st_q, rs_q = one("queue", False)
     log("served (queue):", st_q)
-    st_p, _ = one("plain", False)
+    st_p, rs_p = one("plain", False)
     log("served (plain):", st_p)
-    sat_q, _ = one("queue", True)
-    sat_p, _ = one("plain", True)
-    # verification: every served output against the plain kernel, a sample
-    # against the CPU oracle (pixels whose windows are cut out and filtered)
-    equal = 0
-    for q in rs_q:
-        ref = torch.empty_like(q.dst)
-        B.run(B.Item(q.src, ref, q.radius, q.levels))
-        equal += int(torch.equal(ref, q.dst))
+    # verification: every served output equals the same request filtered by
+    # the plain kernel alone; a sample against the CPU oracle (pixels whose
+    # windows are cut out and filtered)
+    equal = sum(int(torch.equal(a.dst, b.dst)) for a, b in zip(rs_q, rs_p))
+    for q in rs_p:
+        q.dst = None
     torch.cuda.synchronize()
     import numpy as np
     rng = np.random.default_rng(5)
@@ -208,6 +236,9 @@ def bench_serving(torch, B, synth, serve, n_requests, oracle_mod):
             checked += 1
     for q in rs_q:
         q.dst = None
+    torch.cuda.synchronize()
+    sat_q, _ = one("queue", True)
+    sat_p, _ = one("plain", True)
 
     def pick(st):
         return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()
@@ -239,17 +270,76 @@ def cpu_baseline(oracle_mod, img, runs):
             "sample": "the full 1920x1080 sweep (7 runs), row bands over %d threads, %.1f s wall" % (threads, dt)}
 
 
-def hbm_traffic(achieved_launch_bytes):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_plain_fhd_sweep_hbm.json")
+def hbm_traffic(kernel: str, config: str):
+    """HBM bytes per launch of `kernel` on sweep run `config`, from the
+    committed counter summary, if it was taken on the current kernel source
+    (else None)."""
     try:
-        d = json.load(open(path))
+        d = json.load(open(HBM_PROFILE))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    e = d.get("launches", {}).get(config)
+    if not e or e.get("kernel") != kernel:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def _pmc_rows(folder: str, counter: str):
+    """(kernel name, grid size, value) of every dispatch in a rocprofv3
+    --pmc CSV output under `folder`."""
+    import csv
+    import glob
+    import re
+    out = []
+    for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        for row in csv.DictReader(open(f)):
+            if row.get("Counter_Name") != counter:
+                continue
+            m = re.search(r"(k_\w+(?:<[\d, ]+>)?)\(", row["Kernel_Name"])
+            name = m.group(1) if m else row["Kernel_Name"]
+            out.append((name, int(row.get("Grid_Size", 0) or 0), float(row["Counter_Value"])))
+    return out
+
+
+def write_hbm_summary(folder: str, commands: list[str]):
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE over
+    `bench.py --quick` and over `bench.py --copy-ref`, in the sub-folders
+    sweep_fetch, sweep_write, copy_fetch and copy_write of `folder`) into
+    the committed HBM summary: per sweep run, the counters per dispatch of
+    its kernel, scaled so that the copy kernel's counters read its known
+    bytes."""
+    import statistics
+    from paper_1405_1020_amd import binding as B, synth, tune
+    tune.load()  # the launch shapes the profiled runs used
+    copy_bytes = 1 << 30
+    scale = {}
+    for c, sub in (("FETCH_SIZE", "copy_fetch"), ("WRITE_SIZE", "copy_write")):
+        vals = [v for n, g, v in _pmc_rows(os.path.join(folder, sub), c) if g >= (1 << 20)]
+        scale[c] = copy_bytes / (statistics.median(vals) * 1024.0)
+    w, h = 1920, 1080
+    launches = {}
+    for r, L in synth.FHD_SWEEP:
+        v = B.pick_variant(w, h, r, L)
+        name = kernel_name(r, L, v)
+        e = {"kernel": name, "variant": list(v.as_tuple())}
+        for c, sub in (("FETCH_SIZE", "sweep_fetch"), ("WRITE_SIZE", "sweep_write")):
+            vals = [v_ for n, g, v_ in _pmc_rows(os.path.join(folder, sub), c) if n == name]
+            e[c.lower() + "_kib_per_dispatch"] = round(statistics.median(vals), 1) if vals else None
+            e[c.lower() + "_dispatches"] = len(vals)
+        if e["fetch_size_kib_per_dispatch"] is not None and e["write_size_kib_per_dispatch"] is not None:
+            e["hbm_bytes_per_launch"] = round(e["fetch_size_kib_per_dispatch"] * 1024 * scale["FETCH_SIZE"] +
+                                              e["write_size_kib_per_dispatch"] * 1024 * scale["WRITE_SIZE"])
+            e["algorithmic_hbm_bytes"] = 6 * w * h
+        launches["r%d_L%d" % (r, L)] = e
+    out = {"kernel_source_sha": kernel_source_hash(), "workload": "fhd_1920x1080_sweep",
+           "commands": commands, "copy_reference": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
+                                                     "scale": {k: round(v_, 4) for k, v_ in scale.items()}},
+           "launches": launches}
+    with open(HBM_PROFILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def main():
@@ -261,6 +351,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--copy-ref", action="store_true",
                     help="run only a plain 1 GiB device copy kernel (HBM counter scaling) and exit")
+    ap.add_argument("--hbm-summary", metavar="DIR",
+                    help="write the HBM counter summary under profiles/ from rocprofv3 --pmc outputs in DIR")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -271,6 +363,10 @@ def main():
     from paper_1405_1020_amd import binding as B, synth, serve
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B.lib()
+
+    if args.hbm_summary:
+        write_hbm_summary(args.hbm_summary, HBM_COMMANDS)
+        return
 
     if args.copy_ref:
         n = 1 << 30
@@ -298,10 +394,17 @@ def main():
                    "runs": [list(x) for x in synth.FHD_SWEEP], "image": "40 Gaussian colour blobs + U{-8..8} noise, seed 2",
                    "launches_per_step": len(synth.FHD_SWEEP)},
     }
-    res["roofline"] = {"bound": "lds", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
-                       "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
-                       "traffic": hbm_traffic(None), "kernel": "k_plain",
-                       "avg_launch_ms": round(launch_ms, 5)}
+    # roofline of the dominant kernel: the sweep run with the longest launch
+    dom = max(per, key=lambda k: per[k]["ms"])
+    d = per[dom]
+    r_d, L_d = d["r"], d["L"]
+    d_bytes = lds_bytes_per_pixel(r_d, L_d) * img.shape[0] * img.shape[1]
+    d_ach = d_bytes / (d["ms"] / 1e3) / 1e9
+    res["roofline"] = {"bound": "lds", "achieved": round(d_ach, 1), "peak": round(LDS_PEAK_GBS, 1),
+                       "unit": "GB/s", "frac": round(d_ach / LDS_PEAK_GBS, 4),
+                       "traffic": hbm_traffic(d["kernel"], dom), "kernel": d["kernel"], "run": dom,
+                       "lds_bytes_per_launch": d_bytes, "avg_launch_ms": d["ms"],
+                       "sweep_achieved": round(achieved, 1), "sweep_avg_launch_ms": round(launch_ms, 5)}
     res["sweep"] = per
     res["tuned_variants"] = tuned
     if not args.quick:

@@ -282,13 +282,21 @@ def make_requests(workload) -> list[ServeRequest]:
     return out
 
 
-def device_allocator(keep: bool):
+def device_allocator(keep: bool, preallocate=None):
     """allocate/free callbacks that give each admitted request a dense
     [H, W, 3] output buffer; with keep=True outputs stay alive in the request
-    after completion (for verification)."""
+    after completion (for verification).  With `preallocate` (the requests
+    of a run) every output is allocated up front, so that no allocation
+    falls inside the served run."""
     import torch
+    pool = {}
+    if preallocate is not None:
+        for req in preallocate:
+            pool[req.rid] = torch.empty((req.height, req.width, 3), dtype=torch.uint8, device=req.src.device)
 
     def allocate(req: ServeRequest):
+        if req.rid in pool:
+            return pool.pop(req.rid)
         return torch.empty((req.height, req.width, 3), dtype=torch.uint8, device=req.src.device)
 
     def free(req: ServeRequest):
