@@ -48,10 +48,7 @@ size_t lds_bytes(const Job& j) {
     const size_t nb = (size_t)j.bins;
     const size_t lanes = (size_t)j.lanes;
     if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
-    if (j.hist == OILPAINT_HIST_STREAM) {
-        const size_t tw = 64 + 2 * (size_t)j.radius;
-        return nb * 64 * 8 + (2 * (size_t)j.radius + 4) * tw * 4 + 192;
-    }
+    if (j.hist == OILPAINT_HIST_STREAM) return nb * 64 * 8 + stream_ring_bytes(j) + 192;
     const size_t tw = lanes + 2 * (size_t)j.radius;
     const size_t th = (size_t)waves * (size_t)j.rows + 2 * (size_t)j.radius;
     const size_t tile = (tw * th * 4 + 15) & ~(size_t)15;

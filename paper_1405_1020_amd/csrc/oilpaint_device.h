@@ -83,6 +83,19 @@ __device__ __forceinline__ void lds_sub(T* p, T v) {
     __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// LDS words addressed by their 32-bit LDS offset.
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+__device__ __forceinline__ uint32_t lds_offset(const uint8_t* p) {
+    return (uint32_t)(size_t)(const __attribute__((address_space(3))) uint8_t*)p;
+}
+__device__ __forceinline__ lds_u64* lds_word(uint32_t off) { return (lds_u64*)(size_t)off; }
+__device__ __forceinline__ void lds_add(lds_u64* p, uint64_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_sub(lds_u64* p, uint64_t v) {
+    __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // 64-bit packed bin increment for a staged word {c0, c1, c2, level}.
 __device__ __forceinline__ uint64_t packed_value(uint32_t w) {
     const uint32_t lo = (w & 0xFFu) | (((w >> 8) & 0xFFu) << 18);
@@ -535,17 +548,73 @@ __device__ __forceinline__ void tile_wide(const Job& j, int tile, uint8_t* lds) 
 }
 
 // STREAM layout: one wavefront per workgroup, 64 output columns, a run of
-// `rows` output rows.  Same packed bins as the fast path, but only the
-// 2r+4 image rows around the window are staged, in a ring, so the
-// LDS a workgroup needs is its histogram plus a few KB: several wavefronts
-// fit on a CU and runs can be long (the (2r+1)^2 first window is paid once
-// per run).  Image rows are fetched two rows ahead into registers.
-//   LDS: [histogram: bins x 64 lanes x 8 B][ring: (2R+4) rows x (64+2R) words]
+// `rows` output rows.  Only the 2r+4 image rows around the window are
+// staged, in a ring, so the LDS a workgroup needs is its histogram plus a
+// few KB: several wavefronts fit on a CU and runs can be long.  Image rows
+// are fetched two rows ahead into registers.
+//   LDS: [histogram: bins x 64 lanes x 8 B]
+//        [ring: (2R+4) rows x (64+2R) entries -- or, while a run's first
+//         window is built from column histograms, those]
 //        [output row buffer: 192 B]
 //   Ring slot of image row g: (g - (ya - R)) mod (2R+4).
 // Ring rows beyond the 2r+1 of a window: the entering row and the two rows
 // fetched ahead.
 constexpr int kStreamRingExtra = 4;
+
+// (a << 9) + b as one instruction.  Written out because the compiler turns
+// (x >> s) << 9 into a shift and a mask, and then needs a third instruction
+// for the add.
+__device__ __forceinline__ uint32_t shl9_add(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, 9, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Ring entries.  Each window update needs a pixel's bin increment and its
+// level; the entry is what makes both cheap for the bin format in use.
+//   4 bytes (F16 bins, and F18 bins with 64 scanned levels): the staged word
+//     {c0, c1, c2, level}.
+//   8 bytes (F18 bins, at most 32 scanned levels): the increment itself,
+//     count bit 54 set, with the level in bits 55..63 -- the count field's
+//     upper bits, which one pixel's increment leaves zero; an update masks
+//     them off (1 instruction) instead of assembling 18-bit fields.
+template <bool W8>
+struct RingFmt;
+
+template <>
+struct RingFmt<false> {
+    using T = uint32_t;
+    static __device__ __forceinline__ T entry(uint32_t c0, uint32_t c1, uint32_t c2, const Job& j) {
+        return staged_word(c0, c1, c2, j);
+    }
+    static __device__ __forceinline__ T outside(const Job& j) { return (uint32_t)j.trash << 24; }
+    static __device__ __forceinline__ uint32_t bin(T e) { return e >> 24; }
+    static __device__ __forceinline__ uint32_t bin_field(T e) { return e >> 24; }
+    template <bool F16>
+    static __device__ __forceinline__ uint64_t inc(T e) { return BinFmt<F16>::inc(e); }
+};
+
+template <>
+struct RingFmt<true> {
+    using T = uint64_t;
+    static __device__ __forceinline__ T entry(uint32_t c0, uint32_t c1, uint32_t c2, const Job& j) {
+        uint32_t lev = level_of(c0 + c1 + c2, (uint32_t)j.levels, j.paper != 0);
+        if (lev >= (uint32_t)j.levels) lev = (uint32_t)j.white;  // paper form: pure white
+        const uint32_t lo = c0 | (c1 << 18);
+        const uint32_t hi = (c2 << 4) | (1u << 22) | (lev << 23);
+        return ((uint64_t)hi << 32) | lo;
+    }
+    static __device__ __forceinline__ T outside(const Job& j) {
+        return (uint64_t)((1u << 22) | ((uint32_t)j.trash << 23)) << 32;
+    }
+    static __device__ __forceinline__ uint32_t bin(T e) { return (uint32_t)(e >> 55); }
+    static __device__ __forceinline__ uint32_t bin_field(T e) { return (uint32_t)(e >> 55); }
+    template <bool F16>
+    static __device__ __forceinline__ uint64_t inc(T e) {
+        static_assert(!F16, "8-byte entries carry F18 increments");
+        return e & 0x007FFFFFFFFFFFFFull;
+    }
+};
 
 struct RowBytes {
     uint32_t a0, a1, a2, b0, b1, b2;  // pixels at columns lane and lane + 64
@@ -578,12 +647,59 @@ __device__ __forceinline__ void stream_load_row(const Job& j, int x0, int gy, Ro
     }
 }
 
-template <int R>
-__device__ __forceinline__ void stream_write_row(const Job& j, uint32_t* slot, const RowBytes& rb) {
+template <int R, bool W8>
+__device__ __forceinline__ void stream_write_row(const Job& j, typename RingFmt<W8>::T* slot, const RowBytes& rb) {
+    using RF = RingFmt<W8>;
     const int lane = threadIdx.x & 63;
-    const uint32_t trash_word = (uint32_t)j.trash << 24;
-    slot[lane] = rb.ina ? staged_word(rb.a0, rb.a1, rb.a2, j) : trash_word;
-    if (R > 0 && lane < 2 * R) slot[lane + 64] = rb.inb ? staged_word(rb.b0, rb.b1, rb.b2, j) : trash_word;
+    const typename RF::T out = RF::outside(j);
+    slot[lane] = rb.ina ? RF::entry(rb.a0, rb.a1, rb.a2, j) : out;
+    if (R > 0 && lane < 2 * R) slot[lane + 64] = rb.inb ? RF::entry(rb.b0, rb.b1, rb.b2, j) : out;
+}
+
+// Image pixel p of the (64+2R)-wide block whose top-left pixel is
+// (x0 - R, y0 - R): its entry (outside pixels get the trash level), loaded
+// with clamped coordinates so that the loads need no branch.
+template <int R, bool W8>
+struct PixelAt {
+    static constexpr int TW = 64 + 2 * R;
+    int row, col;
+    uint32_t c0, c1, c2;
+    bool in;
+    __device__ __forceinline__ void load(const Job& j, int x0, int y0, int p) {
+        row = p / TW;
+        col = p - row * TW;
+        const int gy = y0 - R + row;
+        const int gx = x0 - R + col;
+        in = gy >= 0 && gy < j.height && gx >= 0 && gx < j.width;
+        const int gyc = min(max(gy, 0), j.height - 1);
+        const int gxc = min(max(gx, 0), j.width - 1);
+        gsrc_t q = gsrc(j.src) + (size_t)gyc * (size_t)j.stride + 3 * gxc;
+        c0 = q[0];
+        c1 = q[1];
+        c2 = q[2];
+    }
+    __device__ __forceinline__ typename RingFmt<W8>::T entry(const Job& j) const {
+        return in ? RingFmt<W8>::entry(c0, c1, c2, j) : RingFmt<W8>::outside(j);
+    }
+};
+
+// Stage rows y0-R .. y0-R+nrows-1 of the strip (64+2R columns) into the
+// ring, slot k holding row y0-R+k; sixteen pixels per lane in flight (one
+// wavefront per CU SIMD leaves little else to hide the memory latency).
+template <int R, bool W8>
+__device__ __forceinline__ void stage_ring(const Job& j, int x0, int y0, int nrows, typename RingFmt<W8>::T* ring) {
+    constexpr int CH = 16;
+    constexpr int TW = 64 + 2 * R;
+    const int lane = threadIdx.x & 63;
+    const int npx = TW * nrows;
+    for (int base = lane; base < npx; base += CH * 64) {
+        PixelAt<R, W8> px[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) px[i].load(j, x0, y0, min(base + i * 64, npx - 1));
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (base + i * 64 < npx) ring[base + i * 64] = px[i].entry(j);
+    }
 }
 
 template <int R, int SB>
@@ -593,7 +709,10 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
     constexpr int RB = kStreamRingExtra + 2 * R;  // ring rows
     constexpr uint32_t BS = 64u * 8u;
     constexpr bool F16 = R <= 7;
+    constexpr bool W8 = stream_wide_ring(R, SB);
     using Fmt = BinFmt<F16>;
+    using RF = RingFmt<W8>;
+    using T = typename RF::T;
     const int lane = threadIdx.x & 63;
     const int scan = j.scan;
     const int tx = unit % j.tiles_x;
@@ -602,23 +721,57 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
     const int ya = j.row_begin + ty * j.rows;
     const int yb = min(ya + j.rows, j.row_end);
     uint8_t* hl = lds + lane * 8;
-    uint32_t* ring = reinterpret_cast<uint32_t*>(lds + (size_t)j.bins * BS);
-    uint8_t* obuf = reinterpret_cast<uint8_t*>(ring + RB * TW);  // one output row, 192 bytes
+    // bin row of an entry for this lane: level * 512 + lane * 8 (as an LDS
+    // offset, so that the shift-add is the whole address computation)
+    const uint32_t lane_off = lds_offset(hl);
+    auto bin_ptr = [&](T e) { return lds_word(shl9_add(RF::bin_field(e), lane_off)); };
+    uint8_t* region = lds + (size_t)j.bins * BS;
+    T* ring = reinterpret_cast<T*>(region);
+    uint8_t* obuf = region + stream_ring_bytes(j);  // one output row, 192 bytes
     auto slot = [&](int g) { return ring + ((g - (ya - R)) % RB) * TW; };
 
-    // rows ya-R .. ya+R+1 (ring slots 0 .. 2R+1)
-    {
-        TileGeom g;
-        g.x0 = x0;
-        g.y0 = ya;
-        g.yend = ya + 2 * R + 2;
-        g.tw = TW;
-        g.th = 2 * R + 2;
-        stage_packed<TW>(j, g, ring);
+    if (j.colfirst) {
+        // First window from column histograms, built in the ring region
+        // before the ring is staged: row k of column c at colh + k*CW + c*8,
+        // levels >= scan (paper white, outside pixels) in a sink row.  The
+        // (64+2R) x (2R+1) window pixels are read from the image, spread
+        // over the lanes (no two lanes of one instruction share a column).
+        constexpr int CW = TW * 8;
+        constexpr int NP = SPAN * TW;
+        constexpr int CH = 12;
+        uint8_t* colh = region;
+        const int n16 = (scan + 1) * CW / 16;
+        for (int e = lane; e < n16; e += 64) *reinterpret_cast<uint4*>(colh + e * 16) = make_uint4(0u, 0u, 0u, 0u);
+        lds_order();
+        for (int base = lane; base < NP; base += CH * 64) {
+            PixelAt<R, W8> px[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) px[i].load(j, x0, ya, min(base + i * 64, NP - 1));
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const T e = px[i].entry(j);
+                const uint32_t k = min(RF::bin(e), (uint32_t)scan);
+                if (base + i * 64 < NP)
+                    lds_add(reinterpret_cast<uint64_t*>(colh + k * CW + px[i].col * 8), RF::template inc<F16>(e));
+            }
+        }
+        lds_order();
+#pragma unroll 1
+        for (int k = 0; k < scan; ++k) {
+            const uint64_t* col = reinterpret_cast<const uint64_t*>(colh + k * CW) + lane;
+            uint64_t acc = 0;
+#pragma unroll
+            for (int i = 0; i < SPAN; ++i) acc += col[i];
+            *reinterpret_cast<uint64_t*>(hl + k * BS) = acc;
+        }
+    } else {
+        for (int k = 0; k < j.bins; ++k) *reinterpret_cast<uint64_t*>(hl + k * BS) = 0;
     }
-    for (int k = 0; k < j.bins; ++k) *reinterpret_cast<uint64_t*>(hl + k * BS) = 0;
-    // the ring is read across lanes: keep every read after every write (one
-    // wavefront, and LDS executes its operations in issue order)
+    // the ring (rows ya-R .. ya+R+1, slots 0 .. 2R+1) replaces the column
+    // histograms; it is read across lanes: keep every read after every
+    // write (one wavefront, and LDS executes its operations in issue order)
+    lds_order();
+    stage_ring<R, W8>(j, x0, ya, 2 * R + 2, ring);
     lds_order();
     // rows ya+2+R and ya+3+R are fetched now and staged at the top of the
     // first loop iteration
@@ -626,15 +779,15 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
     stream_load_row<R>(j, x0, ya + 2 + R, q0);
     stream_load_row<R>(j, x0, ya + 3 + R, q1);
 
-    // first window: slots 0 .. 2R
-    {
-        const uint32_t* t = ring + lane;
-        uint32_t w[SPAN];
+    if (!j.colfirst) {
+        // first window: slots 0 .. 2R
+        const T* t = ring + lane;
+        T w[SPAN];
 #pragma unroll
         for (int i = 0; i < SPAN; ++i) w[i] = t[i];
 #pragma unroll 1
         for (int dy = 0; dy < SPAN; ++dy) {
-            uint32_t cur[SPAN];
+            T cur[SPAN];
 #pragma unroll
             for (int i = 0; i < SPAN; ++i) cur[i] = w[i];
             t += TW;
@@ -644,14 +797,14 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
             }
 #pragma unroll
             for (int i = 0; i < SPAN; ++i)
-                lds_add(reinterpret_cast<uint64_t*>(hl + (cur[i] >> 24) * BS), Fmt::inc(cur[i]));
+                lds_add(bin_ptr(cur[i]), RF::template inc<F16>(cur[i]));
         }
     }
-    // words of the step ya -> ya+1: leaving row ya-R, entering row ya+1+R
-    uint32_t wo[SPAN], wn[SPAN];
+    // entries of the step ya -> ya+1: leaving row ya-R, entering row ya+1+R
+    T wo[SPAN], wn[SPAN];
     {
-        const uint32_t* so = slot(ya - R) + lane;
-        const uint32_t* sn = slot(ya + 1 + R) + lane;
+        const T* so = slot(ya - R) + lane;
+        const T* sn = slot(ya + 1 + R) + lane;
 #pragma unroll
         for (int i = 0; i < SPAN; ++i) {
             wo[i] = so[i];
@@ -661,7 +814,7 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
     ModeBins<SB> mb;
     mode_load<SB>(mb, hl, scan);
 
-    // One output row y, then the step y -> y+1 and the words of the next step.
+    // One output row y, then the step y -> y+1 and the entries of the next step.
     auto row_step = [&](int y, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
         const uint32_t best = mode_reduce<SB, F16>(mb, scan);
@@ -671,13 +824,13 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
         if (FULL || y + 1 < yb) {
 #pragma unroll
             for (int i = 0; i < SPAN; ++i) {
-                lds_sub(reinterpret_cast<uint64_t*>(hl + (wo[i] >> 24) * BS), Fmt::inc(wo[i]));
-                lds_add(reinterpret_cast<uint64_t*>(hl + (wn[i] >> 24) * BS), Fmt::inc(wn[i]));
+                lds_sub(bin_ptr(wo[i]), RF::template inc<F16>(wo[i]));
+                lds_add(bin_ptr(wn[i]), RF::template inc<F16>(wn[i]));
             }
             if (FULL || y + 2 < yb) {
                 // step y+1 -> y+2 removes row y+1-R and adds row y+2+R
-                const uint32_t* so = slot(y + 1 - R) + lane;
-                const uint32_t* sn = slot(y + 2 + R) + lane;
+                const T* so = slot(y + 1 - R) + lane;
+                const T* sn = slot(y + 2 + R) + lane;
 #pragma unroll
                 for (int i = 0; i < SPAN; ++i) {
                     wo[i] = so[i];
@@ -697,8 +850,8 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
     int y = ya;
 #pragma unroll 1
     for (; y + 5 < yb; y += 2) {
-        stream_write_row<R>(j, slot(y + 2 + R), q0);
-        stream_write_row<R>(j, slot(y + 3 + R), q1);
+        stream_write_row<R, W8>(j, slot(y + 2 + R), q0);
+        stream_write_row<R, W8>(j, slot(y + 3 + R), q1);
         lds_order();
         stream_load_row<R>(j, x0, y + 4 + R, q0);
         stream_load_row<R>(j, x0, y + 5 + R, q1);
@@ -707,8 +860,8 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
     }
 #pragma unroll 1
     for (; y < yb; y += 2) {
-        if (y + 2 < yb) stream_write_row<R>(j, slot(y + 2 + R), q0);
-        if (y + 3 < yb) stream_write_row<R>(j, slot(y + 3 + R), q1);
+        if (y + 2 < yb) stream_write_row<R, W8>(j, slot(y + 2 + R), q0);
+        if (y + 3 < yb) stream_write_row<R, W8>(j, slot(y + 3 + R), q1);
         lds_order();
         if (y + 4 < yb) stream_load_row<R>(j, x0, y + 4 + R, q0);
         if (y + 5 < yb) stream_load_row<R>(j, x0, y + 5 + R, q1);

@@ -43,7 +43,7 @@ struct Job {
     int32_t white;      // bin of the paper form's extra pure-white level
     int32_t trash;      // bin of pixels outside the image
     int32_t bins;       // bins per lane
-    int32_t pad0;
+    int32_t colfirst;   // streamed layout: first window built from column histograms
 };
 
 // Work-queue form of a batch: jobs[] in queue order, first_tile[i] the
@@ -64,6 +64,14 @@ size_t lds_bytes(const Job& j);
 // radius, levels, paper): the levels 0..L-1 first -- rounded up to a multiple
 // of 8 empty bins on the fast path -- then the paper form's white level,
 // then the bin for pixels outside the image.
+//
+// The streamed layout builds a run's first window either directly --
+// (2r+1)^2 bin updates per lane -- or from column histograms: per column of
+// the strip a histogram of its 2r+1 window rows (the (64+2r)(2r+1) pixels
+// spread over the 64 lanes), then per level the sum of 2r+1 neighbouring
+// columns.  The second costs ~(2r+1) reads per scanned level instead of
+// ~(2r+1) updates per window row; it is used when the window is wide for
+// the level count.
 inline void set_layout(Job& j) {
     j.fast = ((j.hist == OILPAINT_HIST_PACKED || j.hist == OILPAINT_HIST_STREAM) && j.lanes == 64 &&
               j.radius <= kPackedMaxRadius && j.levels <= 64) ? 1 : 0;
@@ -71,6 +79,24 @@ inline void set_layout(Job& j) {
     j.white = j.scan;
     j.trash = j.scan + (j.paper ? 1 : 0);
     j.bins = j.trash + 1;
+    j.colfirst = (j.hist == OILPAINT_HIST_STREAM && (2 * j.radius + 1) * 10 >= 4 * j.scan + 20) ? 1 : 0;
+}
+
+// Streamed layout, ring entries: 8 bytes (the bin increment itself, level
+// in its top bits) for radius >= 8 with at most 32 scanned levels, else 4
+// bytes (the staged word).
+__host__ __device__ constexpr bool stream_wide_ring(int radius, int scan) { return radius >= 8 && scan <= 32; }
+
+// Streamed layout: bytes of the ring region, (2r+4) rows of 64+2r entries;
+// while a run's first window is built from column histograms the region
+// holds them instead (scan + 1 rows of 64+2r 8-byte entries), so it is the
+// larger of the two.
+__host__ __device__ inline size_t stream_ring_bytes(const Job& j) {
+    const size_t tw = 64 + 2 * (size_t)j.radius;
+    const size_t ring = (2 * (size_t)j.radius + 4) * tw * (stream_wide_ring(j.radius, j.scan) ? 8 : 4);
+    const size_t cols = j.colfirst ? (size_t)(j.scan + 1) * tw * 8 : 0;
+    const size_t b = ring > cols ? ring : cols;
+    return (b + 15) & ~(size_t)15;
 }
 
 // Per-radius kernels (oilpaint_k_fast_*.hip, oilpaint_k_stream_*.hip):
