@@ -118,6 +118,65 @@ class Timer:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps  # ms per call
 
+    def each(self, fn, reps: int) -> list:
+        """Sorted per-call times (ms), an event pair around every call."""
+        torch = self.torch
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return sorted(a.elapsed_time(b) for a, b in ev)
+
+
+def transfers(torch, img) -> dict:
+    """Host-device copy times of one image (pinned host buffer): context for
+    callers that hand over host images; the filter itself takes device
+    pointers and the timed figures exclude copies."""
+    host = torch.from_numpy(img).pin_memory()
+    dev = torch.empty(host.shape, dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        dev.copy_(host, non_blocking=True)
+        host.copy_(dev, non_blocking=True)
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn in (("h2d", lambda: dev.copy_(host, non_blocking=True)),
+                     ("d2h", lambda: host.copy_(dev, non_blocking=True))):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        out[name + "_ms"] = round(ms, 4)
+        out[name + "_gbs"] = round(img.nbytes / (ms / 1e3) / 1e9, 1)
+    out["bytes"] = int(img.nbytes)
+    return out
+
+
+def oracle_timings(oracle_mod, synth, threads: int) -> dict:
+    """The oracle on the 256x256 case, one thread and all threads, and on one
+    1920x1080 run (r = 5, L = 20) on one thread: the paper's serial and
+    row-parallel forms (context beside cpu_baseline)."""
+    out = {}
+    small, r, L = synth.small_case()
+    for name, th in (("256x256_r2_L20_1thread", 1), ("256x256_r2_L20_allthreads", threads)):
+        t0 = time.perf_counter()
+        oracle_mod.oilpaint_ref(small, r, L, nthreads=th)
+        dt = time.perf_counter() - t0
+        out[name] = {"s": round(dt, 4), "mp_per_s": round(small.shape[0] * small.shape[1] / 1e6 / dt, 3),
+                     "threads": th}
+    img = synth.fhd_image()
+    t0 = time.perf_counter()
+    oracle_mod.oilpaint_ref(img, 5, 20, nthreads=1)
+    dt = time.perf_counter() - t0
+    out["1920x1080_r5_L20_1thread"] = {"s": round(dt, 3), "mp_per_s": round(img.shape[0] * img.shape[1] / 1e6 / dt, 3),
+                                       "threads": 1}
+    return out
+
 
 def bench_plain(torch, B, synth, timer, steps, warmup):
     img = synth.fhd_image()
@@ -133,9 +192,13 @@ def bench_plain(torch, B, synth, timer, steps, warmup):
     ms_step = timer.time(step, steps, warmup)
     per = {}
     for r, L in runs:
-        ms = timer.time(lambda: B.oilpaint_async(src, dst, r, L), max(steps, 10), 2)
+        reps = max(steps, 20)
+        ms = timer.time(lambda: B.oilpaint_async(src, dst, r, L), reps, 3)
+        each = timer.each(lambda: B.oilpaint_async(src, dst, r, L), reps)
         v = B.pick_variant(img.shape[1], img.shape[0], r, L)
         per["r%d_L%d" % (r, L)] = {"r": r, "L": L, "ms": round(ms, 5), "mp_per_s": round(mp / (ms / 1e3), 1),
+                                   "median_ms": round(each[len(each) // 2], 5), "min_ms": round(each[0], 5),
+                                   "reps": reps,
                                    "lds_gbs": round(lds_bytes_per_pixel(r, L) * mp * 1e6 / (ms / 1e3) / 1e9, 1),
                                    "kernel": kernel_name(r, L, v), "variant": list(v.as_tuple())}
     total_bytes = sum(lds_bytes_per_pixel(r, L) for r, L in runs) * mp * 1e6
@@ -419,6 +482,8 @@ def main():
         res["serving"] = bench_serving(torch, B, synth, serve, args.serve_requests, oracle_mod)
         log("cpu baseline ...")
         res["cpu_baseline"] = cpu_baseline(oracle_mod, img, synth.FHD_SWEEP)
+        res["oracle_timings"] = oracle_timings(oracle_mod, synth, res["cpu_baseline"]["cores"])
+        res["transfers_1920x1080"] = transfers(torch, img)
         # parity of the timed configuration: the sweep's outputs against the oracle
         bad = 0
         for r, L in synth.FHD_SWEEP:
