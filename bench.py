@@ -74,6 +74,8 @@ def kernel_name(r: int, L: int, v) -> str:
     scan = (L + 7) // 8 * 8
     if v.hist == 1:  # streamed rows
         return "k_plain_stream<%d, %d>" % (r, 32 if scan <= 32 else 64)
+    if v.hist == 3:  # streamed rows, 8-byte entries
+        return "k_plain_stream8<%d>" % r
     if v.hist == 0 and v.lanes == 64 and r <= 15 and L <= 64:
         return "k_plain_fast<%d, %d>" % (r, 16 if scan <= 16 else 32 if scan <= 32 else 64)
     return "k_plain"
@@ -366,6 +368,32 @@ def _pmc_rows(folder: str, counter: str):
     return out
 
 
+def launch_threads(w: int, h: int, variant) -> int:
+    """Work-items of a plain launch of a w x h image with a resolved variant
+    (rows, waves, hist, lanes, per_cu): one workgroup of 64 x waves per tile
+    (the profiler's grid size)."""
+    rows, waves, lanes = variant[0], variant[1], variant[3]
+    tiles = -(-w // lanes) * -(-h // (waves * rows))
+    return tiles * 64 * waves
+
+
+def hbm_entry(folder: str, name: str, variant, w: int, h: int, scale: dict) -> dict:
+    """Counters per dispatch of one sweep run: the dispatches of its kernel
+    with its grid size."""
+    import statistics
+    grid = launch_threads(w, h, variant)
+    e = {"kernel": name, "variant": variant, "grid_threads": grid}
+    for c, sub in (("FETCH_SIZE", "sweep_fetch"), ("WRITE_SIZE", "sweep_write")):
+        vals = [v for n, g, v in _pmc_rows(os.path.join(folder, sub), c) if n == name and g == grid]
+        e[c.lower() + "_kib_per_dispatch"] = round(statistics.median(vals), 1) if vals else None
+        e[c.lower() + "_dispatches"] = len(vals)
+    if e["fetch_size_kib_per_dispatch"] is not None and e["write_size_kib_per_dispatch"] is not None:
+        e["hbm_bytes_per_launch"] = round(e["fetch_size_kib_per_dispatch"] * 1024 * scale["FETCH_SIZE"] +
+                                          e["write_size_kib_per_dispatch"] * 1024 * scale["WRITE_SIZE"])
+        e["algorithmic_hbm_bytes"] = 6 * w * h
+    return e
+
+
 def write_hbm_summary(folder: str, commands: list[str]):
     """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE over
     `bench.py --quick` and over `bench.py --copy-ref`, in the sub-folders
@@ -385,17 +413,7 @@ def write_hbm_summary(folder: str, commands: list[str]):
     launches = {}
     for r, L in synth.FHD_SWEEP:
         v = B.pick_variant(w, h, r, L)
-        name = kernel_name(r, L, v)
-        e = {"kernel": name, "variant": list(v.as_tuple())}
-        for c, sub in (("FETCH_SIZE", "sweep_fetch"), ("WRITE_SIZE", "sweep_write")):
-            vals = [v_ for n, g, v_ in _pmc_rows(os.path.join(folder, sub), c) if n == name]
-            e[c.lower() + "_kib_per_dispatch"] = round(statistics.median(vals), 1) if vals else None
-            e[c.lower() + "_dispatches"] = len(vals)
-        if e["fetch_size_kib_per_dispatch"] is not None and e["write_size_kib_per_dispatch"] is not None:
-            e["hbm_bytes_per_launch"] = round(e["fetch_size_kib_per_dispatch"] * 1024 * scale["FETCH_SIZE"] +
-                                              e["write_size_kib_per_dispatch"] * 1024 * scale["WRITE_SIZE"])
-            e["algorithmic_hbm_bytes"] = 6 * w * h
-        launches["r%d_L%d" % (r, L)] = e
+        launches["r%d_L%d" % (r, L)] = hbm_entry(folder, kernel_name(r, L, v), list(v.as_tuple()), w, h, scale)
     out = {"kernel_source_sha": kernel_source_hash(), "workload": "fhd_1920x1080_sweep",
            "commands": commands, "copy_reference": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
                                                      "scale": {k: round(v_, 4) for k, v_ in scale.items()}},

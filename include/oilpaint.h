@@ -124,10 +124,15 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *                         (waves = 1, lanes = 64), radius <= 15, levels <= 64
  *   OILPAINT_HIST_WIDE    32-bit count and sums, pixels read from device
  *                         memory; any level count and radius up to 2051
+ *   OILPAINT_HIST_STREAM8 OILPAINT_HIST_STREAM whose on-chip rows hold each
+ *                         pixel's ready-made bin increment (8 bytes instead
+ *                         of 4): fewer instructions per window update, twice
+ *                         the row storage; radius 8..15, levels <= 32
  * ------------------------------------------------------------------------- */
-#define OILPAINT_HIST_PACKED 0
-#define OILPAINT_HIST_STREAM 1
-#define OILPAINT_HIST_WIDE   2
+#define OILPAINT_HIST_PACKED  0
+#define OILPAINT_HIST_STREAM  1
+#define OILPAINT_HIST_WIDE    2
+#define OILPAINT_HIST_STREAM8 3
 
 typedef struct oilpaint_variant {
     int32_t rows;   /* output rows per lane, >= 1; 0: derived from per_cu */

@@ -29,6 +29,7 @@ ERR_UNSUPPORTED = -8
 HIST_PACKED = 0
 HIST_STREAM = 1
 HIST_WIDE = 2
+HIST_STREAM8 = 3
 FLAG_PAPER = 1
 
 

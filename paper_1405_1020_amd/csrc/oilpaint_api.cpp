@@ -48,7 +48,7 @@ size_t lds_bytes(const Job& j) {
     const size_t nb = (size_t)j.bins;
     const size_t lanes = (size_t)j.lanes;
     if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
-    if (j.hist == OILPAINT_HIST_STREAM) return nb * 64 * 8 + stream_ring_bytes(j) + 192;
+    if (is_stream(j.hist)) return nb * 64 * 8 + stream_ring_bytes(j) + 192;
     const size_t tw = lanes + 2 * (size_t)j.radius;
     const size_t th = (size_t)waves * (size_t)j.rows + 2 * (size_t)j.radius;
     const size_t tile = (tw * th * 4 + 15) & ~(size_t)15;
@@ -120,6 +120,9 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     } else if (v.hist == OILPAINT_HIST_STREAM) {
         if (j.radius > kPackedMaxRadius || j.levels > 64 || v.waves != 1 || v.lanes != 64)
             return OILPAINT_ERR_UNSUPPORTED;
+    } else if (v.hist == OILPAINT_HIST_STREAM8) {
+        if (j.radius < 8 || j.radius > kPackedMaxRadius || j.levels > 32 || v.waves != 1 || v.lanes != 64)
+            return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_WIDE) {
         if (j.radius > kWideMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
     } else {
@@ -132,9 +135,14 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     set_layout(j);
     const DeviceInfo d = device_info(device);
     const size_t limit = d.ok ? d.lds_per_block : 65536;
+    // the column-histogram first window is an optimisation: dropped first
+    // when the footprint does not fit
+    if (j.colfirst && lds_bytes(j) + kStaticLds > limit) j.colfirst = 0;
     while (lds_bytes(j) + kStaticLds > limit) {
         if (v.rows != 0 || j.rows == 1) return OILPAINT_ERR_UNSUPPORTED;
         j.rows = std::max(1, j.rows / 2);
+        set_layout(j);
+        j.colfirst = 0;
     }
     const int band = j.row_end - j.row_begin;
     j.tiles_x = (j.width + j.lanes - 1) / j.lanes;

@@ -702,14 +702,15 @@ __device__ __forceinline__ void stage_ring(const Job& j, int x0, int y0, int nro
     }
 }
 
-template <int R, int SB>
+// W8: 8-byte ring entries (OILPAINT_HIST_STREAM8: radius >= 8, SB = 32).
+template <int R, int SB, bool W8>
 __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds) {
+    static_assert(!W8 || (R >= 8 && SB == 32), "8-byte entries: F18 bins, at most 32 scanned levels");
     constexpr int SPAN = 2 * R + 1;
     constexpr int TW = 64 + 2 * R;
     constexpr int RB = kStreamRingExtra + 2 * R;  // ring rows
     constexpr uint32_t BS = 64u * 8u;
     constexpr bool F16 = R <= 7;
-    constexpr bool W8 = stream_wide_ring(R, SB);
     using Fmt = BinFmt<F16>;
     using RF = RingFmt<W8>;
     using T = typename RF::T;
@@ -894,15 +895,16 @@ __device__ __forceinline__ int job_of(const BatchArgs& a, int32_t t) {
     return lo;
 }
 
-// One class of a batch in the streamed layout (radius R, scan bucket SB).
-template <int R, int SB>
+// One class of a batch in the streamed layout (radius R, scan bucket SB,
+// ring entry size).
+template <int R, int SB, bool W8>
 __device__ __forceinline__ void batch_stream(const BatchArgs& a, uint8_t* lds) {
     for (;;) {
         const int32_t t = next_tile_wave(a.counter);
         if (t >= a.ntiles) break;
         const int i = job_of(a, t);
         const Job jb = a.jobs[i];
-        tile_stream<R, SB>(jb, t - a.first_tile[i], lds);
+        tile_stream<R, SB, W8>(jb, t - a.first_tile[i], lds);
     }
 }
 

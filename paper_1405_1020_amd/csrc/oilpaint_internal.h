@@ -64,37 +64,46 @@ size_t lds_bytes(const Job& j);
 // radius, levels, paper): the levels 0..L-1 first -- rounded up to a multiple
 // of 8 empty bins on the fast path -- then the paper form's white level,
 // then the bin for pixels outside the image.
+inline bool is_stream(int hist) { return hist == OILPAINT_HIST_STREAM || hist == OILPAINT_HIST_STREAM8; }
+
+// Streamed layout: bytes of the ring of (2r+4) rows of 64+2r entries (8 bytes
+// each for OILPAINT_HIST_STREAM8, else 4), and of the column histograms a
+// run's first window may be built from (scan + 1 rows of 64+2r 8-byte
+// entries), which take the ring's place while they live.
+__host__ __device__ inline size_t stream_ring_only_bytes(const Job& j) {
+    return (2 * (size_t)j.radius + 4) * (64 + 2 * (size_t)j.radius) * (j.hist == OILPAINT_HIST_STREAM8 ? 8 : 4);
+}
+__host__ __device__ inline size_t stream_colh_bytes(const Job& j) {
+    return (size_t)(j.scan + 1) * (64 + 2 * (size_t)j.radius) * 8;
+}
+
 //
 // The streamed layout builds a run's first window either directly --
 // (2r+1)^2 bin updates per lane -- or from column histograms: per column of
 // the strip a histogram of its 2r+1 window rows (the (64+2r)(2r+1) pixels
 // spread over the 64 lanes), then per level the sum of 2r+1 neighbouring
 // columns.  The second costs ~(2r+1) reads per scanned level instead of
-// ~(2r+1) updates per window row; it is used when the window is wide for
-// the level count.
+// ~(2r+1) updates per window row.  It is used when the window is wide for
+// the level count, and only when the column histograms fit in the ring's
+// place or the runs are short enough (at most 4(2r+1) rows) for the first
+// window to matter more than the larger on-chip footprint.
 inline void set_layout(Job& j) {
-    j.fast = ((j.hist == OILPAINT_HIST_PACKED || j.hist == OILPAINT_HIST_STREAM) && j.lanes == 64 &&
+    j.fast = ((j.hist == OILPAINT_HIST_PACKED || is_stream(j.hist)) && j.lanes == 64 &&
               j.radius <= kPackedMaxRadius && j.levels <= 64) ? 1 : 0;
     j.scan = j.fast ? (j.levels + 7) / 8 * 8 : j.levels;
     j.white = j.scan;
     j.trash = j.scan + (j.paper ? 1 : 0);
     j.bins = j.trash + 1;
-    j.colfirst = (j.hist == OILPAINT_HIST_STREAM && (2 * j.radius + 1) * 10 >= 4 * j.scan + 20) ? 1 : 0;
+    j.colfirst = 0;
+    if (is_stream(j.hist) && (2 * j.radius + 1) * 10 >= 4 * j.scan + 20)
+        j.colfirst = (stream_colh_bytes(j) <= stream_ring_only_bytes(j) || j.rows <= 4 * (2 * j.radius + 1)) ? 1 : 0;
 }
 
-// Streamed layout, ring entries: 8 bytes (the bin increment itself, level
-// in its top bits) for radius >= 8 with at most 32 scanned levels, else 4
-// bytes (the staged word).
-__host__ __device__ constexpr bool stream_wide_ring(int radius, int scan) { return radius >= 8 && scan <= 32; }
-
-// Streamed layout: bytes of the ring region, (2r+4) rows of 64+2r entries;
-// while a run's first window is built from column histograms the region
-// holds them instead (scan + 1 rows of 64+2r 8-byte entries), so it is the
-// larger of the two.
+// Streamed layout: bytes of the ring region (the ring, or while they live
+// the first window's column histograms).
 __host__ __device__ inline size_t stream_ring_bytes(const Job& j) {
-    const size_t tw = 64 + 2 * (size_t)j.radius;
-    const size_t ring = (2 * (size_t)j.radius + 4) * tw * (stream_wide_ring(j.radius, j.scan) ? 8 : 4);
-    const size_t cols = j.colfirst ? (size_t)(j.scan + 1) * tw * 8 : 0;
+    const size_t ring = stream_ring_only_bytes(j);
+    const size_t cols = j.colfirst ? stream_colh_bytes(j) : 0;
     const size_t b = ring > cols ? ring : cols;
     return (b + 15) & ~(size_t)15;
 }
@@ -106,22 +115,30 @@ extern const PlainKernel kFast_lo[8][3];
 extern const PlainKernel kFast_hi[8][3];
 extern const PlainKernel kStream_lo[8][2];
 extern const PlainKernel kStream_hi[8][2];
+// Streamed kernels with 8-byte ring entries (OILPAINT_HIST_STREAM8),
+// [radius - 8], levels <= 32.
+extern const PlainKernel kStream8[8];
 
 // Persistent batch kernels of the streamed layout (oilpaint_k_batch_*.hip),
 // indexed like kStream_*.
 typedef void (*BatchKernel)(BatchArgs);
 extern const BatchKernel kBatchStream_lo[8][2];
 extern const BatchKernel kBatchStream_hi[8][2];
+extern const BatchKernel kBatchStream8[8];
 
 // Kernel class of a batch job: 2 * radius + scan bucket (0: scan <= 32,
-// 1: scan <= 64) for the streamed layout, kGenericClass for every other
-// job (generic tile-staged and wide layouts, one kernel for all).  A batch
-// launches one persistent kernel per class present.
-constexpr int kGenericClass = 2 * (kPackedMaxRadius + 1);
+// 1: scan <= 64) for the streamed layout, 32 + radius - 8 for its 8-byte
+// form, kGenericClass for every other job (generic tile-staged and wide
+// layouts, one kernel for all).  A batch launches one persistent kernel per
+// class present.
+constexpr int kStream8Class = 2 * (kPackedMaxRadius + 1);
+constexpr int kGenericClass = kStream8Class + 8;
 constexpr int kBatchClasses = kGenericClass + 1;
 inline int batch_class(const Job& j) {
     if (j.hist == OILPAINT_HIST_STREAM && j.radius >= 0 && j.radius <= kPackedMaxRadius && j.scan <= 64)
         return 2 * j.radius + (j.scan <= 32 ? 0 : 1);
+    if (j.hist == OILPAINT_HIST_STREAM8 && j.radius >= 8 && j.radius <= kPackedMaxRadius && j.scan <= 32)
+        return kStream8Class + j.radius - 8;
     return kGenericClass;
 }
 

@@ -10,7 +10,7 @@ namespace {
 template <int R, int SB>
 __global__ __launch_bounds__(64) void k_batch_stream(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    batch_stream<R, SB>(a, lds);
+    batch_stream<R, SB, false>(a, lds);
 }
 
 }  // namespace

@@ -78,11 +78,13 @@ static hipError_t allow_lds(const void* kernel, size_t lds, int& done) {
 namespace {
 int g_fast_lds_done[kPackedMaxRadius + 1][3];
 int g_stream_lds_done[kPackedMaxRadius + 1][2];
+int g_stream8_lds_done[8];
 int g_plain_lds_done;
 int g_batch_lds_done[kBatchClasses];
 
 BatchKernel batch_kernel(int cls) {
     if (cls < 0 || cls >= kGenericClass) return k_batch;
+    if (cls >= kStream8Class) return kBatchStream8[cls - kStream8Class];
     const int r = cls >> 1, b = cls & 1;
     return r <= 7 ? kBatchStream_lo[r][b] : kBatchStream_hi[r - 8][b];
 }
@@ -93,7 +95,11 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
     if (tiles <= 0) return hipSuccess;
     PlainKernel k = k_plain;
     int* done = &g_plain_lds_done;
-    if (j.hist == OILPAINT_HIST_STREAM) {
+    if (j.hist == OILPAINT_HIST_STREAM8) {
+        if (j.radius < 8 || j.radius > kPackedMaxRadius || j.scan > 32 || waves != 1) return hipErrorInvalidValue;
+        k = kStream8[j.radius - 8];
+        done = &g_stream8_lds_done[j.radius - 8];
+    } else if (j.hist == OILPAINT_HIST_STREAM) {
         if (j.radius < 0 || j.radius > kPackedMaxRadius || j.scan > 64 || waves != 1) return hipErrorInvalidValue;
         const int b = j.scan <= 32 ? 0 : 1;
         k = j.radius <= 7 ? kStream_lo[j.radius][b] : kStream_hi[j.radius - 8][b];

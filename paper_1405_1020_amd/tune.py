@@ -1,8 +1,9 @@
 """Autotuner: the launch shape per (radius, levels).
 
 For each (radius, levels) the candidates -- streamed rows with several
-workgroup densities, tile-staged workgroups of 2 or 4 wavefronts with
-several densities -- are timed by the library itself (oilpaint_tune, HIP
+workgroup densities (and, for radius 8..15 with at most 32 levels, the
+same with 8-byte on-chip row entries), tile-staged workgroups of 2 or 4
+wavefronts with several densities -- are timed by the library itself (oilpaint_tune, HIP
 events around repeated launches on a representative image) and the fastest
 is installed with oilpaint_set_variant, so that oilpaint_async, batches and
 the request queue use it.  Shapes whose rows are derived from a workgroup
@@ -46,6 +47,9 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
     if radius <= 15 and levels <= 64:
         for per_cu in (2, 4, 8, 16, 32):
             out.append(B.Variant(0, 1, B.HIST_STREAM, 64, per_cu))
+    if 8 <= radius <= 15 and levels <= 32:
+        for per_cu in (2, 4, 8, 16):
+            out.append(B.Variant(0, 1, B.HIST_STREAM8, 64, per_cu))
     if radius <= 15 and levels <= 255:
         for waves in (2, 4):
             for per_cu in (1, 2, 4, 8):

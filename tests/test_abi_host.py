@@ -78,6 +78,21 @@ def test_pick_variant_shapes():
     assert B.pick_variant(20, 10, 1000, 20).hist == B.HIST_WIDE
 
 
+def test_stream8_limits():
+    # 8-byte on-chip row entries: radius 8..15 (effective) and <= 32 levels
+    ok = B.Variant(0, 1, B.HIST_STREAM8, 64, 4)
+    try:
+        assert B.set_variant(10, 32, ok) == B.OK
+        assert B.set_variant(8, 1, ok) == B.OK
+        assert B.set_variant(7, 20, ok) == B.ERR_UNSUPPORTED
+        assert B.set_variant(16, 20, ok) == B.ERR_UNSUPPORTED
+        assert B.set_variant(10, 33, ok) == B.ERR_UNSUPPORTED
+        assert B.set_variant(10, 20, B.Variant(0, 2, B.HIST_STREAM8, 64, 4)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(10, 20, B.Variant(0, 1, B.HIST_STREAM8, 32, 4)) == B.ERR_UNSUPPORTED
+    finally:
+        B.clear_variants()
+
+
 def test_kernel_integer_identities():
     # facts the kernels' integer arithmetic relies on, checked exhaustively
     # over their whole domains (no GPU, no oracle involved)
