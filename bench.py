@@ -76,6 +76,8 @@ def kernel_name(r: int, L: int, v) -> str:
         return "k_plain_stream<%d, %d>" % (r, 32 if scan <= 32 else 64)
     if v.hist == 3:  # streamed rows, 8-byte entries
         return "k_plain_stream8<%d>" % r
+    if v.hist == 4:  # column histograms
+        return "k_plain_column<%d>" % ((64 + 2 * r + 63) // 64)
     if v.hist == 0 and v.lanes == 64 and r <= 15 and L <= 64:
         return "k_plain_fast<%d, %d>" % (r, 16 if scan <= 16 else 32 if scan <= 32 else 64)
     return "k_plain"

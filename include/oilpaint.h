@@ -128,11 +128,21 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *                         pixel's ready-made bin increment (8 bytes instead
  *                         of 4): fewer instructions per window update, twice
  *                         the row storage; radius 8..15, levels <= 32
+ *   OILPAINT_HIST_COLUMN  per-column histograms of the window rows; each
+ *                         lane's window is the difference of two per-level
+ *                         prefix sums across the strip, so the work per
+ *                         output row does not grow with the radius (column
+ *                         histograms after Perreault and Hebert, "Median
+ *                         filtering in constant time", 2007); one wavefront
+ *                         of 64 lanes per workgroup, radius <= 255, any
+ *                         level count whose (levels + 1) x (64 + 2 radius)
+ *                         8-byte column histograms fit on chip
  * ------------------------------------------------------------------------- */
 #define OILPAINT_HIST_PACKED  0
 #define OILPAINT_HIST_STREAM  1
 #define OILPAINT_HIST_WIDE    2
 #define OILPAINT_HIST_STREAM8 3
+#define OILPAINT_HIST_COLUMN  4
 
 typedef struct oilpaint_variant {
     int32_t rows;   /* output rows per lane, >= 1; 0: derived from per_cu */

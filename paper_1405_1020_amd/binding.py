@@ -30,6 +30,7 @@ HIST_PACKED = 0
 HIST_STREAM = 1
 HIST_WIDE = 2
 HIST_STREAM8 = 3
+HIST_COLUMN = 4
 FLAG_PAPER = 1
 
 

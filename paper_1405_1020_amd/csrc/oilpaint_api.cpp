@@ -49,6 +49,10 @@ size_t lds_bytes(const Job& j) {
     const size_t lanes = (size_t)j.lanes;
     if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
     if (is_stream(j.hist)) return nb * 64 * 8 + stream_ring_bytes(j) + 192;
+    if (j.hist == OILPAINT_HIST_COLUMN) {
+        const size_t tw = 64 + 2 * (size_t)j.radius;
+        return ((nb * tw * 8 + 15) & ~(size_t)15) + (tw + 1) * 16 + 192;
+    }
     const size_t tw = lanes + 2 * (size_t)j.radius;
     const size_t th = (size_t)waves * (size_t)j.rows + 2 * (size_t)j.radius;
     const size_t tile = (tw * th * 4 + 15) & ~(size_t)15;
@@ -123,6 +127,8 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     } else if (v.hist == OILPAINT_HIST_STREAM8) {
         if (j.radius < 8 || j.radius > kPackedMaxRadius || j.levels > 32 || v.waves != 1 || v.lanes != 64)
             return OILPAINT_ERR_UNSUPPORTED;
+    } else if (v.hist == OILPAINT_HIST_COLUMN) {
+        if (j.radius > kColumnMaxRadius || v.waves != 1 || v.lanes != 64) return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_WIDE) {
         if (j.radius > kWideMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
     } else {
@@ -153,8 +159,10 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
 
 // The built-in launch shape (before any tuning result): streamed rows with
 // about eight one-wavefront workgroups per CU when the window and level
-// count allow it; otherwise tiles of four wavefronts, about two per CU, or
-// the wide layout; shrunk until the on-chip footprint fits.
+// count allow it; for radii 16..255 column histograms, about two
+// workgroups per CU, when they fit on chip; otherwise tiles of four
+// wavefronts, about two per CU, or the wide layout; shrunk until the
+// on-chip footprint fits.
 oilpaint_variant default_variant(int width, int height, int reff, int levels, bool paper, int device) {
     oilpaint_variant v;
     v.rows = 0;
@@ -164,6 +172,21 @@ oilpaint_variant default_variant(int width, int height, int reff, int levels, bo
         v.hist = OILPAINT_HIST_STREAM;
         v.per_cu = 8;
         return v;
+    }
+    if (reff > kPackedMaxRadius && reff <= kColumnMaxRadius) {
+        // column histograms when they fit on chip
+        v.waves = 1;
+        v.hist = OILPAINT_HIST_COLUMN;
+        v.per_cu = 2;
+        Job t{};
+        t.width = width;
+        t.height = height;
+        t.radius = reff;
+        t.levels = levels;
+        t.paper = paper ? 1 : 0;
+        t.row_begin = 0;
+        t.row_end = height;
+        if (apply_variant(t, v, device) == OILPAINT_OK) return v;
     }
     v.waves = 4;
     v.per_cu = 2;

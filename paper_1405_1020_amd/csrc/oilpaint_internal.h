@@ -16,6 +16,12 @@ namespace oilpaint_impl {
 constexpr int kPackedMaxRadius = 15;
 // Largest effective radius of the wide layout: 255 * 4103^2 < 2^32.
 constexpr int kWideMaxRadius = 2051;
+// Largest effective radius of the column layout: a column of 2r+1 pixels
+// keeps its count in 13 bits and its sums in 17, and a strip with its halo
+// spans at most kColumnChunks wavefront widths.
+constexpr int kColumnMaxRadius = 255;
+constexpr int kColumnChunks = 9;
+inline int column_chunks(int radius) { return (64 + 2 * radius + 63) / 64; }
 // Largest window pixel count the packed layout's division table covers.
 constexpr int kPackedMaxCount = 961;
 
@@ -88,6 +94,16 @@ __host__ __device__ inline size_t stream_colh_bytes(const Job& j) {
 // place or the runs are short enough (at most 4(2r+1) rows) for the first
 // window to matter more than the larger on-chip footprint.
 inline void set_layout(Job& j) {
+    if (j.hist == OILPAINT_HIST_COLUMN) {
+        // levels 0 .. L-1, then one sink row for outside pixels and the
+        // paper form's white level
+        j.fast = 0;
+        j.scan = j.levels;
+        j.white = j.trash = j.levels;
+        j.bins = j.levels + 1;
+        j.colfirst = 0;
+        return;
+    }
     j.fast = ((j.hist == OILPAINT_HIST_PACKED || is_stream(j.hist)) && j.lanes == 64 &&
               j.radius <= kPackedMaxRadius && j.levels <= 64) ? 1 : 0;
     j.scan = j.fast ? (j.levels + 7) / 8 * 8 : j.levels;
@@ -125,20 +141,26 @@ typedef void (*BatchKernel)(BatchArgs);
 extern const BatchKernel kBatchStream_lo[8][2];
 extern const BatchKernel kBatchStream_hi[8][2];
 extern const BatchKernel kBatchStream8[8];
+// Column-layout kernels (oilpaint_k_column.hip), [chunks - 1].
+extern const PlainKernel kColumn[kColumnChunks];
+extern const BatchKernel kBatchColumn[kColumnChunks];
 
 // Kernel class of a batch job: 2 * radius + scan bucket (0: scan <= 32,
 // 1: scan <= 64) for the streamed layout, 32 + radius - 8 for its 8-byte
-// form, kGenericClass for every other job (generic tile-staged and wide
-// layouts, one kernel for all).  A batch launches one persistent kernel per
-// class present.
+// form, 40 + chunks - 1 for the column layout, kGenericClass for every
+// other job (generic tile-staged and wide layouts, one kernel for all).  A
+// batch launches one persistent kernel per class present.
 constexpr int kStream8Class = 2 * (kPackedMaxRadius + 1);
-constexpr int kGenericClass = kStream8Class + 8;
+constexpr int kColumnClass = kStream8Class + 8;
+constexpr int kGenericClass = kColumnClass + kColumnChunks;
 constexpr int kBatchClasses = kGenericClass + 1;
 inline int batch_class(const Job& j) {
     if (j.hist == OILPAINT_HIST_STREAM && j.radius >= 0 && j.radius <= kPackedMaxRadius && j.scan <= 64)
         return 2 * j.radius + (j.scan <= 32 ? 0 : 1);
     if (j.hist == OILPAINT_HIST_STREAM8 && j.radius >= 8 && j.radius <= kPackedMaxRadius && j.scan <= 32)
         return kStream8Class + j.radius - 8;
+    if (j.hist == OILPAINT_HIST_COLUMN && j.radius >= 0 && j.radius <= kColumnMaxRadius)
+        return kColumnClass + column_chunks(j.radius) - 1;
     return kGenericClass;
 }
 

@@ -79,11 +79,13 @@ namespace {
 int g_fast_lds_done[kPackedMaxRadius + 1][3];
 int g_stream_lds_done[kPackedMaxRadius + 1][2];
 int g_stream8_lds_done[8];
+int g_column_lds_done[kColumnChunks];
 int g_plain_lds_done;
 int g_batch_lds_done[kBatchClasses];
 
 BatchKernel batch_kernel(int cls) {
     if (cls < 0 || cls >= kGenericClass) return k_batch;
+    if (cls >= kColumnClass) return kBatchColumn[cls - kColumnClass];
     if (cls >= kStream8Class) return kBatchStream8[cls - kStream8Class];
     const int r = cls >> 1, b = cls & 1;
     return r <= 7 ? kBatchStream_lo[r][b] : kBatchStream_hi[r - 8][b];
@@ -95,7 +97,12 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
     if (tiles <= 0) return hipSuccess;
     PlainKernel k = k_plain;
     int* done = &g_plain_lds_done;
-    if (j.hist == OILPAINT_HIST_STREAM8) {
+    if (j.hist == OILPAINT_HIST_COLUMN) {
+        if (j.radius < 0 || j.radius > kColumnMaxRadius || waves != 1) return hipErrorInvalidValue;
+        const int nt = column_chunks(j.radius);
+        k = kColumn[nt - 1];
+        done = &g_column_lds_done[nt - 1];
+    } else if (j.hist == OILPAINT_HIST_STREAM8) {
         if (j.radius < 8 || j.radius > kPackedMaxRadius || j.scan > 32 || waves != 1) return hipErrorInvalidValue;
         k = kStream8[j.radius - 8];
         done = &g_stream8_lds_done[j.radius - 8];

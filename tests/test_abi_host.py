@@ -71,11 +71,15 @@ def test_pick_variant_shapes():
     assert vv.hist == B.HIST_STREAM and vv.lanes == 64 and vv.waves == 1 and vv.rows >= 1
     vv = B.pick_variant(1920, 1080, 5, 100)
     assert vv.hist == B.HIST_PACKED and vv.lanes in (16, 32, 64) and 1 <= vv.waves <= 8 and vv.rows >= 1
-    assert B.pick_variant(1920, 1080, 16, 20).hist == B.HIST_WIDE
+    assert B.pick_variant(1920, 1080, 16, 20).hist == B.HIST_COLUMN
+    assert B.pick_variant(1920, 1080, 255, 20).hist == B.HIST_COLUMN
+    assert B.pick_variant(1920, 1080, 255, 64).hist == B.HIST_WIDE   # 65 x 574 x 8 B do not fit
+    assert B.pick_variant(1920, 1080, 256, 20).hist == B.HIST_WIDE   # beyond the column layout
+    assert B.pick_variant(1920, 1080, 200, 256).hist == B.HIST_WIDE  # column histograms do not fit
     assert B.pick_variant(1920, 1080, 5, 256).hist == B.HIST_WIDE
     # a radius beyond the image behaves as the image size
     assert B.pick_variant(12, 10, 1000, 20).hist == B.HIST_STREAM
-    assert B.pick_variant(20, 10, 1000, 20).hist == B.HIST_WIDE
+    assert B.pick_variant(20, 10, 1000, 20).hist == B.HIST_COLUMN  # effective radius 19
 
 
 def test_stream8_limits():
@@ -91,6 +95,34 @@ def test_stream8_limits():
         assert B.set_variant(10, 20, B.Variant(0, 1, B.HIST_STREAM8, 32, 4)) == B.ERR_UNSUPPORTED
     finally:
         B.clear_variants()
+
+
+def test_column_limits():
+    # column histograms: one wavefront of 64 lanes, radius <= 255, and the
+    # (levels + 1) x (64 + 2r) 8-byte histograms within the on-chip budget
+    v = B.Variant(0, 1, B.HIST_COLUMN, 64, 2)
+    try:
+        assert B.set_variant(0, 1, v) == B.OK
+        assert B.set_variant(255, 20, v) == B.OK
+        assert B.set_variant(64, 64, v) == B.OK
+        assert B.set_variant(256, 20, v) == B.ERR_UNSUPPORTED
+        assert B.set_variant(200, 256, v) == B.ERR_UNSUPPORTED
+        assert B.set_variant(20, 20, B.Variant(0, 2, B.HIST_COLUMN, 64, 2)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(20, 20, B.Variant(0, 1, B.HIST_COLUMN, 32, 2)) == B.ERR_UNSUPPORTED
+    finally:
+        B.clear_variants()
+
+
+def test_column_counts_fit():
+    # the column layout's packed fields and 32-bit window sums hold their
+    # largest values (radius 255: columns of 511 pixels, windows of 511^2)
+    col = 2 * 255 + 1
+    assert col < 2 ** 13 and 255 * col < 2 ** 17
+    assert col * col < 2 ** 32 and 255 * col * col < 2 ** 27
+    # prefix sums over a whole strip with its halo stay below 2^32
+    assert 255 * col * (64 + 2 * 255) < 2 ** 32
+    # the largest strip with its halo spans at most nine wavefront widths
+    assert -(-(64 + 2 * 255) // 64) == 9
 
 
 def test_kernel_integer_identities():

@@ -1,0 +1,121 @@
+"""GPU parity of the column layout (per-column histograms and per-level
+prefix sums across the strip, radius up to 255) against the CPU oracle,
+bit-exact, through the C-ABI: every 64-column chunk count, level counts
+from 1 to 100, ragged sizes, run lengths, radii clipped by the image, the
+paper form, and batches mixing it with the other layouts."""
+import numpy as np
+import pytest
+
+from paper_1405_1020_amd import binding as B
+from paper_1405_1020_amd import synth
+from gpu_util import (to_device, empty_like_device, from_device, padding_bytes, ref, ref_pixel,
+                      first_mismatch, torch_mod)
+
+pytestmark = pytest.mark.gpu
+
+
+def run_variant(img, r, L, variant, pad=0):
+    torch = torch_mod()
+    h, w, _ = img.shape
+    src, sbuf = to_device(img, pad=pad, seed=3)
+    dst, dbuf = empty_like_device(img, pad=pad, seed=5)
+    before = padding_bytes(dbuf, h, w, 3 * w + pad)
+    B.oilpaint_async(src, dst, r, L, variant=variant)
+    torch.cuda.synchronize()
+    assert np.array_equal(before, padding_bytes(dbuf, h, w, 3 * w + pad)), "dst padding was written"
+    return from_device(dst)
+
+
+def image(w, h, seed):
+    if w * h > 100:
+        return synth.make_image(w, h, seed=seed, n_blobs=5, sigma=(3, 25))
+    return synth.make_random(w, h, seed=seed)
+
+
+# (w, h, radii): radii from 0 to 255, so that every chunk count 1..9 of a
+# strip with its halo occurs, some clipped to the image
+CASES = [
+    ((1, 1), (0, 20)),
+    ((65, 40), (0, 3, 15, 16, 31, 32)),
+    ((130, 57), (16, 20, 47, 63, 64)),
+    ((97, 33), (95, 96, 127, 128)),
+    ((300, 21), (159, 160, 191, 192, 223, 224, 255)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_column_matches_oracle(case):
+    (w, h), radii = CASES[case]
+    img = image(w, h, seed=200 + case)
+    for r in radii:
+        for L in (1, 8, 20, 33, 64, 100):
+            want = ref(img, r, L)
+            for rows in (1, 5, 300):
+                v = B.Variant(rows, 1, B.HIST_COLUMN, 64)
+                try:
+                    got = run_variant(img, r, L, v, pad=(w + rows) % 5)
+                except B.OilpaintError as e:
+                    # only when the column histograms exceed the on-chip budget
+                    assert e.status == B.ERR_UNSUPPORTED and (L + 1) * (64 + 2 * min(r, max(w, h) - 1)) * 8 > 150000
+                    continue
+                mm = first_mismatch(got, want)
+                assert mm is None, (w, h, r, L, rows, mm)
+
+
+def test_column_paper_form():
+    torch = torch_mod()
+    img = image(150, 90, seed=7)
+    for r, L in ((16, 20), (40, 8), (20, 64)):
+        src, _ = to_device(img)
+        junk = np.random.default_rng(r).integers(0, 256, img.shape, dtype=np.uint8)
+        dst, _ = to_device(junk)
+        B.run(B.Item(src, dst, r, L, flags=B.FLAG_PAPER))
+        torch.cuda.synchronize()
+        assert B.pick_variant(150, 90, r, L).hist == B.HIST_COLUMN
+        want = ref(img, r, L, paper=True, out=junk.copy())
+        mm = first_mismatch(from_device(dst), want)
+        assert mm is None, (r, L, mm)
+
+
+def test_column_large_image_sampled():
+    # the library's default for r > 15 on a 1920x1080 image, against the
+    # oracle pixel by pixel on a seeded sample (borders and corners included)
+    torch = torch_mod()
+    img = synth.fhd_image()
+    src = torch.from_numpy(img).cuda()
+    rng = np.random.default_rng(11)
+    for r, L in ((20, 20), (64, 32)):
+        assert B.pick_variant(1920, 1080, r, L).hist == B.HIST_COLUMN
+        out = from_device(B.oilpaint(src, r, L))
+        pts = [(0, 0), (1919, 1079), (0, 1079), (1919, 0), (r, r), (1919 - r, 1079 - r)]
+        pts += [(int(rng.integers(0, 1920)), int(rng.integers(0, 1080))) for _ in range(60)]
+        for x, y in pts:
+            want = ref_pixel(img, x, y, r, L)
+            assert np.array_equal(out[y, x], want), (r, L, x, y, out[y, x], want)
+
+
+def test_batch_mixes_column_jobs():
+    torch = torch_mod()
+    cases = [((120, 90), 3, 20), ((200, 70), 20, 20), ((90, 130), 70, 8), ((64, 64), 16, 100),
+             ((150, 40), 5, 200), ((33, 250), 40, 33)]
+    items, imgs = [], []
+    for i, ((w, h), r, L) in enumerate(cases):
+        img = image(w, h, seed=300 + i)
+        src, _ = to_device(img)
+        dst, _ = empty_like_device(img)
+        items.append(B.Item(src, dst, r, L))
+        imgs.append(img)
+    B.batch(items)
+    torch.cuda.synchronize()
+    for (img, ((w, h), r, L)), it in zip(zip(imgs, cases), items):
+        mm = first_mismatch(from_device(it.dst), ref(img, r, L))
+        assert mm is None, (w, h, r, L, mm)
+    plan = B.Plan(items)
+    for _ in range(2):
+        for it in items:
+            it.dst.zero_()
+        plan.launch()
+        torch.cuda.synchronize()
+        for (img, (_, r, L)), it in zip(zip(imgs, cases), items):
+            assert first_mismatch(from_device(it.dst), ref(img, r, L)) is None
+    plan.close()
