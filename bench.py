@@ -99,6 +99,7 @@ def autotune(synth, quick: bool) -> dict:
         out.update(tune.ensure([(2, 20)], 256, 256))
         out.update(tune.ensure([(r, L) for r in (2, 3, 5, 8) for L in (16, 20, 32)], 2048, 1536))
         out.update(tune.ensure([(r, L) for r in range(1, 16) for L in (8, 16, 20, 32, 64)], 2400, 1800))
+        out.update(tune.ensure([(r, 20) for r in LARGE_RADII], 1920, 1080))
     return {k: v["variant"] for k, v in out.items()}
 
 
@@ -217,6 +218,44 @@ def bench_single(torch, B, timer, img, r, L, reps):
     mp = img.shape[0] * img.shape[1] / 1e6
     return {"ms": round(ms, 5), "mp_per_s": round(mp / (ms / 1e3), 1),
             "lds_gbs": round(lds_bytes_per_pixel(r, L) * mp * 1e6 / (ms / 1e3) / 1e9, 1)}
+
+
+LARGE_RADII = (16, 32, 64, 128)
+
+
+def bench_large_radius(torch, B, synth, timer, oracle_mod) -> dict:
+    """Radii above the streamed layout's 15 on the 1920x1080 image (L = 20):
+    the tuned launch (column histograms) against the wide layout, whose
+    work grows with the radius, and a seeded sample of output pixels against
+    the oracle (each pixel filtered on the crop of its own window)."""
+    import numpy as np
+    img = synth.fhd_image()
+    src = torch.from_numpy(img).cuda()
+    dst = torch.empty_like(src)
+    h, w = img.shape[:2]
+    mp = w * h / 1e6
+    rng = np.random.default_rng(13)
+    out = {}
+    for r in LARGE_RADII:
+        L = 20
+        v = B.pick_variant(w, h, r, L)
+        reps = 10 if r <= 32 else 3
+        ms = timer.time(lambda: B.oilpaint_async(src, dst, r, L), reps, 1)
+        wide = B.tune_times(w, h, r, L, [B.Variant(16, 2, B.HIST_WIDE, 64, 1)], reps=1 if r > 32 else 3)[0]
+        B.oilpaint_async(src, dst, r, L)
+        got = dst.cpu().numpy()
+        ok = 0
+        pts = [(int(rng.integers(0, w)), int(rng.integers(0, h))) for _ in range(12)] + [(0, 0), (w - 1, h - 1)]
+        for x, y in pts:
+            y0, y1, x0, x1 = max(0, y - r), min(h, y + r + 1), max(0, x - r), min(w, x + r + 1)
+            want = oracle_mod.oilpaint_ref(np.ascontiguousarray(img[y0:y1, x0:x1]), r, L)[y - y0, x - x0]
+            ok += int((got[y, x] == want).all())
+        out["r%d_L%d" % (r, L)] = {"ms": round(ms, 4), "mp_per_s": round(mp / (ms / 1e3), 1),
+                                   "kernel": kernel_name(r, L, v), "variant": list(v.as_tuple()),
+                                   "wide_ms": round(wide, 4), "wide_mp_per_s": round(mp / (wide / 1e3), 1),
+                                   "speedup_vs_wide": round(wide / ms, 2),
+                                   "oracle_pixels": "%d/%d" % (ok, len(pts))}
+    return out
 
 
 def bench_batched(torch, B, synth, timer, reps):
@@ -498,6 +537,8 @@ def main():
         log("batched ...")
         res["batched"] = bench_batched(torch, B, synth, timer, 5)
         import oracle as oracle_mod
+        log("large radii ...")
+        res["large_radius_1920x1080"] = bench_large_radius(torch, B, synth, timer, oracle_mod)
         log("serving ...")
         res["serving"] = bench_serving(torch, B, synth, serve, args.serve_requests, oracle_mod)
         log("cpu baseline ...")

@@ -1019,22 +1019,29 @@ __device__ __forceinline__ void tile_column(const Job& j, int unit, uint8_t* lds
     // column histograms of rows ya-R .. ya+R, the (2R+1) x TW pixels spread
     // over the lanes (no two lanes of one instruction share a column)
     {
+        // pixel p = base + 64 i sits at (p / TW, p % TW), tracked by steps of
+        // 64 (TW >= 64, so one wrap at most); sixteen pixels per lane in
+        // flight
         const int NP = (2 * R + 1) * TW;
-        constexpr int CH = 8;
+        constexpr int CH = 16;
+        int row = 0, col = lane;
         for (int base = lane; base < NP; base += CH * 64) {
             PixelBytes px[CH];
-            int col[CH];
+            int cl[CH];
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
-                const int p = min(base + i * 64, NP - 1);
-                const int row = p / TW;
-                col[i] = p - row * TW;
-                px[i].load(j, x0 - R + col[i], ya - R + row, true);
+                cl[i] = col;
+                px[i].load(j, x0 - R + col, ya - R + row, base + i * 64 < NP);
+                col += 64;
+                if (col >= TW) {
+                    col -= TW;
+                    ++row;
+                }
             }
 #pragma unroll
             for (int i = 0; i < CH; ++i)
                 if (base + i * 64 < NP)
-                    lds_add(entry(px[i].row(j), col[i]), column_inc(px[i].c0, px[i].c1, px[i].c2));
+                    lds_add(entry(px[i].row(j), cl[i]), column_inc(px[i].c0, px[i].c1, px[i].c2));
         }
     }
     lds_order();
@@ -1052,38 +1059,97 @@ __device__ __forceinline__ void tile_column(const Job& j, int unit, uint8_t* lds
                 ev[t].load(j, x0 - R + c, y + 1 + R, c < TW);
             }
         }
+        // pass 1: the window count of every level for every lane (prefix sums
+        // of the column counts across the strip), four levels at a time --
+        // four independent scans, one prefix entry of four counts, one LDS
+        // round trip; levels are compared in increasing order and the first
+        // strictly larger count wins, so the lowest level wins ties
         Sums4 best = {0u, 0u, 0u, 0u};
+        uint32_t bk = 0;
+        auto count_of = [&](int k, int c) -> uint32_t {
+            return reinterpret_cast<const uint32_t*>(entry((uint32_t)k, c))[1] >> 19;
+        };
 #pragma unroll 1
-        for (int k = 0; k < L; ++k) {
-            uint32_t cn = 0, ca = 0, cb = 0, cc = 0;  // totals of the chunks before
+        for (int k0 = 0; k0 < L; k0 += 4) {
+            const bool h1 = k0 + 1 < L, h2 = k0 + 2 < L, h3 = k0 + 3 < L;
+            uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;  // totals of the chunks before
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = lane + 64 * t;
+                uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+                if (c < TW) {
+                    n0 = count_of(k0, c);
+                    if (h1) n1 = count_of(k0 + 1, c);
+                    if (h2) n2 = count_of(k0 + 2, c);
+                    if (h3) n3 = count_of(k0 + 3, c);
+                }
+                n0 = wave_scan_add(n0) + q0;
+                n1 = wave_scan_add(n1) + q1;
+                n2 = wave_scan_add(n2) + q2;
+                n3 = wave_scan_add(n3) + q3;
+                if (c < TW) *reinterpret_cast<uint4*>(P + (size_t)(c + 1) * 4) = make_uint4(n0, n1, n2, n3);
+                if (t + 1 < NT) {
+                    q0 = (uint32_t)__builtin_amdgcn_readlane((int)n0, 63);
+                    q1 = (uint32_t)__builtin_amdgcn_readlane((int)n1, 63);
+                    q2 = (uint32_t)__builtin_amdgcn_readlane((int)n2, 63);
+                    q3 = (uint32_t)__builtin_amdgcn_readlane((int)n3, 63);
+                }
+            }
+            lds_order();
+            const uint4 hi = *reinterpret_cast<const uint4*>(P + (size_t)(lane + 2 * R + 1) * 4);
+            const uint4 lo = *reinterpret_cast<const uint4*>(P + (size_t)lane * 4);
+            const uint32_t w0 = hi.x - lo.x, w1 = hi.y - lo.y, w2 = hi.z - lo.z, w3 = hi.w - lo.w;
+            if (w0 > best.n) {
+                best.n = w0;
+                bk = (uint32_t)k0;
+            }
+            if (w1 > best.n) {
+                best.n = w1;
+                bk = (uint32_t)k0 + 1;
+            }
+            if (w2 > best.n) {
+                best.n = w2;
+                bk = (uint32_t)k0 + 2;
+            }
+            if (w3 > best.n) {
+                best.n = w3;
+                bk = (uint32_t)k0 + 3;
+            }
+            lds_order();
+        }
+        // pass 2: the channel sums of each lane's winning level, one set of
+        // prefix sums per distinct winner in the wavefront (neighbouring
+        // pixels mostly share their mode)
+        uint64_t pending = __ballot(best.n > 0);
+        while (pending) {
+            const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)bk, (int)__builtin_ctzll(pending));
+            uint32_t ca = 0, cb = 0, cc = 0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int c = lane + 64 * t;
                 uint64_t e = 0;
-                if (c < TW) e = *entry((uint32_t)k, c);
+                if (c < TW) e = *entry(k, c);
                 Sums4 v = column_unpack(e);
-                v.n = wave_scan_add(v.n) + cn;
                 v.a = wave_scan_add(v.a) + ca;
                 v.b = wave_scan_add(v.b) + cb;
                 v.c = wave_scan_add(v.c) + cc;
-                if (c < TW) *reinterpret_cast<uint4*>(P + (size_t)(c + 1) * 4) = make_uint4(v.n, v.a, v.b, v.c);
+                if (c < TW) *reinterpret_cast<uint4*>(P + (size_t)(c + 1) * 4) = make_uint4(0u, v.a, v.b, v.c);
                 if (t + 1 < NT) {
-                    cn = (uint32_t)__builtin_amdgcn_readlane((int)v.n, 63);
                     ca = (uint32_t)__builtin_amdgcn_readlane((int)v.a, 63);
                     cb = (uint32_t)__builtin_amdgcn_readlane((int)v.b, 63);
                     cc = (uint32_t)__builtin_amdgcn_readlane((int)v.c, 63);
                 }
             }
             lds_order();
-            const uint4 hi = *reinterpret_cast<const uint4*>(P + (size_t)(lane + 2 * R + 1) * 4);
-            const uint4 lo = *reinterpret_cast<const uint4*>(P + (size_t)lane * 4);
-            const uint32_t wn = hi.x - lo.x;
-            if (wn > best.n) {
-                best.n = wn;
+            const bool mine = best.n > 0 && bk == k;
+            if (mine) {
+                const uint4 hi = *reinterpret_cast<const uint4*>(P + (size_t)(lane + 2 * R + 1) * 4);
+                const uint4 lo = *reinterpret_cast<const uint4*>(P + (size_t)lane * 4);
                 best.a = hi.y - lo.y;
                 best.b = hi.z - lo.z;
                 best.c = hi.w - lo.w;
             }
+            pending &= ~__ballot(mine);
             lds_order();
         }
         uint32_t px = 0;
