@@ -9,27 +9,34 @@
 //
 // How it is laid out on the GPU (the paper rebuilds the whole window for
 // every pixel; none of the structure below is in the paper):
-//   * A workgroup computes one tile: `lanes` output columns by
-//     waves * rows output rows.  Lane l of wavefront w owns column x0 + l and
-//     output rows [y0 + w*rows, y0 + (w+1)*rows).
-//   * PACKED layout: the tile plus an r-pixel halo is staged once into LDS,
-//     one 32-bit word per pixel {c0, c1, c2, level}; the level is computed
-//     once per staged pixel.  Pixels outside the image get a spare level
-//     (the "trash" bin) that the mode search never scans, so the window needs
-//     no clipping logic.  Each lane keeps its window histogram in LDS, one
-//     64-bit word per level (count:10 | sum2:18 | sum1:18 | sum0:18), bins
-//     interleaved across lanes (bin k of lane l at k*lanes*8 + l*8), which
-//     keeps every lane on its own bank whatever level it touches.  Moving
-//     one row down removes the leaving row and adds the entering row of the
-//     window: 2(2r+1) 64-bit LDS atomics instead of a (2r+1)^2 rebuild.
-//     No field can carry into the next: each stays within its range.
-//   * The mode search scans the lane's bins with the key
-//     (count << 22) | (255 - level), whose maximum is the most populated
-//     level with the lowest index among ties.
-//   * The division is exact (see div_exact).
-//   * WIDE layout (windows wider than 31 or more than 255 levels): two
-//     64-bit words per level with 32-bit count and sums, pixels read from
+//   * A workgroup computes one tile: 64 (or fewer) output columns by a run of
+//     output rows per wavefront.  Lane l owns column x0 + l and slides its
+//     window histogram down the run: moving one row down removes the leaving
+//     window row and adds the entering one, 2(2r+1) bin updates instead of a
+//     (2r+1)^2 rebuild.
+//   * Histograms live in LDS, one 64-bit word per level packing the count
+//     and the three channel sums (F18: count:10 | three 18-bit sums for r
+//     <= 15; F16: count:8 | three 16-bit sums for r <= 7), bins interleaved
+//     across lanes (bin k of lane l at k*512 + l*8) so that every lane stays
+//     on its own bank whatever level it touches.  No field can carry into
+//     the next: each stays within its range.  Pixels outside the image get a
+//     spare level that the mode search never scans, so the window needs no
+//     clipping logic.
+//   * STREAM layout (the default for r <= 15, L <= 64): one wavefront per
+//     workgroup; only the 2r+4 image rows around the window are staged, in a
+//     ring, as 4-byte words {c0, c1, c2, level} or (STREAM8) as 8-byte ready
+//     bin increments; a run's first window comes either from direct updates
+//     or from column histograms.
+//   * PACKED layout: the whole tile plus its r-pixel halo staged once, shared
+//     by several wavefronts.
+//   * COLUMN layout (r up to 255): column histograms and per-level prefix
+//     sums across the strip; the work per row does not grow with r.
+//   * WIDE layout (anything else): 32-bit counts and sums, pixels read from
 //     device memory.
+//   * The mode search takes the maximum of (count << shift) | (C - level)
+//     for a constant C above every level: the most populated level, the
+//     lowest index among ties.
+//   * The divisions are exact (div_exact, div_exact32).
 #pragma once
 
 #include <type_traits>
