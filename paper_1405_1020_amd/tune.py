@@ -3,8 +3,9 @@
 For each (radius, levels) the candidates -- streamed rows with several
 workgroup densities (and, for radius 8..15 with at most 32 levels, the
 same with 8-byte on-chip row entries), tile-staged workgroups of 2 or 4
-wavefronts with several densities, and for radii above 15 column
-histograms and the wide layout -- are timed by the library itself (oilpaint_tune, HIP
+wavefronts with several densities, column histograms for radii from 8
+(at most 32 levels) and above 15, and the wide layout above 15 -- are
+timed by the library itself (oilpaint_tune, HIP
 events around repeated launches on a representative image) and the fastest
 is installed with oilpaint_set_variant, so that oilpaint_async, batches and
 the request queue use it.  Shapes whose rows are derived from a workgroup
@@ -56,7 +57,11 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
             for per_cu in (1, 2, 4, 8):
                 out.append(B.Variant(0, waves, B.HIST_PACKED, 64, per_cu))
     if radius > 15:
-        for per_cu in (1, 2, 4, 8):
+        for per_cu in (1, 2, 4, 8, 16):
+            out.append(B.Variant(0, 1, B.HIST_COLUMN, 64, per_cu))
+    elif radius >= 8 and levels <= 32:
+        # column histograms cost O(levels) per row: they can win at few levels
+        for per_cu in (8, 16):
             out.append(B.Variant(0, 1, B.HIST_COLUMN, 64, per_cu))
     if not out or radius > 15:
         for per_cu in (1, 2, 4):
