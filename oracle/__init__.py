@@ -6,7 +6,8 @@ benchmark's CPU-baseline leg may import this package.  The GPU library
 
 `oilpaint_ref` wraps the plain C implementation in oilpaint_ref.c through
 ctypes on numpy arrays; `brute` is an independent Python brute force for tiny
-images.
+images.  `median_ref` wraps median_ref.c, the windowed median filter (the
+second filter of the same class); `brute.brute_median` is its brute force.
 """
 from __future__ import annotations
 
@@ -16,20 +17,22 @@ import subprocess
 
 import numpy as np
 
-from .brute import brute, level_of  # noqa: F401
+from .brute import brute, brute_median, level_of  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oilpaint_ref.c")
+_SRCS = [_SRC, os.path.join(_HERE, "median_ref.c")]
 _LIB = os.path.join(_HERE, "liboilpaint_ref.so")
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile oilpaint_ref.c with gcc -O2 into liboilpaint_ref.so."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile oilpaint_ref.c and median_ref.c with gcc -O2 into
+    liboilpaint_ref.so."""
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
-                               "-pthread", _SRC, "-o", tmp])
+                               "-pthread"] + _SRCS + ["-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -45,6 +48,8 @@ def _load():
             fn = getattr(lib, name)
             fn.argtypes = [u8p, u8p] + [ctypes.c_int] * 6
             fn.restype = ctypes.c_int
+        lib.median_ref.argtypes = [u8p, u8p] + [ctypes.c_int] * 8
+        lib.median_ref.restype = ctypes.c_int
         for name in ("oilpaint_ref_level", "oilpaint_ref_level_paper"):
             fn = getattr(lib, name)
             fn.argtypes = [ctypes.c_uint] * 4
@@ -101,3 +106,19 @@ def ref_level(r: int, g: int, b: int, levels: int, paper_mode: bool = False) -> 
     lib = _load()
     fn = lib.oilpaint_ref_level_paper if paper_mode else lib.oilpaint_ref_level
     return int(fn(r, g, b, levels))
+
+
+def median_ref(img: np.ndarray, radius: int, channel: int, nthreads: int = 1) -> np.ndarray:
+    """Windowed lower median of one channel of an [H, W, C] uint8 image
+    (window clipped to the image).  Returns an [H, W] uint8 array."""
+    a = np.ascontiguousarray(img)
+    assert a.dtype == np.uint8 and a.ndim == 3
+    h, w, c = a.shape
+    out = np.zeros((h, w), np.uint8)
+    if w == 0 or h == 0:
+        return out
+    st = _load().median_ref(_u8p(a.reshape(-1)), _u8p(out.reshape(-1)), w, h, c * w, w, c, channel, radius,
+                            nthreads)
+    if st != 0:
+        raise ValueError("median_ref: status %d" % st)
+    return out

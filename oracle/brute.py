@@ -44,3 +44,17 @@ def brute(pixels, radius: int, levels: int):
             row_out.append(tuple(sum(int(p[c]) for p in members) // n for c in range(3)))
         out.append(row_out)
     return out
+
+
+def brute_median(img, radius: int, channel: int):
+    """Windowed lower median by sorting each clipped window (tiny images):
+    element floor((n - 1) / 2) of the sorted window values of one channel."""
+    h, w = len(img), len(img[0])
+    out = [[0] * w for _ in range(h)]
+    for y in range(h):
+        for x in range(w):
+            vals = sorted(int(img[yy][xx][channel])
+                          for yy in range(max(0, y - radius), min(h, y + radius + 1))
+                          for xx in range(max(0, x - radius), min(w, x + radius + 1)))
+            out[y][x] = vals[(len(vals) - 1) // 2]
+    return out
