@@ -258,6 +258,29 @@ def bench_large_radius(torch, B, synth, timer, oracle_mod) -> dict:
     return out
 
 
+def bench_median(torch, B, synth, timer, oracle_mod, threads: int) -> dict:
+    """The windowed median of one channel (the second filter of the class) on
+    the 1920x1080 image, channel 1: MP/s per radius, and the whole output
+    against the median oracle at r = 1, 5 and 15."""
+    import numpy as np
+    img = synth.fhd_image()
+    src = torch.from_numpy(img).cuda()
+    h, w = img.shape[:2]
+    dst = torch.empty(h, w, dtype=torch.uint8, device="cuda")
+    mp = w * h / 1e6
+    out = {}
+    for r in (1, 2, 5, 10, 15):
+        ms = timer.time(lambda: B.median_async(src, dst, r, 1), 20, 3)
+        e = {"ms": round(ms, 5), "mp_per_s": round(mp / (ms / 1e3), 1)}
+        if r in (1, 5, 15):
+            B.median_async(src, dst, r, 1)
+            got = dst.cpu().numpy()
+            want = oracle_mod.median_ref(img, r, 1, nthreads=threads)
+            e["pixels_differing"] = int((got != want).sum())
+        out["r%d" % r] = e
+    return out
+
+
 def bench_batched(torch, B, synth, timer, reps):
     specs = synth.batch_items()
     srcs = [synth.batch_image(it) for it in specs]
@@ -539,6 +562,9 @@ def main():
         import oracle as oracle_mod
         log("large radii ...")
         res["large_radius_1920x1080"] = bench_large_radius(torch, B, synth, timer, oracle_mod)
+        log("median ...")
+        res["median_1920x1080_channel1"] = bench_median(torch, B, synth, timer, oracle_mod,
+                                                        max(1, min(16, len(os.sched_getaffinity(0)))))
         log("serving ...")
         res["serving"] = bench_serving(torch, B, synth, serve, args.serve_requests, oracle_mod)
         log("cpu baseline ...")

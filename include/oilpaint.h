@@ -233,6 +233,28 @@ int oilpaint_plan_info(const oilpaint_plan *plan, int *tiles, int *workgroups);
 int oilpaint_plan_destroy(oilpaint_plan *plan);
 
 /* ---------------------------------------------------------------------------
+ * Windowed median of one channel: the second filter of the oil paint's class
+ * (a per-window histogram of pixel values queried per output pixel; the
+ * paper's conclusions name this class of filters).  For every pixel, the
+ * lower median -- the element of rank floor((n-1)/2), 0-based, of the n
+ * values of channel `channel` in its (2r+1) x (2r+1) window clipped to the
+ * image -- is written to a one-channel image.
+ * ------------------------------------------------------------------------- */
+
+/* src: `channels` (1..4) interleaved 8-bit channels per pixel, rows
+ * src_stride bytes apart (>= channels * width); dst: one byte per pixel, rows
+ * dst_stride bytes apart (>= width); bytes [width, dst_stride) of a dst row
+ * are not written.  Device pointers, disjoint.  Effective radius (the radius
+ * clamped to max(width, height) - 1) at most 15, else ERR_UNSUPPORTED.
+ * Enqueues on `stream`; errors as oilpaint_async (ERR_NULL, ERR_ARG for a
+ * size, stride or channel, ERR_OVERLAP, ERR_NOT_DEVICE, ERR_HIP). */
+int oilpaint_median_async(const uint8_t *src, int src_stride, int channels, int channel, uint8_t *dst,
+                          int dst_stride, int width, int height, int radius, void *stream);
+/* The same on the default stream, then wait for it. */
+int oilpaint_median(const uint8_t *src, int src_stride, int channels, int channel, uint8_t *dst,
+                    int dst_stride, int width, int height, int radius);
+
+/* ---------------------------------------------------------------------------
  * Continuous batching.  A queue accepts filter requests at any time; each
  * oilpaint_queue_step (also run by push, poll and completed) packs the work
  * that is waiting -- new requests and the unfinished rows of running ones,

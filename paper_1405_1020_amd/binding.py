@@ -81,6 +81,11 @@ _SIGS = {
     "oilpaint_async_variant": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5
                                + [ctypes.POINTER(Variant), ctypes.c_void_p], ctypes.c_int),
     "oilpaint_run": ([ctypes.POINTER(Desc), ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_median_async": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                               ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
+                              ctypes.c_int),
+    "oilpaint_median": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "oilpaint_tune": ([ctypes.c_int] * 4 + [ctypes.POINTER(Variant), ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                        ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "oilpaint_batch": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
@@ -212,6 +217,46 @@ def oilpaint(src, radius: int, levels: int, out=None, stream=None, variant: Vari
         buf = torch.empty(max(h - 1, 0) * s + 3 * w, dtype=torch.uint8, device=src.device)
         out = buf.as_strided((h, w, 3), (s, 3, 1))
     oilpaint_async(src, out, radius, levels, stream=stream, variant=variant)
+    return out
+
+
+def _plane_geometry(t, channels: int | None) -> tuple[int, int, int, int]:
+    """(width, height, row stride, channels) of a uint8 [H, W, C] (C = 1..4)
+    or [H, W] tensor with packed pixels."""
+    torch = _torch()
+    if t.dtype != torch.uint8 or t.dim() not in (2, 3) or (t.dim() == 3 and not 1 <= t.shape[2] <= 4):
+        raise ValueError("expected a uint8 [H, W] or [H, W, C<=4] tensor")
+    h, w = t.shape[0], t.shape[1]
+    c = t.shape[2] if t.dim() == 3 else 1
+    st = t.stride()
+    if h > 0 and w > 0 and (st[1] != c or (t.dim() == 3 and st[2] != 1) or (h > 1 and st[0] < c * w)):
+        raise ValueError("pixels must be packed, got strides %s" % (st,))
+    return w, h, (st[0] if h > 1 else c * w), c
+
+
+def median_async(src, dst, radius: int, channel: int, stream=None) -> int:
+    """oilpaint_median_async: the windowed median of channel `channel` of
+    src (uint8 [H, W, C] CUDA tensor) into dst (uint8 [H, W] or [H, W, 1]),
+    each with its own row stride, on `stream`."""
+    _require_cuda(src, dst)
+    w, h, s, c = _plane_geometry(src, None)
+    w2, h2, s2, c2 = _plane_geometry(dst, None)
+    if (w, h) != (w2, h2) or c2 != 1:
+        raise ValueError("dst must be a one-channel image of src's width and height")
+    if w == 0 or h == 0:
+        return OK
+    st = lib().oilpaint_median_async(ctypes.c_void_p(src.data_ptr()), s, c, channel,
+                                     ctypes.c_void_p(dst.data_ptr()), s2, w, h, radius, _stream_ptr(stream))
+    return _check(st, "oilpaint_median_async")
+
+
+def median(src, radius: int, channel: int, out=None, stream=None):
+    """Windowed median of one channel; returns `out` (uint8 [H, W],
+    allocated if None)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(src.shape[0], src.shape[1], dtype=torch.uint8, device=src.device)
+    median_async(src, out, radius, channel, stream=stream)
     return out
 
 

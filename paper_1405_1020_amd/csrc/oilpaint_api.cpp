@@ -321,6 +321,59 @@ static int launch_one(const uint8_t* src, uint8_t* dst, int width, int height, i
     return launch_desc(d, v, stream);
 }
 
+int oilpaint_median_async(const uint8_t* src, int src_stride, int channels, int channel, uint8_t* dst,
+                          int dst_stride, int width, int height, int radius, void* stream) {
+    if (!src || !dst) return OILPAINT_ERR_NULL;
+    if (width < 0 || height < 0 || radius < 0 || channels < 1 || channels > 4 || channel < 0 ||
+        channel >= channels)
+        return OILPAINT_ERR_ARG;
+    if ((int64_t)src_stride < (int64_t)channels * width || dst_stride < width) return OILPAINT_ERR_ARG;
+    if (width == 0 || height == 0) return OILPAINT_OK;
+    const size_t slen = (size_t)src_stride * (size_t)(height - 1) + (size_t)channels * (size_t)width;
+    const size_t dlen = (size_t)dst_stride * (size_t)(height - 1) + (size_t)width;
+    if (ranges_overlap(src, slen, dst, dlen)) return OILPAINT_ERR_OVERLAP;
+    const int reff = effective_radius(width, height, radius);
+    if (reff > kMedianMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
+    int st = check_device_ptr(src);
+    if (st == OILPAINT_OK) st = check_device_ptr(dst);
+    if (st != OILPAINT_OK) return st;
+    int device = 0;
+    if (note_hip("hipGetDevice", hipGetDevice(&device)) != hipSuccess) return OILPAINT_ERR_HIP;
+    const DeviceInfo d = device_info(device);
+    MedianJob j;
+    j.src = src;
+    j.dst = dst;
+    j.width = width;
+    j.height = height;
+    j.src_stride = src_stride;
+    j.dst_stride = dst_stride;
+    j.channels = channels;
+    j.channel = channel;
+    j.radius = reff;
+    // as many one-wavefront workgroups per CU as fit on chip (at most 8), so
+    // that the whole grid is resident and runs are as long as that allows:
+    // 8 .. 1024 rows
+    const long strips = (width + 63) / 64;
+    const size_t lds = median_lds_bytes(reff);
+    const long fit = (long)((d.ok ? d.lds_per_block : 65536) / lds);
+    const long want = std::max(1L, std::min(fit, 8L)) * (d.ok ? d.cus : 256);
+    j.rows = (int)std::max(8L, std::min((strips * height + want - 1) / want, 1024L));
+    j.tiles_x = (int)strips;
+    j.tiles_y = (height + j.rows - 1) / j.rows;
+    hipLaunchKernelGGL(kMedian[reff], dim3(j.tiles_x * j.tiles_y), dim3(64), median_lds_bytes(reff),
+                       (hipStream_t)stream, j);
+    return note_hip("median launch", hipGetLastError()) == hipSuccess ? OILPAINT_OK : OILPAINT_ERR_HIP;
+}
+
+int oilpaint_median(const uint8_t* src, int src_stride, int channels, int channel, uint8_t* dst, int dst_stride,
+                    int width, int height, int radius) {
+    const int st = oilpaint_median_async(src, src_stride, channels, channel, dst, dst_stride, width, height,
+                                         radius, nullptr);
+    if (st != OILPAINT_OK) return st;
+    return note_hip("hipStreamSynchronize", hipStreamSynchronize(nullptr)) == hipSuccess ? OILPAINT_OK
+                                                                                          : OILPAINT_ERR_HIP;
+}
+
 int oilpaint_run(const oilpaint_desc* desc, void* stream) {
     if (!desc) return OILPAINT_ERR_NULL;
     return launch_desc(*desc, nullptr, (hipStream_t)stream);

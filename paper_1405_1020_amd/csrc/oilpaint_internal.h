@@ -164,6 +164,22 @@ inline int batch_class(const Job& j) {
     return kGenericClass;
 }
 
+// Windowed median of one channel (oilpaint_k_median.hip): one image, one
+// wavefront per workgroup of 64 output columns by `rows` output rows.
+constexpr int kMedianMaxRadius = 15;
+struct MedianJob {
+    const uint8_t* src;
+    uint8_t* dst;
+    int32_t width, height;
+    int32_t src_stride, dst_stride;  // bytes
+    int32_t channels, channel;       // interleaved channels of src, the one filtered
+    int32_t radius;                  // effective radius
+    int32_t rows, tiles_x, tiles_y;
+};
+typedef void (*MedianKernel)(MedianJob);
+extern const MedianKernel kMedian[kMedianMaxRadius + 1];
+size_t median_lds_bytes(int radius);
+
 // Kernel launches (oilpaint_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream);
 hipError_t launch_batch(const BatchArgs& a, int cls, int waves, size_t lds, int grid, hipStream_t stream);

@@ -64,6 +64,29 @@ def test_validate_overlap():
     assert v(src=BASE, dst=BASE + 47 * 200 + 192, s=200) == B.OK
 
 
+def test_median_argument_checks():
+    # the median entry point's checks that come before any device call
+    L = B.lib()
+    buf = (ctypes.c_uint8 * 4096)()
+    a = ctypes.addressof(buf)
+    src, dst = ctypes.c_void_p(a), ctypes.c_void_p(a + 2048)
+    call = lambda s, ss, c, ch, d, ds, w, h, r: L.oilpaint_median_async(s, ss, c, ch, d, ds, w, h, r, None)
+    assert call(None, 30, 3, 0, dst, 10, 10, 5, 2) == B.ERR_NULL
+    assert call(src, 30, 3, 0, None, 10, 10, 5, 2) == B.ERR_NULL
+    assert call(src, 30, 3, 3, dst, 10, 10, 5, 2) == B.ERR_ARG   # channel
+    assert call(src, 30, 5, 0, dst, 10, 10, 5, 2) == B.ERR_ARG   # channels
+    assert call(src, 29, 3, 0, dst, 10, 10, 5, 2) == B.ERR_ARG   # src stride
+    assert call(src, 30, 3, 0, dst, 9, 10, 5, 2) == B.ERR_ARG    # dst stride
+    assert call(src, 30, 3, 0, dst, 10, 10, 5, -1) == B.ERR_ARG
+    assert call(src, 30, 3, 0, dst, 10, -1, 5, 2) == B.ERR_ARG
+    assert call(src, 30, 3, 0, dst, 10, 0, 5, 2) == B.OK         # empty: nothing to do
+    assert call(src, 30, 3, 0, ctypes.c_void_p(a + 100), 10, 10, 5, 2) == B.ERR_OVERLAP
+    # radius 16 on a 20 x 20 image is 16 effective: beyond the median kernels
+    assert call(src, 60, 3, 0, dst, 20, 20, 20, 16) == B.ERR_UNSUPPORTED
+    # on a 10 x 5 image it is 9 effective: valid, and host memory is refused
+    assert call(src, 30, 3, 0, dst, 10, 10, 5, 16) == B.ERR_NOT_DEVICE
+
+
 def test_pick_variant_shapes():
     # the choice is pure host logic once the device facts are cached; without
     # a GPU it falls back to nominal facts
