@@ -83,9 +83,19 @@ def kernel_name(r: int, L: int, v) -> str:
     return "k_plain"
 
 
+# Sources that define the plain kernels the sweep launches; the HBM counter
+# summary is valid while they are unchanged.
+SWEEP_KERNEL_SOURCES = ("oilpaint_internal.h", "oilpaint_device.h", "oilpaint_k_stream_lo.hip",
+                        "oilpaint_k_stream_hi.hip", "oilpaint_k_stream8.hip", "oilpaint_k_fast_lo.hip",
+                        "oilpaint_k_fast_hi.hip")
+
+
 def kernel_source_hash() -> str:
-    from paper_1405_1020_amd import tune
-    return tune.code_hash()
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1405_1020_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def autotune(synth, quick: bool) -> dict:

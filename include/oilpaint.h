@@ -173,9 +173,10 @@ int oilpaint_async_variant(const uint8_t *src, uint8_t *dst, int width, int heig
                            int radius, int levels, const oilpaint_variant *v, void *stream);
 
 /* Time n candidate variants for (radius, levels) on a width x height image
- * that the library allocates and fills with a fixed pseudo-random pattern
- * (the filter's cost does not depend on the pixel values' distribution in
- * any way the candidates differ by).  Each candidate is run once untimed,
+ * that the library allocates and fills with a fixed photo-like pattern
+ * (smooth ramps with small noise: the column layout's cost depends on how
+ * many distinct modes neighbouring pixels have, and photographs have few).
+ * Each candidate is run once untimed,
  * then `reps` times between HIP events on `stream`; ms_out[i] receives its
  * average milliseconds per launch, or -1 if it cannot run (radius, levels).
  * Synchronizes `stream`.  Returns OK, ERR_NULL, ERR_ARG, ERR_NOMEM or

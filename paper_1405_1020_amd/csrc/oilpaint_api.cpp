@@ -416,7 +416,7 @@ int oilpaint_tune(int width, int height, int radius, int levels, const oilpaint_
     if (st == OILPAINT_OK && (note_hip("hipEventCreate", hipEventCreate(&e0)) != hipSuccess ||
                               note_hip("hipEventCreate", hipEventCreate(&e1)) != hipSuccess))
         st = OILPAINT_ERR_HIP;
-    if (st == OILPAINT_OK && launch_fill(src, bytes, stream) != hipSuccess) st = OILPAINT_ERR_HIP;
+    if (st == OILPAINT_OK && launch_fill(src, bytes, width, stream) != hipSuccess) st = OILPAINT_ERR_HIP;
     for (int i = 0; st == OILPAINT_OK && i < n; ++i) {
         ms_out[i] = -1.0f;
         const int s0 = oilpaint_async_variant(src, dst, width, height, 3 * width, radius, levels, &cands[i], stream);

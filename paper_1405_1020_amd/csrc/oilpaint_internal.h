@@ -186,7 +186,8 @@ hipError_t launch_batch(const BatchArgs& a, int cls, int waves, size_t lds, int 
 // Clear n counters, stride_words apart (a kernel, so that a captured graph
 // holds no memset node).
 hipError_t launch_reset_counters(uint32_t* counters, int n, int stride_words, hipStream_t stream);
-hipError_t launch_fill(uint8_t* p, size_t n, hipStream_t stream);
+// Photo-like test image (3-byte pixels, `width` per row) for the tuner.
+hipError_t launch_fill(uint8_t* p, size_t n, int width, hipStream_t stream);
 
 // Record a failed HIP call (text readable through oilpaint_last_error) and
 // clear the runtime's sticky last-error state.  Returns `e`.

@@ -38,14 +38,20 @@ __global__ __launch_bounds__(64) void k_batch(BatchArgs a) {
     }
 }
 
-// Fixed pseudo-random bytes (a 32-bit integer hash of the index).
-__global__ void k_fill(uint8_t* p, size_t n) {
+// A photo-like test image for timing launch shapes: per channel a smooth
+// diagonal ramp with a slow ripple, plus small pseudo-random noise (a 32-bit
+// integer hash of the byte index); `width` pixels of 3 bytes per row.
+__global__ void k_fill(uint8_t* p, size_t n, int width) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         uint32_t h = (uint32_t)i * 2654435761u;
         h ^= h >> 15;
         h *= 2246822519u;
         h ^= h >> 13;
-        p[i] = (uint8_t)h;
+        const size_t px = i / 3;
+        const uint32_t c = (uint32_t)(i - 3 * px);
+        const uint32_t x = (uint32_t)(px % (size_t)width), y = (uint32_t)(px / (size_t)width);
+        const uint32_t ramp = (x / 7 + y / 5 + 60 * c) + ((x / 97 + y / 61) & 3) * 23;
+        p[i] = (uint8_t)((ramp & 255) ^ (h & 7));
     }
 }
 
@@ -132,8 +138,8 @@ hipError_t launch_batch(const BatchArgs& a, int cls, int waves, size_t lds, int 
     return note_hip("batch kernel launch", hipGetLastError());
 }
 
-hipError_t launch_fill(uint8_t* p, size_t n, hipStream_t stream) {
-    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, stream, p, n);
+hipError_t launch_fill(uint8_t* p, size_t n, int width, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, stream, p, n, width > 0 ? width : 1);
     return note_hip("k_fill launch", hipGetLastError());
 }
 
