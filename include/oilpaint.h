@@ -127,7 +127,15 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *   OILPAINT_HIST_STREAM8 OILPAINT_HIST_STREAM whose on-chip rows hold each
  *                         pixel's ready-made bin increment (8 bytes instead
  *                         of 4): fewer instructions per window update, twice
- *                         the row storage; radius 8..15, levels <= 32
+ *                         the row storage; radius 8..15, levels <= 32.
+ *                         waves = 1: one wavefront per strip; waves = 4: four
+ *                         wavefronts share one strip's histogram and rows,
+ *                         each making a quarter of every row step's updates
+ *                         and of the mode search (a CU then holds four times
+ *                         the wavefronts at about the same on-chip
+ *                         footprint); `rows` is then the run of the whole
+ *                         workgroup.  Batches and plans run these jobs with
+ *                         waves = 1.
  *   OILPAINT_HIST_COLUMN  per-column histograms of the window rows; each
  *                         lane's window is the difference of two per-level
  *                         prefix sums across the strip, so the work per

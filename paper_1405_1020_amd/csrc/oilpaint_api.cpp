@@ -48,7 +48,7 @@ size_t lds_bytes(const Job& j) {
     const size_t nb = (size_t)j.bins;
     const size_t lanes = (size_t)j.lanes;
     if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
-    if (is_stream(j.hist)) return nb * 64 * 8 + stream_ring_bytes(j) + 192;
+    if (is_stream(j.hist)) return nb * 64 * 8 + stream_ring_bytes(j) + 192 + (is_split(j) ? kSplitPartBytes : 0);
     if (j.hist == OILPAINT_HIST_COLUMN) {
         const size_t tw = 64 + 2 * (size_t)j.radius;
         return ((nb * tw * 8 + 15) & ~(size_t)15) + (tw + 1) * 16 + 192;
@@ -108,7 +108,8 @@ int auto_rows(const Job& j, const oilpaint_variant& v, int device) {
     const long strips = (j.width + v.lanes - 1) / v.lanes;
     const long band = j.row_end - j.row_begin;
     const long want = (long)std::max(v.per_cu, 1) * cus;
-    long rows = (strips * band + want * v.waves - 1) / (want * v.waves);
+    const long runs = is_stream(v.hist) ? 1 : v.waves;  // runs of rows per tile
+    long rows = (strips * band + want * runs - 1) / (want * runs);
     return (int)std::max(8L, std::min(rows, 1024L));
 }
 
@@ -125,7 +126,8 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
         if (j.radius > kPackedMaxRadius || j.levels > 64 || v.waves != 1 || v.lanes != 64)
             return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_STREAM8) {
-        if (j.radius < 8 || j.radius > kPackedMaxRadius || j.levels > 32 || v.waves != 1 || v.lanes != 64)
+        if (j.radius < 8 || j.radius > kPackedMaxRadius || j.levels > 32 || v.lanes != 64 ||
+            (v.waves != 1 && v.waves != kSplitWaves))
             return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_COLUMN) {
         if (j.radius > kColumnMaxRadius || v.waves != 1 || v.lanes != 64) return OILPAINT_ERR_UNSUPPORTED;
@@ -152,7 +154,7 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     }
     const int band = j.row_end - j.row_begin;
     j.tiles_x = (j.width + j.lanes - 1) / j.lanes;
-    const long per_tile = (long)v.waves * j.rows;
+    const long per_tile = (long)(is_stream(v.hist) ? 1 : v.waves) * j.rows;
     j.tiles_y = (int)((band + per_tile - 1) / per_tile);
     return OILPAINT_OK;
 }

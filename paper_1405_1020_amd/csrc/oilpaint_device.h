@@ -691,21 +691,22 @@ struct PixelAt {
 };
 
 // Stage rows y0-R .. y0-R+nrows-1 of the strip (64+2R columns) into the
-// ring, slot k holding row y0-R+k; sixteen pixels per lane in flight (one
-// wavefront per CU SIMD leaves little else to hide the memory latency).
-template <int R, bool W8>
+// ring, slot k holding row y0-R+k, by the NT threads of the workgroup;
+// sixteen pixels per thread in flight (one wavefront per CU SIMD leaves
+// little else to hide the memory latency).
+template <int R, bool W8, int NT = 64>
 __device__ __forceinline__ void stage_ring(const Job& j, int x0, int y0, int nrows, typename RingFmt<W8>::T* ring) {
     constexpr int CH = 16;
     constexpr int TW = 64 + 2 * R;
-    const int lane = threadIdx.x & 63;
+    const int t = NT == 64 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
     const int npx = TW * nrows;
-    for (int base = lane; base < npx; base += CH * 64) {
+    for (int base = t; base < npx; base += CH * NT) {
         PixelAt<R, W8> px[CH];
 #pragma unroll
-        for (int i = 0; i < CH; ++i) px[i].load(j, x0, y0, min(base + i * 64, npx - 1));
+        for (int i = 0; i < CH; ++i) px[i].load(j, x0, y0, min(base + i * NT, npx - 1));
 #pragma unroll
         for (int i = 0; i < CH; ++i)
-            if (base + i * 64 < npx) ring[base + i * 64] = px[i].entry(j);
+            if (base + i * NT < npx) ring[base + i * NT] = px[i].entry(j);
     }
 }
 
@@ -912,6 +913,245 @@ __device__ __forceinline__ void batch_stream(const BatchArgs& a, uint8_t* lds) {
         const int i = job_of(a, t);
         const Job jb = a.jobs[i];
         tile_stream<R, SB, W8>(jb, t - a.first_tile[i], lds);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// STREAM8 worked by four wavefronts per strip
+// ---------------------------------------------------------------------------
+// The strip, the run of rows, the histogram and the ring of tile_stream<R,
+// 32, true>, shared by kSplitWaves wavefronts.  Wavefront w makes the updates
+// of window columns w*C .. w*C+C-1 (C = ceil((2r+1)/4)) of every row step and
+// scans bins w*MB .. w*MB+MB-1 (the host pads the scanned levels to 4*MB with
+// bins no pixel reaches).  Two workgroup barriers per output row: after the
+// updates (the window is complete) and after the scans (every wavefront's
+// best level -- its key and bin word -- is in LDS).  Then one wavefront,
+// rotating, combines the four and stores the row while all of them go on
+// with the next row step.  Each wavefront does a quarter of the work, and a
+// CU holds four times the wavefronts at the same LDS footprint, which hides
+// the LDS latency that one wavefront per strip leaves exposed.
+//   LDS: [histogram: bins x 64 lanes x 8 B][ring region][output row: 192 B]
+//        [keys: 64 lanes x 4 x 4 B][bin words: 4 x 64 lanes x 8 B]
+
+// Workgroup barrier for LDS traffic: waits for this wavefront's LDS
+// operations only (global loads fetched ahead stay in flight), then meets
+// the other wavefronts.  Every wavefront of the workgroup reaches every one.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Wavefront priority from a run's progress: the fewer rows done, the higher.
+// The workgroups sharing a CU start together; left to the hardware, which
+// favours the oldest wavefronts, the first ones finish well ahead of the last
+// and the CU ends with too few wavefronts to hide the LDS latency.  With this
+// they move together.  q1 < q2 < q3 are the quarter points of the run.
+__device__ __forceinline__ void progress_priority(int done, int q1, int q2, int q3) {
+    if (done < q1)
+        __builtin_amdgcn_s_setprio(3);
+    else if (done < q2)
+        __builtin_amdgcn_s_setprio(2);
+    else if (done < q3)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(0);
+}
+
+template <int R, int MB>
+__device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_t* lds) {
+    static_assert(R >= 8 && R <= 15 && MB >= 1 && kSplitWaves * MB <= 32, "F18 bins, at most 32 scanned levels");
+    constexpr int NW = kSplitWaves;
+    constexpr int NT = 64 * NW;
+    constexpr int SPAN = 2 * R + 1;
+    constexpr int TW = 64 + 2 * R;
+    constexpr int RB = kStreamRingExtra + 2 * R;
+    constexpr int C = (SPAN + NW - 1) / NW;      // window columns per wavefront
+    constexpr int CMIN = SPAN - (NW - 1) * C;    // those of the last wavefront
+    constexpr uint32_t BS = 64u * 8u;
+    constexpr uint32_t M = BinFmt<false>::kCountMask;
+    using RF = RingFmt<true>;
+    using T = uint64_t;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int c0 = w * C;
+    const int scan = j.scan;
+    const int tx = unit % j.tiles_x;
+    const int ty = unit / j.tiles_x;
+    const int x0 = tx * 64;
+    const int ya = j.row_begin + ty * j.rows;
+    const int yb = min(ya + j.rows, j.row_end);
+    uint8_t* hl = lds + lane * 8;
+    const uint32_t lane_off = lds_offset(hl);
+    auto bin_ptr = [&](T e) { return lds_word(shl9_add(RF::bin_field(e), lane_off)); };
+    uint8_t* region = lds + (size_t)j.bins * BS;
+    T* ring = reinterpret_cast<T*>(region);
+    uint8_t* obuf = region + stream_ring_bytes(j);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(obuf + 192);                    // [lane][w]
+    uint64_t* words = reinterpret_cast<uint64_t*>(obuf + 192 + 64 * NW * 4);     // [w][lane]
+    auto slot = [&](int g) { return ring + ((g - (ya - R)) % RB) * TW; };
+    auto mine = [&](int c) { return c < CMIN || c0 + c < SPAN; };  // uniform
+
+    {
+        // One load round for the run's first 2R+2 ring rows (ya-R .. ya+R+1),
+        // spread over all NT threads.  Their entries stay in registers while
+        // the first window is built -- from column histograms of the 2R+1
+        // window rows among them, in the ring region (as in tile_stream) --
+        // and then enter the ring.
+        constexpr int NS = (2 * R + 2) * TW;
+        constexpr int CH = (NS + NT - 1) / NT;
+        constexpr int CW = TW * 8;
+        constexpr int NP = SPAN * TW;
+        const int t = (int)threadIdx.x;
+        T ent[CH];
+        {
+            PixelAt<R, true> px[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) px[i].load(j, x0, ya, min(t + i * NT, NS - 1));
+            // while the loads are in flight: clear the column histograms, or
+            // the histogram that direct updates will fill
+            if (j.colfirst) {
+                const int n16 = (scan + 1) * CW / 16;
+                for (int e = t; e < n16; e += NT)
+                    *reinterpret_cast<uint4*>(region + e * 16) = make_uint4(0u, 0u, 0u, 0u);
+            } else {
+                for (int k = w; k < j.bins; k += NW) *reinterpret_cast<uint64_t*>(hl + k * BS) = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < CH; ++i) ent[i] = px[i].entry(j);
+        }
+        lds_barrier();
+        if (j.colfirst) {
+            uint8_t* colh = region;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int p = t + i * NT;
+                const uint32_t k = min(RF::bin(ent[i]), (uint32_t)scan);
+                if (p < NP)
+                    lds_add(reinterpret_cast<uint64_t*>(colh + k * CW + (p % TW) * 8), RF::template inc<false>(ent[i]));
+            }
+            lds_barrier();
+#pragma unroll 1
+            for (int k = w; k < scan; k += NW) {
+                const uint64_t* col = reinterpret_cast<const uint64_t*>(colh + k * CW) + lane;
+                uint64_t acc = 0;
+#pragma unroll
+                for (int i = 0; i < SPAN; ++i) acc += col[i];
+                *reinterpret_cast<uint64_t*>(hl + k * BS) = acc;
+            }
+            // the ring replaces the column histograms
+            lds_barrier();
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (t + i * NT < NS) ring[t + i * NT] = ent[i];
+    }
+    lds_barrier();
+    // rows ya+2+R (wavefront 0) and ya+3+R (wavefront 1) are fetched now and
+    // staged at the top of the first loop iteration
+    RowBytes q;
+    if (w < 2) stream_load_row<R>(j, x0, ya + 2 + R + w, q);
+
+    if (!j.colfirst) {
+        // first window: this wavefront's columns of slots 0 .. 2R
+        const T* t = ring + lane + c0;
+#pragma unroll 1
+        for (int dy = 0; dy < SPAN; ++dy) {
+            T cur[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (mine(c)) cur[c] = t[c];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (mine(c)) lds_add(bin_ptr(cur[c]), RF::template inc<false>(cur[c]));
+            t += TW;
+        }
+    }
+    // entries of the step ya -> ya+1: leaving row ya-R, entering row ya+1+R
+    T wo[C], wn[C];
+    {
+        const T* so = slot(ya - R) + lane + c0;
+        const T* sn = slot(ya + 1 + R) + lane + c0;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (mine(c)) {
+                wo[c] = so[c];
+                wn[c] = sn[c];
+            }
+    }
+
+    // Output row y, then the step y -> y+1 and the entries of the next step.
+    auto row_step = [&](int y, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        lds_barrier();  // window(y) complete
+        uint64_t v[MB];
+        const uint8_t* hb = hl + (size_t)(w * MB) * BS;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
+        uint32_t best = 0;
+        uint64_t bw = 0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * MB - i);
+            if (key > best) {
+                best = key;
+                bw = v[i];
+            }
+        }
+        keys[lane * NW + w] = best;
+        words[w * 64 + lane] = bw;
+        lds_barrier();  // every wavefront's best is in LDS; the window may change
+        if (w == ((y - ya) & (NW - 1))) {
+            const uint4 kk = *reinterpret_cast<const uint4*>(keys + lane * NW);
+            const uint32_t top = max(max(kk.x, kk.y), max(kk.z, kk.w));
+            const uint32_t kbest = 63u - (top & 63u);
+            const uint64_t win = words[(kbest / MB) * 64 + lane];
+            const uint32_t n = top >> BinFmt<false>::kCountShift;
+            store_row(j, x0, y, n, finalize_packed<false>(n, win), obuf);
+        }
+        if (FULL || y + 1 < yb) {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (mine(c)) {
+                    lds_sub(bin_ptr(wo[c]), RF::template inc<false>(wo[c]));
+                    lds_add(bin_ptr(wn[c]), RF::template inc<false>(wn[c]));
+                }
+            if (FULL || y + 2 < yb) {
+                // step y+1 -> y+2 removes row y+1-R and adds row y+2+R
+                const T* so = slot(y + 1 - R) + lane + c0;
+                const T* sn = slot(y + 2 + R) + lane + c0;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (mine(c)) {
+                        wo[c] = so[c];
+                        wn[c] = sn[c];
+                    }
+            }
+        }
+    };
+    // Two output rows per iteration.  At the top, rows y+2+R and y+3+R
+    // (fetched one iteration earlier by wavefronts 0 and 1) enter the ring --
+    // into the slots of rows y-R-2 and y-R-1, which no window needs any more
+    // -- and rows y+4+R and y+5+R are fetched.  The barriers of the two rows
+    // order the ring writes before every read of them.
+    using Full = std::true_type;
+    using Tail = std::false_type;
+    const int q1 = ya + (yb - ya) / 4, q2 = ya + (yb - ya) / 2, q3 = ya + 3 * (yb - ya) / 4;
+    int y = ya;
+#pragma unroll 1
+    for (; y + 5 < yb; y += 2) {
+        progress_priority(y, q1, q2, q3);
+        if (w < 2) {
+            stream_write_row<R, true>(j, slot(y + 2 + R + w), q);
+            stream_load_row<R>(j, x0, y + 4 + R + w, q);
+        }
+        row_step(y, Full{});
+        row_step(y + 1, Full{});
+    }
+#pragma unroll 1
+    for (; y < yb; y += 2) {
+        if (w < 2) {
+            if (y + 2 + w < yb) stream_write_row<R, true>(j, slot(y + 2 + R + w), q);
+            if (y + 4 + w < yb) stream_load_row<R>(j, x0, y + 4 + R + w, q);
+        }
+        row_step(y, Tail{});
+        if (y + 1 < yb) row_step(y + 1, Tail{});
     }
 }
 

@@ -33,7 +33,9 @@ constexpr int kBatchWaves = 1;
 int batch_shape(Job& j, int waves, int device) {
     oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
     if (v.waves > waves) {
-        if (j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
+        // the batch kernels of the 8-byte streamed layout run one wavefront
+        // per strip; other many-wavefront shapes become the streamed layout
+        if (v.hist != OILPAINT_HIST_STREAM8 && j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
             v.hist = OILPAINT_HIST_STREAM;
             v.lanes = 64;
             v.rows = 0;

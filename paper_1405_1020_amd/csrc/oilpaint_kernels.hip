@@ -85,6 +85,7 @@ namespace {
 int g_fast_lds_done[kPackedMaxRadius + 1][3];
 int g_stream_lds_done[kPackedMaxRadius + 1][2];
 int g_stream8_lds_done[8];
+int g_split_lds_done[8][4];
 int g_column_lds_done[kColumnChunks];
 int g_plain_lds_done;
 int g_batch_lds_done[kBatchClasses];
@@ -108,6 +109,11 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
         const int nt = column_chunks(j.radius);
         k = kColumn[nt - 1];
         done = &g_column_lds_done[nt - 1];
+    } else if (j.hist == OILPAINT_HIST_STREAM8 && waves == kSplitWaves) {
+        const int b = j.scan % kSplitWaves == 0 ? split_bucket(j.scan / kSplitWaves) : -1;
+        if (j.radius < 8 || j.radius > kPackedMaxRadius || b < 0 || j.waves != kSplitWaves) return hipErrorInvalidValue;
+        k = kStream8Split[j.radius - 8][b];
+        done = &g_split_lds_done[j.radius - 8][b];
     } else if (j.hist == OILPAINT_HIST_STREAM8) {
         if (j.radius < 8 || j.radius > kPackedMaxRadius || j.scan > 32 || waves != 1) return hipErrorInvalidValue;
         k = kStream8[j.radius - 8];

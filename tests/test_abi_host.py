@@ -116,6 +116,12 @@ def test_stream8_limits():
         assert B.set_variant(16, 20, ok) == B.ERR_UNSUPPORTED
         assert B.set_variant(10, 33, ok) == B.ERR_UNSUPPORTED
         assert B.set_variant(10, 20, B.Variant(0, 2, B.HIST_STREAM8, 64, 4)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(10, 20, B.Variant(0, 8, B.HIST_STREAM8, 64, 4)) == B.ERR_UNSUPPORTED
+        # four wavefronts sharing a strip
+        assert B.set_variant(10, 20, B.Variant(0, 4, B.HIST_STREAM8, 64, 4)) == B.OK
+        assert B.set_variant(15, 32, B.Variant(0, 4, B.HIST_STREAM8, 64, 2)) == B.OK
+        assert B.set_variant(15, 33, B.Variant(0, 4, B.HIST_STREAM8, 64, 2)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(7, 20, B.Variant(0, 4, B.HIST_STREAM8, 64, 2)) == B.ERR_UNSUPPORTED
         assert B.set_variant(10, 20, B.Variant(0, 1, B.HIST_STREAM8, 32, 4)) == B.ERR_UNSUPPORTED
     finally:
         B.clear_variants()

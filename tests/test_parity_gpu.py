@@ -109,8 +109,8 @@ def test_stream_every_radius(r):
         want = {L: ref(img, r, L) for L in (1, 8, 20, 32, 33, 64)}
         for rows in (1, 2, 5, 16, 300):
             for L in (1, 8, 20, 32, 33, 64):
-                for hist in (B.HIST_STREAM, B.HIST_STREAM8):
-                    v = B.Variant(rows, 1, hist, 64)
+                for hist, waves in ((B.HIST_STREAM, 1), (B.HIST_STREAM8, 1), (B.HIST_STREAM8, 4)):
+                    v = B.Variant(rows, waves, hist, 64)
                     reff = min(r, max(w, h) - 1)
                     if hist == B.HIST_STREAM8 and not (8 <= reff and L <= 32):
                         with pytest.raises(B.OilpaintError) as e:
@@ -119,7 +119,7 @@ def test_stream_every_radius(r):
                         continue
                     got = run_plain(img, r, L, pad=(w + rows) % 5, variant=v)
                     mm = first_mismatch(got, want[L])
-                    assert mm is None, (w, h, r, L, rows, hist, mm)
+                    assert mm is None, (w, h, r, L, rows, hist, waves, mm)
 
 
 def test_repeat_is_deterministic():
