@@ -72,10 +72,13 @@ def kernel_name(r: int, L: int, v) -> str:
     """Name of the plain kernel a (radius, levels, variant) launch runs, as
     the profiler reports it."""
     scan = (L + 7) // 8 * 8
+    mb = 2 if L <= 8 else 4 if L <= 16 else 5 if L <= 20 else 8 if L <= 32 else 16  # bins per wavefront
+    if v.hist == 1 and v.waves == 4:  # streamed rows, four wavefronts per strip
+        return "k_plain_split<%d, %d>" % (r, mb)
+    if v.hist == 3 and v.waves == 4:  # streamed rows, 8-byte entries, four wavefronts per strip
+        return "k_plain_split8<%d, %d>" % (r, mb)
     if v.hist == 1:  # streamed rows
         return "k_plain_stream<%d, %d>" % (r, 32 if scan <= 32 else 64)
-    if v.hist == 3 and v.waves == 4:  # streamed rows, 8-byte entries, four wavefronts per strip
-        return "k_plain_split<%d, %d>" % (r, 2 if L <= 8 else 4 if L <= 16 else 5 if L <= 20 else 8)
     if v.hist == 3:  # streamed rows, 8-byte entries
         return "k_plain_stream8<%d>" % r
     if v.hist == 4:  # column histograms
@@ -89,7 +92,8 @@ def kernel_name(r: int, L: int, v) -> str:
 # summary is valid while they are unchanged.
 SWEEP_KERNEL_SOURCES = ("oilpaint_internal.h", "oilpaint_device.h", "oilpaint_k_stream_lo.hip",
                         "oilpaint_k_stream_hi.hip", "oilpaint_k_stream8.hip", "oilpaint_k_split.hip",
-                        "oilpaint_k_fast_lo.hip", "oilpaint_k_fast_hi.hip")
+                        "oilpaint_k_split_lo.hip", "oilpaint_k_split_hi.hip", "oilpaint_k_fast_lo.hip",
+                        "oilpaint_k_fast_hi.hip")
 
 
 def kernel_source_hash() -> str:

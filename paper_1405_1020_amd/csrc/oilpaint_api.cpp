@@ -123,7 +123,7 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     if (v.hist == OILPAINT_HIST_PACKED) {
         if (!packed_ok(j.radius, j.levels, j.paper != 0)) return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_STREAM) {
-        if (j.radius > kPackedMaxRadius || j.levels > 64 || v.waves != 1 || v.lanes != 64)
+        if (j.radius > kPackedMaxRadius || j.levels > 64 || v.lanes != 64 || (v.waves != 1 && v.waves != kSplitWaves))
             return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_STREAM8) {
         if (j.radius < 8 || j.radius > kPackedMaxRadius || j.levels > 32 || v.lanes != 64 ||

@@ -46,11 +46,13 @@
 namespace oilpaint_impl {
 namespace dev {
 
-// floor(s / n) for 1 <= n <= 961 and s <= 255 n, without a divide: the float
-// estimate s * (1/n) is within 1e-4 of s/n (s < 2^18, relative error of the
-// reciprocal and the product a few ulp), and s/n lies at least 1/961 below
-// the next integer, so truncating the estimate gives floor(s/n) or one less;
-// the integer checks correct either way.
+// floor(s / n) for 1 <= n <= 961 and s <= 255 n, without a divide: with rn
+// the hardware reciprocal of n (v_rcp_f32, within 1 ulp), the float estimate
+// s * rn is within 1e-4 of s/n (s < 2^18, relative error of the reciprocal
+// and the product a few ulp), and s/n lies at least 1/961 below the next
+// integer, so truncating the estimate gives floor(s/n) or one less; the
+// integer checks correct either way.
+__device__ __forceinline__ float rcp_approx(uint32_t n) { return __builtin_amdgcn_rcpf((float)n); }
 __device__ __forceinline__ uint32_t div_exact(uint32_t s, uint32_t n, float rn) {
     uint32_t q = (uint32_t)((float)s * rn);
     q += ((q + 1u) * n <= s) ? 1u : 0u;
@@ -227,7 +229,7 @@ __device__ __forceinline__ void store_packed(const Job& j, int x, int y, uint32_
     const uint32_t s0 = lo & 0x3FFFFu;
     const uint32_t s1 = (lo >> 18) | ((hi & 0xFu) << 14);
     const uint32_t s2 = (hi >> 4) & 0x3FFFFu;
-    const float rn = __frcp_rn((float)n);
+    const float rn = rcp_approx(n);
     gdst_t o = gdst(j.dst) + (size_t)y * (size_t)j.dst_stride + 3 * x;
     o[0] = (uint8_t)div_exact(s0, n, rn);
     o[1] = (uint8_t)div_exact(s1, n, rn);
@@ -241,7 +243,7 @@ __device__ __forceinline__ uint32_t finalize_packed(uint32_t n, uint64_t b) {
     uint32_t s0, s1, s2;
     BinFmt<F16>::sums(b, s0, s1, s2);
     const uint32_t nn = n ? n : 1u;
-    const float rn = __frcp_rn((float)nn);
+    const float rn = rcp_approx(nn);
     return div_exact(s0, nn, rn) | (div_exact(s1, nn, rn) << 8) | (div_exact(s2, nn, rn) << 16);
 }
 
@@ -917,10 +919,10 @@ __device__ __forceinline__ void batch_stream(const BatchArgs& a, uint8_t* lds) {
 }
 
 // ---------------------------------------------------------------------------
-// STREAM8 worked by four wavefronts per strip
+// The streamed layout worked by four wavefronts per strip
 // ---------------------------------------------------------------------------
 // The strip, the run of rows, the histogram and the ring of tile_stream<R,
-// 32, true>, shared by kSplitWaves wavefronts.  Wavefront w makes the updates
+// SB, W8>, shared by kSplitWaves wavefronts.  Wavefront w makes the updates
 // of window columns w*C .. w*C+C-1 (C = ceil((2r+1)/4)) of every row step and
 // scans bins w*MB .. w*MB+MB-1 (the host pads the scanned levels to 4*MB with
 // bins no pixel reaches).  Two workgroup barriers per output row: after the
@@ -954,9 +956,10 @@ __device__ __forceinline__ void progress_priority(int done, int q1, int q2, int 
         __builtin_amdgcn_s_setprio(0);
 }
 
-template <int R, int MB>
+template <int R, int MB, bool W8>
 __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_t* lds) {
-    static_assert(R >= 8 && R <= 15 && MB >= 1 && kSplitWaves * MB <= 32, "F18 bins, at most 32 scanned levels");
+    static_assert(R >= 0 && R <= 15 && MB >= 1 && kSplitWaves * MB <= 64, "level index must fit 6 bits");
+    static_assert(!W8 || (R >= 8 && kSplitWaves * MB <= 32), "8-byte entries: F18 bins, at most 32 scanned levels");
     constexpr int NW = kSplitWaves;
     constexpr int NT = 64 * NW;
     constexpr int SPAN = 2 * R + 1;
@@ -965,9 +968,11 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
     constexpr int C = (SPAN + NW - 1) / NW;      // window columns per wavefront
     constexpr int CMIN = SPAN - (NW - 1) * C;    // those of the last wavefront
     constexpr uint32_t BS = 64u * 8u;
-    constexpr uint32_t M = BinFmt<false>::kCountMask;
-    using RF = RingFmt<true>;
-    using T = uint64_t;
+    constexpr bool F16 = R <= 7;
+    using Fmt = BinFmt<F16>;
+    constexpr uint32_t M = Fmt::kCountMask;
+    using RF = RingFmt<W8>;
+    using T = typename RF::T;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int c0 = w * C;
@@ -1001,7 +1006,7 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
         const int t = (int)threadIdx.x;
         T ent[CH];
         {
-            PixelAt<R, true> px[CH];
+            PixelAt<R, W8> px[CH];
 #pragma unroll
             for (int i = 0; i < CH; ++i) px[i].load(j, x0, ya, min(t + i * NT, NS - 1));
             // while the loads are in flight: clear the column histograms, or
@@ -1024,7 +1029,7 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
                 const int p = t + i * NT;
                 const uint32_t k = min(RF::bin(ent[i]), (uint32_t)scan);
                 if (p < NP)
-                    lds_add(reinterpret_cast<uint64_t*>(colh + k * CW + (p % TW) * 8), RF::template inc<false>(ent[i]));
+                    lds_add(reinterpret_cast<uint64_t*>(colh + k * CW + (p % TW) * 8), RF::template inc<F16>(ent[i]));
             }
             lds_barrier();
 #pragma unroll 1
@@ -1059,7 +1064,7 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
                 if (mine(c)) cur[c] = t[c];
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                if (mine(c)) lds_add(bin_ptr(cur[c]), RF::template inc<false>(cur[c]));
+                if (mine(c)) lds_add(bin_ptr(cur[c]), RF::template inc<F16>(cur[c]));
             t += TW;
         }
     }
@@ -1102,15 +1107,15 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
             const uint32_t top = max(max(kk.x, kk.y), max(kk.z, kk.w));
             const uint32_t kbest = 63u - (top & 63u);
             const uint64_t win = words[(kbest / MB) * 64 + lane];
-            const uint32_t n = top >> BinFmt<false>::kCountShift;
-            store_row(j, x0, y, n, finalize_packed<false>(n, win), obuf);
+            const uint32_t n = top >> Fmt::kCountShift;
+            store_row(j, x0, y, n, finalize_packed<F16>(n, win), obuf);
         }
         if (FULL || y + 1 < yb) {
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 if (mine(c)) {
-                    lds_sub(bin_ptr(wo[c]), RF::template inc<false>(wo[c]));
-                    lds_add(bin_ptr(wn[c]), RF::template inc<false>(wn[c]));
+                    lds_sub(bin_ptr(wo[c]), RF::template inc<F16>(wo[c]));
+                    lds_add(bin_ptr(wn[c]), RF::template inc<F16>(wn[c]));
                 }
             if (FULL || y + 2 < yb) {
                 // step y+1 -> y+2 removes row y+1-R and adds row y+2+R
@@ -1138,7 +1143,7 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
     for (; y + 5 < yb; y += 2) {
         progress_priority(y, q1, q2, q3);
         if (w < 2) {
-            stream_write_row<R, true>(j, slot(y + 2 + R + w), q);
+            stream_write_row<R, W8>(j, slot(y + 2 + R + w), q);
             stream_load_row<R>(j, x0, y + 4 + R + w, q);
         }
         row_step(y, Full{});
@@ -1147,7 +1152,7 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
 #pragma unroll 1
     for (; y < yb; y += 2) {
         if (w < 2) {
-            if (y + 2 + w < yb) stream_write_row<R, true>(j, slot(y + 2 + R + w), q);
+            if (y + 2 + w < yb) stream_write_row<R, W8>(j, slot(y + 2 + R + w), q);
             if (y + 4 + w < yb) stream_load_row<R>(j, x0, y + 4 + R + w, q);
         }
         row_step(y, Tail{});

@@ -72,16 +72,20 @@ size_t lds_bytes(const Job& j);
 // then the bin for pixels outside the image.
 inline bool is_stream(int hist) { return hist == OILPAINT_HIST_STREAM || hist == OILPAINT_HIST_STREAM8; }
 
-// Streamed layout worked by several wavefronts per strip (OILPAINT_HIST_STREAM8
-// with waves == kSplitWaves): the wavefronts share one histogram and one ring,
-// each making a quarter of every row step's updates and scanning a block of
-// split_bins(L) bins; the scanned levels are padded to kSplitWaves blocks with
-// bins no pixel reaches.  Rows per tile are the run of every wavefront (not
-// multiplied by the wavefront count).
+// Streamed layout worked by several wavefronts per strip (OILPAINT_HIST_STREAM
+// or OILPAINT_HIST_STREAM8 with waves == kSplitWaves): the wavefronts share
+// one histogram and one ring, each making a quarter of every row step's
+// updates and scanning a block of split_bins(L) bins; the scanned levels are
+// padded to kSplitWaves blocks with bins no pixel reaches.  Rows per tile are
+// the run of every wavefront (not multiplied by the wavefront count).
 constexpr int kSplitWaves = 4;
-inline bool is_split(const Job& j) { return j.hist == OILPAINT_HIST_STREAM8 && j.waves == kSplitWaves; }
-inline int split_bins(int levels) { return levels <= 8 ? 2 : levels <= 16 ? 4 : levels <= 20 ? 5 : 8; }
-inline int split_bucket(int bins) { return bins == 2 ? 0 : bins == 4 ? 1 : bins == 5 ? 2 : bins == 8 ? 3 : -1; }
+inline bool is_split(const Job& j) { return is_stream(j.hist) && j.waves == kSplitWaves; }
+inline int split_bins(int levels) {
+    return levels <= 8 ? 2 : levels <= 16 ? 4 : levels <= 20 ? 5 : levels <= 32 ? 8 : 16;
+}
+inline int split_bucket(int bins) {
+    return bins == 2 ? 0 : bins == 4 ? 1 : bins == 5 ? 2 : bins == 8 ? 3 : bins == 16 ? 4 : -1;
+}
 // LDS of the per-wavefront mode-search results: a 4-byte key per lane and
 // wavefront, and the winning 8-byte bin word per lane and wavefront.
 constexpr size_t kSplitPartBytes = (size_t)kSplitWaves * 64 * 12;
@@ -121,7 +125,7 @@ inline void set_layout(Job& j) {
     j.fast = ((j.hist == OILPAINT_HIST_PACKED || is_stream(j.hist)) && j.lanes == 64 &&
               j.radius <= kPackedMaxRadius && j.levels <= 64) ? 1 : 0;
     j.scan = j.fast ? (j.levels + 7) / 8 * 8 : j.levels;
-    if (is_split(j) && j.levels <= 32) j.scan = kSplitWaves * split_bins(j.levels);
+    if (is_split(j) && j.levels <= 64) j.scan = kSplitWaves * split_bins(j.levels);
     j.white = j.scan;
     j.trash = j.scan + (j.paper ? 1 : 0);
     j.bins = j.trash + 1;
@@ -149,9 +153,12 @@ extern const PlainKernel kStream_hi[8][2];
 // Streamed kernels with 8-byte ring entries (OILPAINT_HIST_STREAM8),
 // [radius - 8], levels <= 32.
 extern const PlainKernel kStream8[8];
-// The same worked by kSplitWaves wavefronts per strip (oilpaint_k_split.hip),
-// [radius - 8][split_bucket(bins per wavefront)].
+// The streamed kernels worked by kSplitWaves wavefronts per strip
+// (oilpaint_k_split*.hip): [radius - 8 or 0][split_bucket(bins per
+// wavefront)], 8-byte entries up to 8 bins per wavefront, 4-byte up to 16.
 extern const PlainKernel kStream8Split[8][4];
+extern const PlainKernel kStreamSplit_lo[8][5];
+extern const PlainKernel kStreamSplit_hi[8][5];
 
 // Persistent batch kernels of the streamed layout (oilpaint_k_batch_*.hip),
 // indexed like kStream_*.

@@ -8,14 +8,14 @@ using namespace dev;
 namespace {
 
 template <int R, int MB>
-__global__ __launch_bounds__(64 * kSplitWaves) void k_plain_split(Job j) {
+__global__ __launch_bounds__(64 * kSplitWaves) void k_plain_split8(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_stream_split<R, MB>(j, blockIdx.x, lds);
+    tile_stream_split<R, MB, true>(j, blockIdx.x, lds);
 }
 
 }  // namespace
 
-#define OILPAINT_SPLIT_ROW(R) {k_plain_split<R, 2>, k_plain_split<R, 4>, k_plain_split<R, 5>, k_plain_split<R, 8>}
+#define OILPAINT_SPLIT_ROW(R) {k_plain_split8<R, 2>, k_plain_split8<R, 4>, k_plain_split8<R, 5>, k_plain_split8<R, 8>}
 
 // By [radius - 8][split_bucket(bins per wavefront)]: 2, 4, 5, 8 bins.
 const PlainKernel kStream8Split[8][4] = {OILPAINT_SPLIT_ROW(8),  OILPAINT_SPLIT_ROW(9),  OILPAINT_SPLIT_ROW(10),

@@ -86,6 +86,7 @@ int g_fast_lds_done[kPackedMaxRadius + 1][3];
 int g_stream_lds_done[kPackedMaxRadius + 1][2];
 int g_stream8_lds_done[8];
 int g_split_lds_done[8][4];
+int g_split4_lds_done[kPackedMaxRadius + 1][5];
 int g_column_lds_done[kColumnChunks];
 int g_plain_lds_done;
 int g_batch_lds_done[kBatchClasses];
@@ -109,9 +110,15 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
         const int nt = column_chunks(j.radius);
         k = kColumn[nt - 1];
         done = &g_column_lds_done[nt - 1];
+    } else if (j.hist == OILPAINT_HIST_STREAM && waves == kSplitWaves) {
+        const int b = j.scan % kSplitWaves == 0 ? split_bucket(j.scan / kSplitWaves) : -1;
+        if (j.radius < 0 || j.radius > kPackedMaxRadius || b < 0 || j.waves != kSplitWaves) return hipErrorInvalidValue;
+        k = j.radius <= 7 ? kStreamSplit_lo[j.radius][b] : kStreamSplit_hi[j.radius - 8][b];
+        done = &g_split4_lds_done[j.radius][b];
     } else if (j.hist == OILPAINT_HIST_STREAM8 && waves == kSplitWaves) {
         const int b = j.scan % kSplitWaves == 0 ? split_bucket(j.scan / kSplitWaves) : -1;
-        if (j.radius < 8 || j.radius > kPackedMaxRadius || b < 0 || j.waves != kSplitWaves) return hipErrorInvalidValue;
+        if (j.radius < 8 || j.radius > kPackedMaxRadius || b < 0 || b > 3 || j.waves != kSplitWaves)
+            return hipErrorInvalidValue;
         k = kStream8Split[j.radius - 8][b];
         done = &g_split_lds_done[j.radius - 8][b];
     } else if (j.hist == OILPAINT_HIST_STREAM8) {

@@ -49,6 +49,9 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
     if radius <= 15 and levels <= 64:
         for per_cu in (2, 4, 8, 16, 32):
             out.append(B.Variant(0, 1, B.HIST_STREAM, 64, per_cu))
+        # four wavefronts per strip
+        for per_cu in (2, 4, 8, 16):
+            out.append(B.Variant(0, 4, B.HIST_STREAM, 64, per_cu))
     if 8 <= radius <= 15 and levels <= 32:
         for per_cu in (2, 4, 8, 16):
             out.append(B.Variant(0, 1, B.HIST_STREAM8, 64, per_cu))

@@ -106,6 +106,21 @@ def test_pick_variant_shapes():
     assert B.pick_variant(20, 10, 1000, 20).hist == B.HIST_COLUMN  # effective radius 19
 
 
+def test_stream_split_limits():
+    # four wavefronts per strip: radius <= 15, levels <= 64, 64 lanes; other
+    # wavefront counts are refused for the streamed layout
+    try:
+        assert B.set_variant(0, 1, B.Variant(0, 4, B.HIST_STREAM, 64, 4)) == B.OK
+        assert B.set_variant(5, 64, B.Variant(0, 4, B.HIST_STREAM, 64, 4)) == B.OK
+        assert B.set_variant(15, 20, B.Variant(16, 4, B.HIST_STREAM, 64, 0)) == B.OK
+        assert B.set_variant(5, 65, B.Variant(0, 4, B.HIST_STREAM, 64, 4)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(16, 20, B.Variant(0, 4, B.HIST_STREAM, 64, 4)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(5, 20, B.Variant(0, 2, B.HIST_STREAM, 64, 4)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(5, 20, B.Variant(0, 4, B.HIST_STREAM, 32, 4)) == B.ERR_UNSUPPORTED
+    finally:
+        B.clear_variants()
+
+
 def test_stream8_limits():
     # 8-byte on-chip row entries: radius 8..15 (effective) and <= 32 levels
     ok = B.Variant(0, 1, B.HIST_STREAM8, 64, 4)

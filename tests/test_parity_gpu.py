@@ -109,7 +109,7 @@ def test_stream_every_radius(r):
         want = {L: ref(img, r, L) for L in (1, 8, 20, 32, 33, 64)}
         for rows in (1, 2, 5, 16, 300):
             for L in (1, 8, 20, 32, 33, 64):
-                for hist, waves in ((B.HIST_STREAM, 1), (B.HIST_STREAM8, 1), (B.HIST_STREAM8, 4)):
+                for hist, waves in ((B.HIST_STREAM, 1), (B.HIST_STREAM, 4), (B.HIST_STREAM8, 1), (B.HIST_STREAM8, 4)):
                     v = B.Variant(rows, waves, hist, 64)
                     reff = min(r, max(w, h) - 1)
                     if hist == B.HIST_STREAM8 and not (8 <= reff and L <= 32):
