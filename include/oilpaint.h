@@ -265,17 +265,19 @@ int oilpaint_median(const uint8_t *src, int src_stride, int channels, int channe
 
 /* ---------------------------------------------------------------------------
  * Continuous batching.  A queue accepts filter requests at any time; each
- * oilpaint_queue_step (also run by push, poll and completed) packs the work
- * that is waiting -- new requests and the unfinished rows of running ones,
- * an equal share of the launch's pixels each, in whole tile rows -- into one
- * batch launch, keeping at most four launches in flight, so that requests
- * that arrive while others are on the GPU share the next launch with them.
- * Launches run on the queue's side streams and do not wait for each other:
- * the next launch's kernels start while the previous one's last tiles
- * finish.  A launch covers `step_pixels` output pixels,
- * or a quarter of the waiting pixels when that is more (at most 64 x
- * step_pixels).  A lone request with nothing in flight is launched whole
- * with the plain kernel and its own launch shape.
+ * oilpaint_queue_step (also run by push, poll and completed) packs the small
+ * requests that are waiting -- new requests and the unfinished rows of
+ * running ones, an equal share of the launch's pixels each, in whole tile
+ * rows -- into one batch launch, keeping at most four launches in flight, so
+ * that requests that arrive while others are on the GPU share the next
+ * launch with them.  Launches run on the queue's side streams and do not
+ * wait for each other: the next launch's kernels start while the previous
+ * one's last tiles finish.  A launch covers `step_pixels` output pixels, or
+ * a quarter of the waiting small-request pixels when that is more (at most
+ * 64 x step_pixels).  A request of at least 4 Mi output pixels, and a lone
+ * request with nothing in flight, is launched whole with the plain kernel
+ * and its own launch shape; while small requests wait, at most every other
+ * launch is such a large request.
  * ------------------------------------------------------------------------- */
 typedef struct oilpaint_queue oilpaint_queue;
 

@@ -108,7 +108,7 @@ int auto_rows(const Job& j, const oilpaint_variant& v, int device) {
     const long strips = (j.width + v.lanes - 1) / v.lanes;
     const long band = j.row_end - j.row_begin;
     const long want = (long)std::max(v.per_cu, 1) * cus;
-    const long runs = is_stream(v.hist) ? 1 : v.waves;  // runs of rows per tile
+    const long runs = runs_per_tile(v.hist, v.waves);
     long rows = (strips * band + want * runs - 1) / (want * runs);
     return (int)std::max(8L, std::min(rows, 1024L));
 }
@@ -154,7 +154,7 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     }
     const int band = j.row_end - j.row_begin;
     j.tiles_x = (j.width + j.lanes - 1) / j.lanes;
-    const long per_tile = (long)(is_stream(v.hist) ? 1 : v.waves) * j.rows;
+    const long per_tile = (long)runs_per_tile(v.hist, v.waves) * j.rows;
     j.tiles_y = (int)((band + per_tile - 1) / per_tile);
     return OILPAINT_OK;
 }

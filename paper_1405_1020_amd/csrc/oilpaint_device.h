@@ -956,7 +956,10 @@ __device__ __forceinline__ void progress_priority(int done, int q1, int q2, int 
         __builtin_amdgcn_s_setprio(0);
 }
 
-template <int R, int MB, bool W8>
+// MB: bins per wavefront, or with RT their maximum, the count being
+// j.scan / kSplitWaves (the persistent batch kernels, one per radius and
+// level bucket).
+template <int R, int MB, bool W8, bool RT = false>
 __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_t* lds) {
     static_assert(R >= 0 && R <= 15 && MB >= 1 && kSplitWaves * MB <= 64, "level index must fit 6 bits");
     static_assert(!W8 || (R >= 8 && kSplitWaves * MB <= 32), "8-byte entries: F18 bins, at most 32 scanned levels");
@@ -977,6 +980,7 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int c0 = w * C;
     const int scan = j.scan;
+    const int mb = RT ? scan / NW : MB;  // bins this wavefront scans
     const int tx = unit % j.tiles_x;
     const int ty = unit / j.tiles_x;
     const int x0 = tx * 64;
@@ -1086,27 +1090,32 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
         constexpr bool FULL = decltype(full_tag)::value;
         lds_barrier();  // window(y) complete
         uint64_t v[MB];
-        const uint8_t* hb = hl + (size_t)(w * MB) * BS;
+        const uint8_t* hb = hl + (size_t)(w * mb) * BS;
 #pragma unroll
-        for (int i = 0; i < MB; ++i) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
+        for (int i = 0; i < MB; ++i)
+            if (!RT || i < mb) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
         uint32_t best = 0;
         uint64_t bw = 0;
 #pragma unroll
-        for (int i = 0; i < MB; ++i) {
-            const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * MB - i);
-            if (key > best) {
-                best = key;
-                bw = v[i];
+        for (int i = 0; i < MB; ++i)
+            if (!RT || i < mb) {
+                const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i);
+                if (key > best) {
+                    best = key;
+                    bw = v[i];
+                }
             }
-        }
         keys[lane * NW + w] = best;
         words[w * 64 + lane] = bw;
         lds_barrier();  // every wavefront's best is in LDS; the window may change
         if (w == ((y - ya) & (NW - 1))) {
             const uint4 kk = *reinterpret_cast<const uint4*>(keys + lane * NW);
-            const uint32_t top = max(max(kk.x, kk.y), max(kk.z, kk.w));
-            const uint32_t kbest = 63u - (top & 63u);
-            const uint64_t win = words[(kbest / MB) * 64 + lane];
+            // the largest key (keys of different wavefronts differ in level)
+            uint32_t top = kk.x, ww = 0;
+            if (kk.y > top) top = kk.y, ww = 1;
+            if (kk.z > top) top = kk.z, ww = 2;
+            if (kk.w > top) top = kk.w, ww = 3;
+            const uint64_t win = words[ww * 64 + lane];
             const uint32_t n = top >> Fmt::kCountShift;
             store_row(j, x0, y, n, finalize_packed<F16>(n, win), obuf);
         }
@@ -1157,6 +1166,26 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
         }
         row_step(y, Tail{});
         if (y + 1 < yb) row_step(y + 1, Tail{});
+    }
+}
+
+// Persistent batch form: the next tile of the class's queue, taken by the
+// workgroup's first thread and handed to all four wavefronts through LDS.
+// The barrier after the hand-over also orders the previous tile's last LDS
+// accesses before the next tile's first ones; the next hand-over comes only
+// after every wavefront has read this one (the tile's own barriers lie
+// between).
+template <int R, int MB, bool W8>
+__device__ __forceinline__ void batch_stream_split(const BatchArgs& a, uint8_t* lds) {
+    __shared__ int32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int32_t)atomicAdd(a.counter, 1u);
+        lds_barrier();
+        const int32_t t = __builtin_amdgcn_readfirstlane(next);
+        if (t >= a.ntiles) break;
+        const int i = job_of(a, t);
+        const Job jb = a.jobs[i];
+        tile_stream_split<R, MB, W8, true>(jb, t - a.first_tile[i], lds);
     }
 }
 

@@ -23,31 +23,29 @@ oilpaint_variant choose_variant(int width, int height, int reff, int levels, boo
 
 namespace {
 
-constexpr int kBatchWaves = 1;
-
-// Layout of a job inside a persistent launch of `waves` wavefronts per
-// workgroup: the job's own choice with at most `waves` computing wavefronts
-// (the streamed layout replaces a wider tile-staged one when it applies),
-// shrunk (wavefronts, then rows, then lanes) until its on-chip footprint
-// fits.  The rows are set afterwards for the whole launch (shape_rows).
-int batch_shape(Job& j, int waves, int device) {
+// Layout of a job inside a persistent launch: the streamed layouts as the
+// job's own choice (four wavefronts sharing a strip where that is its plain
+// shape, else one), every other layout with one computing wavefront per
+// workgroup (a tile-staged shape of several wavefronts becomes the streamed
+// layout when it applies); shrunk (wavefronts, then rows, then lanes) until
+// its on-chip footprint fits.  The rows are set afterwards for the whole
+// launch (shape_rows).
+int batch_shape(Job& j, int device) {
     oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
-    if (v.waves > waves) {
-        // the batch kernels of the 8-byte streamed layout run one wavefront
-        // per strip; other many-wavefront shapes become the streamed layout
-        if (v.hist != OILPAINT_HIST_STREAM8 && j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
+    if (!is_stream(v.hist) && v.waves > 1) {
+        if (j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
             v.hist = OILPAINT_HIST_STREAM;
             v.lanes = 64;
             v.rows = 0;
             v.per_cu = 8;
         }
-        v.waves = waves;
+        v.waves = 1;
     }
     for (;;) {
         const int st = apply_variant(j, v, device);
         if (st == OILPAINT_OK) return st;
         if (v.waves > 1)
-            v.waves >>= 1;
+            v.waves = 1;
         else if (v.rows > 8)
             v.rows >>= 1;
         else if (v.lanes > 16)
@@ -88,12 +86,13 @@ void shape_rows(std::vector<Job>& jobs, int device) {
         v.hist = j.hist;
         v.lanes = j.lanes;
         v.per_cu = 1;
-        v.rows = std::max(1, (rows + j.waves - 1) / j.waves);
+        const int runs = runs_per_tile(j.hist, j.waves);
+        v.rows = std::max(1, (rows + runs - 1) / runs);
         Job t = j;
         if (apply_variant(t, v, device) == OILPAINT_OK) {
             j = t;
         } else {  // own rows, tiles over this band
-            const long per_tile = (long)j.waves * j.rows;
+            const long per_tile = (long)runs * j.rows;
             j.tiles_y = (int)((band + per_tile - 1) / per_tile);
         }
     }
@@ -103,8 +102,9 @@ void shape_rows(std::vector<Job>& jobs, int device) {
 // pixel, plus the first window of every lane.
 double tile_cost(const Job& j) {
     const double span = 2.0 * j.radius + 1.0;
-    const double px = (double)j.lanes * j.rows * j.waves;
-    return px * (2.0 * span + j.levels * 0.5 + 4.0) + (double)j.lanes * j.waves * span * span;
+    const int runs = runs_per_tile(j.hist, j.waves);
+    const double px = (double)j.lanes * j.rows * runs;
+    return px * (2.0 * span + j.levels * 0.5 + 4.0) + (double)j.lanes * runs * span * span;
 }
 
 // One kernel class of a batch (batch_class): its jobs in queue order and
@@ -267,8 +267,9 @@ int enqueue_classes(const Layout& L, uint8_t* dev, int device, Branches& br, hip
         if (c.ntiles == 0) continue;
         const int b = (int)(std::min_element(load, load + nb) - load);
         load[b] += c.cost;
-        const int grid = std::min(batch_grid(device, c.cls, kBatchWaves, c.lds), c.ntiles);
-        if (launch_batch(class_args(L, (size_t)k, dev), c.cls, kBatchWaves, c.lds, grid, bs[b]) != hipSuccess)
+        const int waves = batch_waves(c.cls);
+        const int grid = std::min(batch_grid(device, c.cls, waves, c.lds), c.ntiles);
+        if (launch_batch(class_args(L, (size_t)k, dev), c.cls, waves, c.lds, grid, bs[b]) != hipSuccess)
             return OILPAINT_ERR_HIP;
         total += grid;
     }
@@ -410,7 +411,7 @@ int collect_jobs(const oilpaint_desc* descs, int n, int device, std::vector<Job>
         Job j;
         bool empty = false;
         int st = make_job(descs[i], nullptr, device, j, empty);
-        if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, device);
+        if (st == OILPAINT_OK && !empty) st = batch_shape(j, device);
         if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.src);
         if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.dst);
         if (st != OILPAINT_OK) {
@@ -476,6 +477,7 @@ struct oilpaint_queue {
                                     // tickets already reported by poll)
     size_t held = 0;  // requests not yet complete
     unsigned next_side = 0;  // side stream of the next single-band launch
+    bool last_direct = false;  // the last launch was one large request alone
 };
 
 namespace {
@@ -519,83 +521,127 @@ int retire(oilpaint_queue* q, bool block) {
     return OILPAINT_OK;
 }
 
-// Pack waiting work into one launch.  Every waiting request gets an equal
-// share of the launch's pixels (at least one tile row of its own shape), so
-// a small request that arrives behind a large one finishes in the next
-// launch instead of waiting for the large one to drain.  The launch covers
-// step_pixels, or a quarter of the waiting pixels when the backlog is larger
-// (at most 64 x step_pixels), so that a backlog keeps enough work in flight;
-// a lone request with nothing in flight runs whole.  A launch of a single
-// band uses the plain kernel with the request's own launch shape.
+// Waiting work goes out in launches.  Small requests are packed together:
+// each gets an equal share of the launch's pixels (at least one tile row of
+// its own shape), so a small request that arrives behind others finishes in
+// the next launch instead of waiting for them to drain.  Such a launch covers
+// step_pixels, or a quarter of the waiting small pixels when the backlog is
+// larger (at most 64 x step_pixels), so that a backlog keeps enough work in
+// flight.  A launch of a single band uses the plain kernel with the
+// request's own launch shape.  A request with at least kDirectPixels left
+// fills the GPU alone: it goes out whole as one plain launch with its own
+// tuned shape instead of in bands, on a side stream of its own, so that
+// batches of small requests run beside it.
+constexpr int64_t kDirectPixels = 4 << 20;
+
+int64_t pixels_left(const QueueReq& r) { return (int64_t)(r.job.row_end - r.next_row) * r.job.width; }
+
+// Rows [rb, re) of request t as one plain launch on the next side stream.
+int launch_direct(oilpaint_queue* q, uint64_t t, int rb, int re, hipStream_t* end) {
+    oilpaint_desc d = q->reqs[t].desc;
+    d.row_begin = rb;
+    d.row_end = re;
+    Job pj;
+    bool empty = false;
+    const hipStream_t side = q->branches->side[q->next_side++ % kMaxBranches];
+    *end = side;
+    const int st = make_job(d, nullptr, q->device, pj, empty);
+    if (st != OILPAINT_OK) return st;
+    if (!empty && launch_plain(pj, pj.waves, lds_bytes(pj), side) != hipSuccess) return OILPAINT_ERR_HIP;
+    return OILPAINT_OK;
+}
+
+// One launch of waiting work (returns 1, 0 if there was none, or an error):
+//   * a lone request with nothing in flight: the whole request, plain;
+//   * a large request (kDirectPixels): the whole request, plain -- at most
+//     every other launch while small requests wait, so that neither kind
+//     starves the other;
+//   * otherwise every waiting small request gets an equal share of the
+//     launch's pixels (at least one run of min_run_rows), one batch launch.
 int launch_step(oilpaint_queue* q) {
     if (q->waiting.empty()) return 0;
-    int64_t waiting_px = 0;
-    for (uint64_t t : q->waiting) {
-        const QueueReq& r = q->reqs[t];
-        waiting_px += (int64_t)(r.job.row_end - r.next_row) * r.job.width;
-    }
-    const bool lone = q->waiting.size() == 1 && q->inflight.empty();
-    int64_t budget = lone ? waiting_px
-                          : std::max(q->step_pixels, std::min(64 * q->step_pixels, waiting_px / 4));
-    std::vector<Job> jobs;
-    std::vector<uint64_t> tickets;
-    const int64_t share = std::max<int64_t>(1, budget / (int64_t)q->waiting.size());
-    std::deque<uint64_t> still;
-    for (uint64_t t : q->waiting) {
-        QueueReq& r = q->reqs[t];
-        if (budget <= 0) {
-            still.push_back(t);
-            continue;
-        }
-        const Job& w = r.job;
-        const int64_t row_px = (int64_t)w.width;
-        const int rb = r.next_row;
-        Job band = w;
-        band.row_begin = rb;
-        band.row_end = w.row_end;
-        const int64_t unit = min_run_rows(band);  // shortest band worth a tile
-        const int64_t want_rows =
-            std::max<int64_t>(unit, std::min<int64_t>(share, budget) / std::max<int64_t>(row_px, 1));
-        const int re = (int)std::min<int64_t>(w.row_end, rb + want_rows);
-        band.row_end = re;
-        jobs.push_back(band);
-        tickets.push_back(t);
-        r.next_row = re;
-        r.launches_left += 1;
-        budget -= (int64_t)(re - rb) * row_px;
-        if (re >= w.row_end)
-            r.all_launched = true;
-        else
-            still.push_back(t);
-    }
-    q->waiting.swap(still);
-    if (jobs.empty()) return 0;
     // The work goes to side streams only, so that nothing on the queue's own
     // stream (uploads, counter resets) waits for a running launch.
     if (!q->branches->ensure(kMaxBranches)) {
         (void)note_hip("branch streams", hipGetLastError());
         return OILPAINT_ERR_HIP;
     }
+    bool any_small = false;
+    auto big = q->waiting.end();
+    for (auto it = q->waiting.begin(); it != q->waiting.end(); ++it) {
+        const int64_t left = pixels_left(q->reqs[*it]);
+        if (left >= kDirectPixels) {
+            if (big == q->waiting.end()) big = it;
+        } else {
+            any_small = true;
+        }
+    }
+    const bool lone = q->waiting.size() == 1 && q->inflight.empty();
     hipStream_t ends[kMaxBranches];
     int nends = 0;
+    std::vector<uint64_t> tickets;
     int st = OILPAINT_OK;
-    if (jobs.size() == 1) {
-        oilpaint_desc d = q->reqs[tickets[0]].desc;
-        d.row_begin = jobs[0].row_begin;
-        d.row_end = jobs[0].row_end;
-        Job pj;
-        bool empty = false;
-        const hipStream_t side = q->branches->side[q->next_side++ % kMaxBranches];
-        st = make_job(d, nullptr, q->device, pj, empty);
-        if (st == OILPAINT_OK && !empty && launch_plain(pj, pj.waves, lds_bytes(pj), side) != hipSuccess)
-            st = OILPAINT_ERR_HIP;
-        ends[0] = side;
+    if (lone || (big != q->waiting.end() && (!q->last_direct || !any_small))) {
+        const uint64_t t = lone ? q->waiting.front() : *big;
+        QueueReq& r = q->reqs[t];
+        st = launch_direct(q, t, r.next_row, r.job.row_end, &ends[0]);
         nends = 1;
+        r.next_row = r.job.row_end;
+        r.launches_left += 1;
+        r.all_launched = true;
+        q->waiting.erase(lone ? q->waiting.begin() : big);
+        tickets.push_back(t);
+        q->last_direct = !lone;
     } else {
-        shape_rows(jobs, q->device);
-        Layout L;
-        build_layout(jobs, L);
-        st = enqueue_layout(L, q->device, *q->ring, *q->branches, q->stream, false, ends, &nends);
+        q->last_direct = false;
+        int64_t small_px = 0;
+        int nsmall = 0;
+        for (uint64_t t : q->waiting) {
+            const int64_t left = pixels_left(q->reqs[t]);
+            if (left < kDirectPixels) small_px += left, ++nsmall;
+        }
+        int64_t budget = std::max(q->step_pixels, std::min(64 * q->step_pixels, small_px / 4));
+        const int64_t share = std::max<int64_t>(1, budget / (int64_t)std::max(nsmall, 1));
+        std::vector<Job> jobs;
+        std::deque<uint64_t> still;
+        for (uint64_t t : q->waiting) {
+            QueueReq& r = q->reqs[t];
+            if (budget <= 0 || pixels_left(r) >= kDirectPixels) {
+                still.push_back(t);
+                continue;
+            }
+            const Job& w = r.job;
+            const int64_t row_px = (int64_t)w.width;
+            const int rb = r.next_row;
+            Job band = w;
+            band.row_begin = rb;
+            band.row_end = w.row_end;
+            const int64_t unit = min_run_rows(band);  // shortest band worth a tile
+            const int64_t want_rows =
+                std::max<int64_t>(unit, std::min<int64_t>(share, budget) / std::max<int64_t>(row_px, 1));
+            const int re = (int)std::min<int64_t>(w.row_end, rb + want_rows);
+            band.row_end = re;
+            jobs.push_back(band);
+            tickets.push_back(t);
+            r.next_row = re;
+            r.launches_left += 1;
+            budget -= (int64_t)(re - rb) * row_px;
+            if (re >= w.row_end)
+                r.all_launched = true;
+            else
+                still.push_back(t);
+        }
+        q->waiting.swap(still);
+        if (jobs.empty()) return 0;
+        if (jobs.size() == 1) {
+            st = launch_direct(q, tickets[0], jobs[0].row_begin, jobs[0].row_end, &ends[0]);
+            nends = 1;
+        } else {
+            shape_rows(jobs, q->device);
+            Layout L;
+            build_layout(jobs, L);
+            st = enqueue_layout(L, q->device, *q->ring, *q->branches, q->stream, false, ends, &nends);
+        }
     }
     if (st != OILPAINT_OK) return st;
     Inflight f;
@@ -733,7 +779,7 @@ int oilpaint_queue_push(oilpaint_queue* q, const oilpaint_desc* desc, uint64_t* 
     Job j;
     bool empty = false;
     int st = make_job(*desc, nullptr, q->device, j, empty);
-    if (st == OILPAINT_OK && !empty) st = batch_shape(j, kBatchWaves, q->device);
+    if (st == OILPAINT_OK && !empty) st = batch_shape(j, q->device);
     if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.src);
     if (st == OILPAINT_OK && !empty) st = check_device_ptr(j.dst);
     if (st != OILPAINT_OK) return st;

@@ -166,28 +166,43 @@ typedef void (*BatchKernel)(BatchArgs);
 extern const BatchKernel kBatchStream_lo[8][2];
 extern const BatchKernel kBatchStream_hi[8][2];
 extern const BatchKernel kBatchStream8[8];
+// Persistent batch forms of the four-wavefront streamed kernels
+// (oilpaint_k_split*.hip): [radius - 0 or 8][level bucket: up to 32, up to
+// 64 levels], and [radius - 8] for 8-byte entries.
+extern const BatchKernel kBatchSplit_lo[8][2];
+extern const BatchKernel kBatchSplit_hi[8][2];
+extern const BatchKernel kBatchSplit8[8];
 // Column-layout kernels (oilpaint_k_column.hip), [chunks - 1].
 extern const PlainKernel kColumn[kColumnChunks];
 extern const BatchKernel kBatchColumn[kColumnChunks];
 
 // Kernel class of a batch job: 2 * radius + scan bucket (0: scan <= 32,
 // 1: scan <= 64) for the streamed layout, 32 + radius - 8 for its 8-byte
-// form, 40 + chunks - 1 for the column layout, kGenericClass for every
-// other job (generic tile-staged and wide layouts, one kernel for all).  A
-// batch launches one persistent kernel per class present.
+// form, 40 + chunks - 1 for the column layout, then the same for the
+// four-wavefront streamed layouts (from kSplitClass: 2 * radius + bucket,
+// then 32 + radius - 8), and kGenericClass for every other job (generic
+// tile-staged and wide layouts, one kernel for all).  A batch launches one
+// persistent kernel per class present, of batch_waves(class) wavefronts per
+// workgroup.
 constexpr int kStream8Class = 2 * (kPackedMaxRadius + 1);
 constexpr int kColumnClass = kStream8Class + 8;
-constexpr int kGenericClass = kColumnClass + kColumnChunks;
+constexpr int kSplitClass = kColumnClass + kColumnChunks;
+constexpr int kGenericClass = kSplitClass + kStream8Class + 8;
 constexpr int kBatchClasses = kGenericClass + 1;
 inline int batch_class(const Job& j) {
+    const int split = is_split(j) ? kSplitClass : 0;
     if (j.hist == OILPAINT_HIST_STREAM && j.radius >= 0 && j.radius <= kPackedMaxRadius && j.scan <= 64)
-        return 2 * j.radius + (j.scan <= 32 ? 0 : 1);
+        return split + 2 * j.radius + (j.scan <= 32 ? 0 : 1);
     if (j.hist == OILPAINT_HIST_STREAM8 && j.radius >= 8 && j.radius <= kPackedMaxRadius && j.scan <= 32)
-        return kStream8Class + j.radius - 8;
+        return split + kStream8Class + j.radius - 8;
     if (j.hist == OILPAINT_HIST_COLUMN && j.radius >= 0 && j.radius <= kColumnMaxRadius)
         return kColumnClass + column_chunks(j.radius) - 1;
     return kGenericClass;
 }
+inline int batch_waves(int cls) { return cls >= kSplitClass && cls < kGenericClass ? kSplitWaves : 1; }
+// Output rows of one tile: a run per wavefront, except in the streamed
+// layouts, whose wavefronts share one run.
+inline int runs_per_tile(int hist, int waves) { return is_stream(hist) ? 1 : waves; }
 
 // Windowed median of one channel (oilpaint_k_median.hip): one image, one
 // wavefront per workgroup of 64 output columns by `rows` output rows.

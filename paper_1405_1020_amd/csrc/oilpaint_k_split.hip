@@ -1,6 +1,7 @@
 // Streamed-row kernels with 8-byte ring entries worked by four wavefronts per
-// strip (OILPAINT_HIST_STREAM8, waves 4), radius 8..15, by the number of bins
-// each wavefront's mode search scans.
+// strip (OILPAINT_HIST_STREAM8, waves 4), radius 8..15: plain kernels by the
+// number of bins each wavefront's mode search scans, and the persistent
+// batch form (up to 8 bins per wavefront, the count from the job).
 #include "oilpaint_device.h"
 
 namespace oilpaint_impl {
@@ -13,6 +14,12 @@ __global__ __launch_bounds__(64 * kSplitWaves) void k_plain_split8(Job j) {
     tile_stream_split<R, MB, true>(j, blockIdx.x, lds);
 }
 
+template <int R>
+__global__ __launch_bounds__(64 * kSplitWaves) void k_batch_split8(BatchArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    batch_stream_split<R, 8, true>(a, lds);
+}
+
 }  // namespace
 
 #define OILPAINT_SPLIT_ROW(R) {k_plain_split8<R, 2>, k_plain_split8<R, 4>, k_plain_split8<R, 5>, k_plain_split8<R, 8>}
@@ -23,5 +30,9 @@ const PlainKernel kStream8Split[8][4] = {OILPAINT_SPLIT_ROW(8),  OILPAINT_SPLIT_
                                          OILPAINT_SPLIT_ROW(14), OILPAINT_SPLIT_ROW(15)};
 
 #undef OILPAINT_SPLIT_ROW
+
+// By [radius - 8].
+const BatchKernel kBatchSplit8[8] = {k_batch_split8<8>,  k_batch_split8<9>,  k_batch_split8<10>, k_batch_split8<11>,
+                                     k_batch_split8<12>, k_batch_split8<13>, k_batch_split8<14>, k_batch_split8<15>};
 
 }  // namespace oilpaint_impl

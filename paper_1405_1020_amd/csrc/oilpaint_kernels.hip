@@ -93,6 +93,12 @@ int g_batch_lds_done[kBatchClasses];
 
 BatchKernel batch_kernel(int cls) {
     if (cls < 0 || cls >= kGenericClass) return k_batch;
+    if (cls >= kSplitClass) {
+        const int c = cls - kSplitClass;
+        if (c >= kStream8Class) return kBatchSplit8[c - kStream8Class];
+        const int r = c >> 1, b = c & 1;
+        return r <= 7 ? kBatchSplit_lo[r][b] : kBatchSplit_hi[r - 8][b];
+    }
     if (cls >= kColumnClass) return kBatchColumn[cls - kColumnClass];
     if (cls >= kStream8Class) return kBatchStream8[cls - kStream8Class];
     const int r = cls >> 1, b = cls & 1;
@@ -143,7 +149,7 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
 
 hipError_t launch_batch(const BatchArgs& a, int cls, int waves, size_t lds, int grid, hipStream_t stream) {
     if (a.ntiles <= 0) return hipSuccess;
-    if (cls < 0 || cls >= kBatchClasses || (cls < kGenericClass && waves != 1)) return hipErrorInvalidValue;
+    if (cls < 0 || cls >= kBatchClasses || waves != batch_waves(cls)) return hipErrorInvalidValue;
     const BatchKernel k = batch_kernel(cls);
     const hipError_t e = allow_lds(reinterpret_cast<const void*>(k), lds, g_batch_lds_done[cls]);
     if (e != hipSuccess) return e;

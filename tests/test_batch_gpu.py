@@ -189,3 +189,37 @@ def test_queue_bulk_completion_and_lone_request():
     with pytest.raises(B.OilpaintError):
         q.poll(t0)
     q.close()
+
+
+@pytest.mark.gpu
+def test_queue_large_requests_whole_beside_batches():
+    """Requests of at least 4 Mi pixels go out whole as plain launches,
+    alternating with batch launches of the small ones; every output equals
+    the plain kernel's, and sampled pixels of the large ones the oracle's."""
+    torch = torch_mod()
+    large = [(synth.make_image(2304, 1824, seed=301, n_blobs=12, sigma=(10, 120)), 10, 20, 0),
+             (synth.make_image(2100, 2100, seed=302, n_blobs=12, sigma=(10, 120)), 3, 64, 2)]
+    cases = large[:1] + small_batch(10, seed=31) + large[1:]
+    items, keep = device_items(cases)
+    q = B.Queue(capacity=64, step_pixels=20000)
+    tickets = {q.push(it): i for i, it in enumerate(items)}
+    got = []
+    while len(got) < len(tickets):
+        got += q.completed()
+    assert sorted(got) == sorted(tickets)
+    torch.cuda.synchronize()
+    for (img, r, L, pad), it in zip(cases, items):
+        want, _ = empty_like_device(img, pad=pad, seed=7)
+        B.oilpaint_async(it.src, want, r, L)
+        torch.cuda.synchronize()
+        assert torch.equal(want, it.dst), (img.shape, r, L)
+    rng = np.random.default_rng(3)
+    for (img, r, L, pad), it in zip(cases, items):
+        if img.shape[0] * img.shape[1] < (4 << 20):
+            continue
+        out = from_device(it.dst)
+        h, w, _ = img.shape
+        pts = [(0, 0), (w - 1, h - 1)] + [(int(rng.integers(0, w)), int(rng.integers(0, h))) for _ in range(40)]
+        for x, y in pts:
+            assert tuple(out[y, x]) == tuple(ref_pixel(img, x, y, r, L)), (img.shape, x, y)
+    q.close()
