@@ -452,9 +452,11 @@ def _pmc_rows(folder: str, counter: str):
 def launch_threads(w: int, h: int, variant) -> int:
     """Work-items of a plain launch of a w x h image with a resolved variant
     (rows, waves, hist, lanes, per_cu): one workgroup of 64 x waves per tile
-    (the profiler's grid size)."""
-    rows, waves, lanes = variant[0], variant[1], variant[3]
-    tiles = -(-w // lanes) * -(-h // (waves * rows))
+    (the profiler's grid size); a tile spans waves x rows output rows, except
+    in the streamed layouts (hist 1 and 3), whose wavefronts share one run."""
+    rows, waves, hist, lanes = variant[0], variant[1], variant[2], variant[3]
+    runs = 1 if hist in (1, 3) else waves
+    tiles = -(-w // lanes) * -(-h // (runs * rows))
     return tiles * 64 * waves
 
 
