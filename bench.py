@@ -416,10 +416,10 @@ def cpu_baseline(oracle_mod, img, runs):
             "sample": "the full 1920x1080 sweep (7 runs), row bands over %d threads, %.1f s wall" % (threads, dt)}
 
 
-def hbm_traffic(kernel: str, config: str):
+def hbm_traffic(kernel: str, config: str, variant=None):
     """HBM bytes per launch of `kernel` on sweep run `config`, from the
     committed counter summary, if it was taken on the current kernel source
-    (else None)."""
+    and (when given) the same resolved launch shape (else None)."""
     try:
         d = json.load(open(HBM_PROFILE))
     except (OSError, ValueError):
@@ -428,6 +428,8 @@ def hbm_traffic(kernel: str, config: str):
         return None
     e = d.get("launches", {}).get(config)
     if not e or e.get("kernel") != kernel:
+        return None
+    if variant is not None and list(e.get("variant", [])) != list(variant):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -567,7 +569,7 @@ def main():
     d_ach = d_bytes / (d["ms"] / 1e3) / 1e9
     res["roofline"] = {"bound": "lds", "achieved": round(d_ach, 1), "peak": round(LDS_PEAK_GBS, 1),
                        "unit": "GB/s", "frac": round(d_ach / LDS_PEAK_GBS, 4),
-                       "traffic": hbm_traffic(d["kernel"], dom), "kernel": d["kernel"], "run": dom,
+                       "traffic": hbm_traffic(d["kernel"], dom, d["variant"]), "kernel": d["kernel"], "run": dom,
                        "lds_bytes_per_launch": d_bytes, "avg_launch_ms": d["ms"],
                        "sweep_achieved": round(achieved, 1), "sweep_avg_launch_ms": round(launch_ms, 5)}
     res["sweep"] = per

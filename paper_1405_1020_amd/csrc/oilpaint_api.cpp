@@ -159,20 +159,22 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     return OILPAINT_OK;
 }
 
-// The built-in launch shape (before any tuning result): streamed rows with
-// about eight one-wavefront workgroups per CU when the window and level
-// count allow it; for radii 16..255 column histograms, about two
-// workgroups per CU, when they fit on chip; otherwise tiles of four
-// wavefronts, about two per CU, or the wide layout; shrunk until the
+// The built-in launch shape (before any tuning result): streamed rows when
+// the window and level count allow it -- four wavefronts per strip, about
+// four workgroups per CU, for radius 7 and up or more than 32 levels, else
+// one wavefront, about eight per CU; for radii 16..255 column histograms,
+// about two workgroups per CU, when they fit on chip; otherwise tiles of
+// four wavefronts, about two per CU, or the wide layout; shrunk until the
 // on-chip footprint fits.
 oilpaint_variant default_variant(int width, int height, int reff, int levels, bool paper, int device) {
     oilpaint_variant v;
     v.rows = 0;
     v.lanes = 64;
     if (reff <= kPackedMaxRadius && levels <= 64) {
-        v.waves = 1;
+        const bool split = reff >= 7 || levels > 32;
+        v.waves = split ? kSplitWaves : 1;
         v.hist = OILPAINT_HIST_STREAM;
-        v.per_cu = 8;
+        v.per_cu = split ? 4 : 8;
         return v;
     }
     if (reff > kPackedMaxRadius && reff <= kColumnMaxRadius) {

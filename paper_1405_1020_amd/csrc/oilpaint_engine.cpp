@@ -23,15 +23,24 @@ oilpaint_variant choose_variant(int width, int height, int reff, int levels, boo
 
 namespace {
 
+// Smallest radius whose batch tiles use four wavefronts per strip: below it
+// a persistent class's long runs leave one wavefront per strip ahead (the
+// two barriers per row cost more than the little work between them).
+constexpr int kBatchSplitMinRadius = 8;
+
 // Layout of a job inside a persistent launch: the streamed layouts as the
 // job's own choice (four wavefronts sharing a strip where that is its plain
-// shape, else one), every other layout with one computing wavefront per
+// shape and the radius is at least kBatchSplitMinRadius, else one), every other layout with one computing wavefront per
 // workgroup (a tile-staged shape of several wavefronts becomes the streamed
 // layout when it applies); shrunk (wavefronts, then rows, then lanes) until
 // its on-chip footprint fits.  The rows are set afterwards for the whole
 // launch (shape_rows).
 int batch_shape(Job& j, int device) {
     oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
+    if (is_stream(v.hist) && v.waves > 1 && j.radius < kBatchSplitMinRadius) {
+        v.waves = 1;
+        v.per_cu = 8;
+    }
     if (!is_stream(v.hist) && v.waves > 1) {
         if (j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
             v.hist = OILPAINT_HIST_STREAM;

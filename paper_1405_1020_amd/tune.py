@@ -50,13 +50,13 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
         for per_cu in (2, 4, 8, 16, 32):
             out.append(B.Variant(0, 1, B.HIST_STREAM, 64, per_cu))
         # four wavefronts per strip
-        for per_cu in (2, 4, 8, 16):
+        for per_cu in (2, 3, 4, 5, 6, 8, 16):
             out.append(B.Variant(0, 4, B.HIST_STREAM, 64, per_cu))
     if 8 <= radius <= 15 and levels <= 32:
         for per_cu in (2, 4, 8, 16):
             out.append(B.Variant(0, 1, B.HIST_STREAM8, 64, per_cu))
         # four wavefronts per strip
-        for per_cu in (1, 2, 4, 8):
+        for per_cu in (1, 2, 3, 4, 5, 8):
             out.append(B.Variant(0, 4, B.HIST_STREAM8, 64, per_cu))
     if radius <= 15 and levels <= 255:
         for waves in (2, 4):

@@ -92,6 +92,10 @@ def test_pick_variant_shapes():
     # a GPU it falls back to nominal facts
     vv = B.pick_variant(1920, 1080, 5, 20)
     assert vv.hist == B.HIST_STREAM and vv.lanes == 64 and vv.waves == 1 and vv.rows >= 1
+    # four wavefronts per strip for wide windows and many levels
+    for r, L in ((7, 20), (15, 20), (5, 64)):
+        vv = B.pick_variant(1920, 1080, r, L)
+        assert vv.hist == B.HIST_STREAM and vv.lanes == 64 and vv.waves == 4 and vv.rows >= 1, (r, L)
     vv = B.pick_variant(1920, 1080, 5, 100)
     assert vv.hist == B.HIST_PACKED and vv.lanes in (16, 32, 64) and 1 <= vv.waves <= 8 and vv.rows >= 1
     assert B.pick_variant(1920, 1080, 16, 20).hist == B.HIST_COLUMN
