@@ -223,3 +223,25 @@ def test_queue_large_requests_whole_beside_batches():
         for x, y in pts:
             assert tuple(out[y, x]) == tuple(ref_pixel(img, x, y, r, L)), (img.shape, x, y)
     q.close()
+
+
+@pytest.mark.gpu
+def test_paper_flag_in_four_wavefront_classes():
+    # paper-form jobs of radius 8 and up run in the four-wavefront batch classes
+    torch = torch_mod()
+    cases = []
+    for k, (r, L) in enumerate([(8, 20), (15, 8), (12, 33), (9, 64)]):
+        img = synth.make_image(150 + 13 * k, 97 + 7 * k, seed=60 + k, n_blobs=5, sigma=(4, 30))
+        img[5:25, 5:45] = 255
+        cases.append((img, r, L))
+    items, want = [], []
+    for k, (img, r, L) in enumerate(cases):
+        junk = np.random.default_rng(k).integers(0, 256, size=img.shape, dtype=np.uint8)
+        src, _ = to_device(img)
+        dst, _ = to_device(junk)
+        items.append(B.Item(src, dst, r, L, flags=B.FLAG_PAPER))
+        want.append(ref(img, r, L, paper=True, out=junk.copy()))
+    B.batch(items)
+    torch.cuda.synchronize()
+    for (img, r, L), it, w in zip(cases, items, want):
+        assert first_mismatch(from_device(it.dst), w) is None, (img.shape, r, L)

@@ -199,3 +199,25 @@ def test_sampled_pixels_full_size_camera():
     pts += [(int(x), int(y)) for x, y in zip(rng.integers(0, w, 200), rng.integers(0, h, 200))]
     for x, y in pts:
         assert tuple(got[y, x]) == tuple(ref_pixel(img, x, y, r, L)), (x, y)
+
+
+@pytest.mark.parametrize("r", [3, 7, 10, 15])
+def test_paper_form_every_default_layout(r):
+    # the listing's literal form (interior pixels only, the pure-white level
+    # never chosen, nothing written where the winning count is 0) through the
+    # library's own launch shapes: one wavefront per strip below radius 7,
+    # four from 7 on, the tile-staged or wide layouts beyond 64 levels
+    torch = torch_mod()
+    img = synth.make_image(203, 149, seed=40 + r, n_blobs=6, sigma=(4, 40))
+    img[20:60, 30:90] = 255
+    img[100:104, :] = 255
+    junk = np.random.default_rng(r).integers(0, 256, size=img.shape, dtype=np.uint8)
+    for L in (8, 20, 33, 64, 200):
+        print("paper", r, L, flush=True)
+        src, _ = to_device(img, pad=3, seed=1)
+        dst, dbuf = to_device(junk, pad=3, seed=2)
+        B.run(B.Item(src, dst, r, L, flags=B.FLAG_PAPER))
+        torch.cuda.synchronize()
+        want = ref(img, r, L, paper=True, out=junk.copy())
+        mm = first_mismatch(from_device(dst), want)
+        assert mm is None, (r, L, B.pick_variant(203, 149, r, L).as_tuple(), mm)
