@@ -114,15 +114,27 @@ def load() -> int:
     return install(_load_file())
 
 
+# A later candidate replaces an earlier one only when it is faster by more
+# than this fraction, so that near-ties resolve the same way from run to run.
+TIE = 0.02
+
+
+def pick(timed):
+    """The first (candidate, ms) within TIE of the fastest."""
+    fastest = min(t for _, t in timed)
+    return next((c, t) for c, t in timed if t <= fastest * (1.0 + TIE))
+
+
 def tune(radius: int, levels: int, width: int = 1920, height: int = 1080, reps: int = 5) -> dict:
     """Time the candidates for (radius, levels) on a width x height image and
-    return {"variant": [...], "ms": best, "all": [(variant, ms), ...]}."""
+    return {"variant": [...], "ms": best, "all": [(variant, ms), ...]}; near
+    ties go to the earlier candidate (pick)."""
     cands = candidates(radius, levels)
     times = B.tune_times(width, height, radius, levels, cands, reps=reps)
     ok = [(c, t) for c, t in zip(cands, times) if t > 0]
     if not ok:
         raise B.OilpaintError(B.ERR_UNSUPPORTED, "no candidate runs (r=%d, L=%d)" % (radius, levels))
-    best, ms = min(ok, key=lambda ct: ct[1])
+    best, ms = pick(ok)
     return {"variant": list(best.as_tuple()), "ms": ms, "size": [width, height],
             "all": [(list(c.as_tuple()), t) for c, t in zip(cands, times)]}
 
