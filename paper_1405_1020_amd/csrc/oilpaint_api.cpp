@@ -354,18 +354,26 @@ int oilpaint_median_async(const uint8_t* src, int src_stride, int channels, int 
     j.channels = channels;
     j.channel = channel;
     j.radius = reff;
-    // as many one-wavefront workgroups per CU as fit on chip (at most 8), so
-    // that the whole grid is resident and runs are as long as that allows:
-    // 8 .. 1024 rows
+    // as many workgroups per CU as are resident at once (the kernel's
+    // occupancy at this LDS size, at most 8), so that the whole grid runs in
+    // one wave and runs are as long as that allows: 8 .. 1024 rows; one or
+    // four wavefronts per strip (median_split)
+    const bool split = median_split(reff);
+    const MedianKernel kern = split ? kMedian4[reff] : kMedian[reff];
     const long strips = (width + 63) / 64;
     const size_t lds = median_lds_bytes(reff);
-    const long fit = (long)((d.ok ? d.lds_per_block : 65536) / lds);
-    const long want = std::max(1L, std::min(fit, 8L)) * (d.ok ? d.cus : 256);
+    int fit = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void*>(kern), split ? 256 : 64,
+                                                     lds) != hipSuccess ||
+        fit < 1) {
+        (void)hipGetLastError();
+        fit = (int)std::max<size_t>(1, (d.ok ? d.lds_per_block : 65536) / lds);
+    }
+    const long want = std::max(1L, std::min((long)fit, 8L)) * (d.ok ? d.cus : 256);
     j.rows = (int)std::max(8L, std::min((strips * height + want - 1) / want, 1024L));
     j.tiles_x = (int)strips;
     j.tiles_y = (height + j.rows - 1) / j.rows;
-    hipLaunchKernelGGL(kMedian[reff], dim3(j.tiles_x * j.tiles_y), dim3(64), median_lds_bytes(reff),
-                       (hipStream_t)stream, j);
+    hipLaunchKernelGGL(kern, dim3(j.tiles_x * j.tiles_y), dim3(split ? 256 : 64), lds, (hipStream_t)stream, j);
     return note_hip("median launch", hipGetLastError()) == hipSuccess ? OILPAINT_OK : OILPAINT_ERR_HIP;
 }
 
