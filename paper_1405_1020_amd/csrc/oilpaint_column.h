@@ -1,0 +1,288 @@
+// Device code of the column-histogram layout (OILPAINT_HIST_COLUMN), used by
+// oilpaint_k_column.hip only.
+#pragma once
+
+#include "oilpaint_device.h"
+
+namespace oilpaint_impl {
+namespace dev {
+
+// ---------------------------------------------------------------------------
+// COLUMN layout (any radius up to 255): the window histogram of every lane
+// from column histograms, with no per-radius work per output row.
+// ---------------------------------------------------------------------------
+// One wavefront per workgroup, 64 output columns, a run of rows.  LDS holds,
+// for each of the 64+2r columns of the strip, the histogram of its 2r+1
+// window rows (column histograms; L levels plus a sink row for outside
+// pixels and the paper form's white level).  Per output row and level, an
+// inclusive prefix sum of the column histograms across the strip -- a
+// wavefront scan per 64 columns -- gives every lane its window as the
+// difference of two prefix entries; the running maximum over levels (first
+// strictly larger count wins, so the lowest level wins ties) is the mode.
+// Moving one row down changes each column histogram by two pixels.
+//   LDS: [column histograms: (L+1) x (64+2r) x 8 B][prefix: (64+2r+1) x 16 B]
+//        [output row buffer: 192 B]
+// Column histogram entry: count:13 @51 | sum2:17 @34 | sum1:17 @17 |
+// sum0:17 @0 (count <= 511, sums <= 130,305 for r <= 255).  Prefix entries
+// and window sums are four 32-bit fields (window count <= 261,121, sums <=
+// 66,585,855).
+
+// Inclusive prefix sum over the 64 lanes of a wavefront: shifts within the
+// 16-lane rows, then the last lane of each row broadcast into the next rows.
+// Every lane must be active.
+__device__ __forceinline__ uint32_t wave_scan_add(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ uint64_t column_inc(uint32_t c0, uint32_t c1, uint32_t c2) {
+    return (uint64_t)c0 | ((uint64_t)c1 << 17) | ((uint64_t)c2 << 34) | (1ull << 51);
+}
+
+struct Sums4 {
+    uint32_t n, a, b, c;  // count, sum0, sum1, sum2
+};
+
+__device__ __forceinline__ Sums4 column_unpack(uint64_t e) {
+    const uint32_t lo = (uint32_t)e, hi = (uint32_t)(e >> 32);
+    Sums4 r;
+    r.a = lo & 0x1FFFFu;
+    r.b = (lo >> 17) | ((hi & 0x3u) << 15);
+    r.c = (hi >> 2) & 0x1FFFFu;
+    r.n = hi >> 19;
+    return r;
+}
+
+// floor(s / n) for s < 2^27 and 1 <= n < 2^19: the product with the correctly
+// rounded double reciprocal is within a tiny fraction of s/n, so truncating
+// it gives the quotient or one less; the integer checks correct either way.
+__device__ __forceinline__ uint32_t div_exact32(uint32_t s, uint32_t n, double rn) {
+    uint32_t q = (uint32_t)((double)s * rn);
+    q += ((q + 1u) * n <= s) ? 1u : 0u;
+    q -= (q * n > s) ? 1u : 0u;
+    return q;
+}
+
+// Three bytes of an image pixel at (gx, gy), coordinates clamped into the
+// image (so the load needs no branch) and `in` telling whether it is real.
+struct PixelBytes {
+    uint32_t c0, c1, c2;
+    bool in;
+    __device__ __forceinline__ void load(const Job& j, int gx, int gy, bool valid) {
+        in = valid && gy >= 0 && gy < j.height && gx >= 0 && gx < j.width;
+        const int gyc = min(max(gy, 0), j.height - 1);
+        const int gxc = min(max(gx, 0), j.width - 1);
+        gsrc_t q = gsrc(j.src) + (size_t)gyc * (size_t)j.stride + 3 * gxc;
+        c0 = q[0];
+        c1 = q[1];
+        c2 = q[2];
+    }
+    // column-histogram row: the level, or the sink (row L) for outside
+    // pixels and the paper form's white level
+    __device__ __forceinline__ uint32_t row(const Job& j) const {
+        if (!in) return (uint32_t)j.levels;
+        const uint32_t lev = level_of(c0 + c1 + c2, (uint32_t)j.levels, j.paper != 0);
+        return lev >= (uint32_t)j.levels ? (uint32_t)j.levels : lev;
+    }
+};
+
+// NT: 64-column chunks of the strip with its halo, ceil((64 + 2r) / 64).
+template <int NT>
+__device__ __forceinline__ void tile_column(const Job& j, int unit, uint8_t* lds) {
+    const int R = j.radius;
+    const int TW = 64 + 2 * R;
+    const int L = j.levels;
+    const int lane = threadIdx.x & 63;
+    const int tx = unit % j.tiles_x;
+    const int ty = unit / j.tiles_x;
+    const int x0 = tx * 64;
+    const int ya = j.row_begin + ty * j.rows;
+    const int yb = min(ya + j.rows, j.row_end);
+    const size_t chb = ((size_t)(L + 1) * TW * 8 + 15) & ~(size_t)15;
+    uint8_t* ch = lds;
+    uint32_t* P = reinterpret_cast<uint32_t*>(lds + chb);  // (TW + 1) entries of 4 words
+    uint8_t* obuf = lds + chb + (size_t)(TW + 1) * 16;
+    auto entry = [&](uint32_t row, int c) { return reinterpret_cast<uint64_t*>(ch + ((size_t)row * TW + c) * 8); };
+
+    {
+        const int n16 = (int)((size_t)(L + 1) * TW * 8 / 16);
+        for (int e = lane; e < n16; e += 64) *reinterpret_cast<uint4*>(ch + (size_t)e * 16) = make_uint4(0u, 0u, 0u, 0u);
+        if (lane == 0) *reinterpret_cast<uint4*>(P) = make_uint4(0u, 0u, 0u, 0u);
+    }
+    lds_order();
+    // column histograms of rows ya-R .. ya+R, the (2R+1) x TW pixels spread
+    // over the lanes (no two lanes of one instruction share a column)
+    {
+        // pixel p = base + 64 i sits at (p / TW, p % TW), tracked by steps of
+        // 64 (TW >= 64, so one wrap at most); sixteen pixels per lane in
+        // flight
+        const int NP = (2 * R + 1) * TW;
+        constexpr int CH = 16;
+        int row = 0, col = lane;
+        for (int base = lane; base < NP; base += CH * 64) {
+            PixelBytes px[CH];
+            int cl[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                cl[i] = col;
+                px[i].load(j, x0 - R + col, ya - R + row, base + i * 64 < NP);
+                col += 64;
+                if (col >= TW) {
+                    col -= TW;
+                    ++row;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+                if (base + i * 64 < NP)
+                    lds_add(entry(px[i].row(j), cl[i]), column_inc(px[i].c0, px[i].c1, px[i].c2));
+        }
+    }
+    lds_order();
+#pragma unroll 1
+    for (int y = ya; y < yb; ++y) {
+        // pixels of the step y -> y+1, fetched now and applied after the row:
+        // the leaving row y-R and the entering row y+1+R of every column
+        const bool step = y + 1 < yb;
+        PixelBytes lv[NT], ev[NT];
+        if (step) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = lane + 64 * t;
+                lv[t].load(j, x0 - R + c, y - R, c < TW);
+                ev[t].load(j, x0 - R + c, y + 1 + R, c < TW);
+            }
+        }
+        // pass 1: the window count of every level for every lane (prefix sums
+        // of the column counts across the strip), four levels at a time --
+        // four independent scans, one prefix entry of four counts, one LDS
+        // round trip; levels are compared in increasing order and the first
+        // strictly larger count wins, so the lowest level wins ties
+        Sums4 best = {0u, 0u, 0u, 0u};
+        uint32_t bk = 0;
+        auto count_of = [&](int k, int c) -> uint32_t {
+            return reinterpret_cast<const uint32_t*>(entry((uint32_t)k, c))[1] >> 19;
+        };
+#pragma unroll 1
+        for (int k0 = 0; k0 < L; k0 += 4) {
+            const bool h1 = k0 + 1 < L, h2 = k0 + 2 < L, h3 = k0 + 3 < L;
+            uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;  // totals of the chunks before
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = lane + 64 * t;
+                uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+                if (c < TW) {
+                    n0 = count_of(k0, c);
+                    if (h1) n1 = count_of(k0 + 1, c);
+                    if (h2) n2 = count_of(k0 + 2, c);
+                    if (h3) n3 = count_of(k0 + 3, c);
+                }
+                n0 = wave_scan_add(n0) + q0;
+                n1 = wave_scan_add(n1) + q1;
+                n2 = wave_scan_add(n2) + q2;
+                n3 = wave_scan_add(n3) + q3;
+                if (c < TW) *reinterpret_cast<uint4*>(P + (size_t)(c + 1) * 4) = make_uint4(n0, n1, n2, n3);
+                if (t + 1 < NT) {
+                    q0 = (uint32_t)__builtin_amdgcn_readlane((int)n0, 63);
+                    q1 = (uint32_t)__builtin_amdgcn_readlane((int)n1, 63);
+                    q2 = (uint32_t)__builtin_amdgcn_readlane((int)n2, 63);
+                    q3 = (uint32_t)__builtin_amdgcn_readlane((int)n3, 63);
+                }
+            }
+            lds_order();
+            const uint4 hi = *reinterpret_cast<const uint4*>(P + (size_t)(lane + 2 * R + 1) * 4);
+            const uint4 lo = *reinterpret_cast<const uint4*>(P + (size_t)lane * 4);
+            const uint32_t w0 = hi.x - lo.x, w1 = hi.y - lo.y, w2 = hi.z - lo.z, w3 = hi.w - lo.w;
+            if (w0 > best.n) {
+                best.n = w0;
+                bk = (uint32_t)k0;
+            }
+            if (w1 > best.n) {
+                best.n = w1;
+                bk = (uint32_t)k0 + 1;
+            }
+            if (w2 > best.n) {
+                best.n = w2;
+                bk = (uint32_t)k0 + 2;
+            }
+            if (w3 > best.n) {
+                best.n = w3;
+                bk = (uint32_t)k0 + 3;
+            }
+            lds_order();
+        }
+        // pass 2: the channel sums of each lane's winning level, one set of
+        // prefix sums per distinct winner in the wavefront (neighbouring
+        // pixels mostly share their mode)
+        uint64_t pending = __ballot(best.n > 0);
+        while (pending) {
+            const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)bk, (int)__builtin_ctzll(pending));
+            uint32_t ca = 0, cb = 0, cc = 0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = lane + 64 * t;
+                uint64_t e = 0;
+                if (c < TW) e = *entry(k, c);
+                Sums4 v = column_unpack(e);
+                v.a = wave_scan_add(v.a) + ca;
+                v.b = wave_scan_add(v.b) + cb;
+                v.c = wave_scan_add(v.c) + cc;
+                if (c < TW) *reinterpret_cast<uint4*>(P + (size_t)(c + 1) * 4) = make_uint4(0u, v.a, v.b, v.c);
+                if (t + 1 < NT) {
+                    ca = (uint32_t)__builtin_amdgcn_readlane((int)v.a, 63);
+                    cb = (uint32_t)__builtin_amdgcn_readlane((int)v.b, 63);
+                    cc = (uint32_t)__builtin_amdgcn_readlane((int)v.c, 63);
+                }
+            }
+            lds_order();
+            const bool mine = best.n > 0 && bk == k;
+            if (mine) {
+                const uint4 hi = *reinterpret_cast<const uint4*>(P + (size_t)(lane + 2 * R + 1) * 4);
+                const uint4 lo = *reinterpret_cast<const uint4*>(P + (size_t)lane * 4);
+                best.a = hi.y - lo.y;
+                best.b = hi.z - lo.z;
+                best.c = hi.w - lo.w;
+            }
+            pending &= ~__ballot(mine);
+            lds_order();
+        }
+        uint32_t px = 0;
+        if (best.n > 0) {
+            const double rn = 1.0 / (double)best.n;
+            px = div_exact32(best.a, best.n, rn) | (div_exact32(best.b, best.n, rn) << 8) |
+                 (div_exact32(best.c, best.n, rn) << 16);
+        }
+        store_row(j, x0, y, best.n, px, obuf);
+        if (step) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = lane + 64 * t;
+                if (c < TW) {
+                    lds_sub(entry(lv[t].row(j), c), column_inc(lv[t].c0, lv[t].c1, lv[t].c2));
+                    lds_add(entry(ev[t].row(j), c), column_inc(ev[t].c0, ev[t].c1, ev[t].c2));
+                }
+            }
+            lds_order();
+        }
+    }
+}
+
+// One class of a batch in the column layout.
+template <int NT>
+__device__ __forceinline__ void batch_column(const BatchArgs& a, uint8_t* lds) {
+    for (;;) {
+        const int32_t t = next_tile_wave(a.counter);
+        if (t >= a.ntiles) break;
+        const int i = job_of(a, t);
+        const Job jb = a.jobs[i];
+        tile_column<NT>(jb, t - a.first_tile[i], lds);
+    }
+}
+
+}  // namespace dev
+}  // namespace oilpaint_impl

@@ -1,7 +1,7 @@
 // Column-layout kernels (OILPAINT_HIST_COLUMN), plain and persistent batch
 // forms, by the number of 64-column chunks of a strip with its halo
 // (1..9: radius up to 255).
-#include "oilpaint_device.h"
+#include "oilpaint_column.h"
 
 namespace oilpaint_impl {
 using namespace dev;
