@@ -120,8 +120,10 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *                         levels <= 255 (<= 254 with OILPAINT_FLAG_PAPER)
  *   OILPAINT_HIST_STREAM  the PACKED bins with only the 2r+2 image rows the
  *                         windows span kept on chip, fetched as the run
- *                         advances; one wavefront of 64 lanes per workgroup
- *                         (waves = 1, lanes = 64), radius <= 15, levels <= 64
+ *                         advances; 64 lanes, radius <= 15, levels <= 64;
+ *                         waves = 1 (one wavefront per strip) or 4 (four
+ *                         wavefronts share a strip, as described for
+ *                         OILPAINT_HIST_STREAM8)
  *   OILPAINT_HIST_WIDE    32-bit count and sums, pixels read from device
  *                         memory; any level count and radius up to 2051
  *   OILPAINT_HIST_STREAM8 OILPAINT_HIST_STREAM whose on-chip rows hold each

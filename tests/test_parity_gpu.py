@@ -221,3 +221,24 @@ def test_paper_form_every_default_layout(r):
         want = ref(img, r, L, paper=True, out=junk.copy())
         mm = first_mismatch(from_device(dst), want)
         assert mm is None, (r, L, B.pick_variant(203, 149, r, L).as_tuple(), mm)
+
+
+def test_row_bands_four_wavefronts():
+    # output-row bands through the descriptor path (each band a launch of its
+    # own, its windows reaching rows outside the band) with the four-wavefront
+    # streamed shapes, against the whole image's oracle output
+    torch = torch_mod()
+    img = synth.make_image(190, 141, seed=71, n_blobs=6, sigma=(4, 40))
+    for r, L, hist in ((10, 20, B.HIST_STREAM), (12, 32, B.HIST_STREAM8), (15, 64, B.HIST_STREAM)):
+        want = ref(img, r, L)
+        src, _ = to_device(img, pad=2)
+        dst, _ = empty_like_device(img, pad=2)
+        B.set_variant(r, L, B.Variant(0, 4, hist, 64, 4))
+        try:
+            for a, b in ((0, 1), (1, 30), (30, 31), (31, 100), (100, 141)):
+                B.run(B.Item(src, dst, r, L, row_begin=a, row_end=b))
+            torch.cuda.synchronize()
+        finally:
+            B.clear_variants()
+        mm = first_mismatch(from_device(dst), want)
+        assert mm is None, (r, L, hist, mm)
