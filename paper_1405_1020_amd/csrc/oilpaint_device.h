@@ -23,10 +23,10 @@
 //     spare level that the mode search never scans, so the window needs no
 //     clipping logic.
 //   * STREAM layout (the default for r <= 15, L <= 64): one wavefront per
-//     workgroup; only the 2r+4 image rows around the window are staged, in a
-//     ring, as 4-byte words {c0, c1, c2, level} or (STREAM8) as 8-byte ready
-//     bin increments; a run's first window comes either from direct updates
-//     or from column histograms.
+//     strip, or four sharing it (tile_stream_split); only the 2r+4 image rows
+//     around the window are staged, in a ring, as 4-byte words {c0, c1, c2,
+//     level} or (STREAM8) as 8-byte ready bin increments; a run's first
+//     window comes either from direct updates or from column histograms.
 //   * PACKED layout: the whole tile plus its r-pixel halo staged once, shared
 //     by several wavefronts.
 //   * COLUMN layout (r up to 255, oilpaint_column.h): column histograms and
@@ -557,8 +557,9 @@ __device__ __forceinline__ void tile_wide(const Job& j, int tile, uint8_t* lds) 
     }
 }
 
-// STREAM layout: one wavefront per workgroup, 64 output columns, a run of
-// `rows` output rows.  Only the 2r+4 image rows around the window are
+// STREAM layout, one wavefront per workgroup (tile_stream; the four-wavefront
+// form is tile_stream_split below): 64 output columns, a run of `rows`
+// output rows.  Only the 2r+4 image rows around the window are
 // staged, in a ring, so the LDS a workgroup needs is its histogram plus a
 // few KB: several wavefronts fit on a CU and runs can be long.  Image rows
 // are fetched two rows ahead into registers.

@@ -78,7 +78,7 @@ int min_run_rows(const Job& j) {
 // min_run_rows and at most the band or 1024 rows.  A job whose layout does
 // not fit the new rows keeps its own.
 constexpr int kTilesPerSlot = 32;
-constexpr int kSlotsPerCu = 8;  // typical resident one-wavefront workgroups
+constexpr int kSlotsPerCu = 8;  // typical resident workgroups (one-wavefront classes)
 
 void shape_rows(std::vector<Job>& jobs, int device) {
     const DeviceInfo d = device_info(device);
