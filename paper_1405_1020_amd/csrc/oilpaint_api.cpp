@@ -48,7 +48,13 @@ size_t lds_bytes(const Job& j) {
     const size_t nb = (size_t)j.bins;
     const size_t lanes = (size_t)j.lanes;
     if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
-    if (is_stream(j.hist)) return nb * 64 * 8 + stream_ring_bytes(j) + 192 + (is_split(j) ? kSplitPartBytes : 0);
+    if (is_stream(j.hist)) {
+        // radius 1 with one wavefront and more than 8 scanned levels keeps its
+        // window in registers (no histogram: tile_direct1)
+        if (j.hist == OILPAINT_HIST_STREAM && j.waves == 1 && j.radius == 1 && j.scan > 8)
+            return stream_ring_bytes(j) + 192;
+        return nb * 64 * 8 + stream_ring_bytes(j) + 192 + (is_split(j) ? kSplitPartBytes : 0);
+    }
     if (j.hist == OILPAINT_HIST_COLUMN) {
         const size_t tw = 64 + 2 * (size_t)j.radius;
         return ((nb * tw * 8 + 15) & ~(size_t)15) + (tw + 1) * 16 + 192;

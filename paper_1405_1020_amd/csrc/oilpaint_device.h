@@ -714,9 +714,113 @@ __device__ __forceinline__ void stage_ring(const Job& j, int x0, int y0, int nro
     }
 }
 
+// Radius 1 in the streamed layout (one wavefront, more than eight scanned
+// levels): a 3 x 3 window holds at most nine levels, so the mode is found in
+// registers -- a window pixel's
+// count is the number of window pixels on its level, the largest count wins
+// and the lowest level among equal counts -- and no histogram is kept.  The
+// workgroup's LDS is the ring and the output row buffer only.  The window's
+// staged words slide down in registers; each output row reads one ring row,
+// issued before the row's mode is computed.  Levels at or above L (the
+// paper form's white level, pixels outside the image) are never chosen.
+__device__ __forceinline__ uint32_t direct9_pixel(const uint32_t (&v)[9], uint32_t levels, uint32_t& n) {
+    uint32_t lev[9], cnt[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        lev[i] = v[i] >> 24;
+        cnt[i] = 1;
+    }
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+            const uint32_t eq = lev[i] == lev[k] ? 1u : 0u;
+            cnt[i] += eq;
+            cnt[k] += eq;
+        }
+    uint32_t best = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) best = max(best, lev[i] < levels ? (cnt[i] << 8) | (255u - lev[i]) : 0u);
+    n = best >> 8;
+    const uint32_t kb = 255u - (best & 255u);
+    uint32_t s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (n > 0 && lev[i] == kb) {
+            s0 += v[i] & 0xFFu;
+            s1 += (v[i] >> 8) & 0xFFu;
+            s2 += (v[i] >> 16) & 0xFFu;
+        }
+    const uint32_t nn = n ? n : 1u;
+    const float rn = rcp_approx(nn);
+    return div_exact(s0, nn, rn) | (div_exact(s1, nn, rn) << 8) | (div_exact(s2, nn, rn) << 16);
+}
+
+__device__ __forceinline__ void tile_direct1(const Job& j, int unit, uint8_t* lds) {
+    constexpr int R = 1;
+    constexpr int TW = 64 + 2 * R;
+    constexpr int RB = kStreamRingExtra + 2 * R;  // ring rows
+    const int lane = threadIdx.x & 63;
+    const int tx = unit % j.tiles_x;
+    const int ty = unit / j.tiles_x;
+    const int x0 = tx * 64;
+    const int ya = j.row_begin + ty * j.rows;
+    const int yb = min(ya + j.rows, j.row_end);
+    uint32_t* ring = reinterpret_cast<uint32_t*>(lds);
+    uint8_t* obuf = lds + stream_ring_bytes(j);
+    auto slot = [&](int g) { return ring + ((g - (ya - R)) % RB) * TW; };
+    stage_ring<R, false>(j, x0, ya, 2 * R + 2, ring);
+    lds_order();
+    RowBytes q0, q1;
+    stream_load_row<R>(j, x0, ya + 2 + R, q0);
+    stream_load_row<R>(j, x0, ya + 3 + R, q1);
+    // window rows ya-1, ya, ya+1 (slots 0 .. 2), words of columns lane .. lane+2
+    uint32_t w[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[3 * r + c] = ring[r * TW + lane + c];
+    auto row = [&](int y) {
+        uint32_t nw[3] = {0u, 0u, 0u};
+        if (y + 1 < yb) {
+            const uint32_t* s = slot(y + 2) + lane;  // the row entering the next window
+#pragma unroll
+            for (int c = 0; c < 3; ++c) nw[c] = s[c];
+        }
+        uint32_t n;
+        const uint32_t px = direct9_pixel(w, (uint32_t)j.levels, n);
+        store_row(j, x0, y, n, px, obuf);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            w[c] = w[3 + c];
+            w[3 + c] = w[6 + c];
+            w[6 + c] = nw[c];
+        }
+    };
+    // Two output rows per iteration; at the top rows y+3 and y+4 (fetched an
+    // iteration earlier) enter the ring, into the slots of rows y-3 and y-2.
+    int y = ya;
+#pragma unroll 1
+    for (; y < yb; y += 2) {
+        if (y + 2 < yb) stream_write_row<R, false>(j, slot(y + 2 + R), q0);
+        if (y + 3 < yb) stream_write_row<R, false>(j, slot(y + 3 + R), q1);
+        lds_order();
+        if (y + 4 < yb) stream_load_row<R>(j, x0, y + 4 + R, q0);
+        if (y + 5 < yb) stream_load_row<R>(j, x0, y + 5 + R, q1);
+        row(y);
+        if (y + 1 < yb) row(y + 1);
+    }
+}
+
 // W8: 8-byte ring entries (OILPAINT_HIST_STREAM8: radius >= 8, SB = 32).
 template <int R, int SB, bool W8>
 __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds) {
+    if constexpr (R == 1 && !W8) {
+        if (j.scan > 8) {  // eight bins scan faster than nine-way compares
+            tile_direct1(j, unit, lds);
+            return;
+        }
+    }
     static_assert(!W8 || (R >= 8 && SB == 32), "8-byte entries: F18 bins, at most 32 scanned levels");
     constexpr int SPAN = 2 * R + 1;
     constexpr int TW = 64 + 2 * R;

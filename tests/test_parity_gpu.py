@@ -201,7 +201,7 @@ def test_sampled_pixels_full_size_camera():
         assert tuple(got[y, x]) == tuple(ref_pixel(img, x, y, r, L)), (x, y)
 
 
-@pytest.mark.parametrize("r", [3, 7, 10, 15])
+@pytest.mark.parametrize("r", [1, 3, 7, 10, 15])
 def test_paper_form_every_default_layout(r):
     # the listing's literal form (interior pixels only, the pure-white level
     # never chosen, nothing written where the winning count is 0) through the
