@@ -812,6 +812,18 @@ __device__ __forceinline__ void tile_direct1(const Job& j, int unit, uint8_t* ld
     }
 }
 
+// Sum of the 2R+1 column entries col[0 .. 2R] (packed bin words; each field's
+// total stays in range), as four independent chains: the additions of one
+// chain wait on each other, so a single chain of 2R+1 would be latency-bound.
+template <int R>
+__device__ __forceinline__ uint64_t window_column_sum(const uint64_t* col) {
+    constexpr int SPAN = 2 * R + 1;
+    uint64_t a[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < SPAN; ++i) a[i & 3] += col[i];
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
 // W8: 8-byte ring entries (OILPAINT_HIST_STREAM8: radius >= 8, SB = 32).
 template <int R, int SB, bool W8>
 __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds) {
@@ -876,10 +888,7 @@ __device__ __forceinline__ void tile_stream(const Job& j, int unit, uint8_t* lds
 #pragma unroll 1
         for (int k = 0; k < scan; ++k) {
             const uint64_t* col = reinterpret_cast<const uint64_t*>(colh + k * CW) + lane;
-            uint64_t acc = 0;
-#pragma unroll
-            for (int i = 0; i < SPAN; ++i) acc += col[i];
-            *reinterpret_cast<uint64_t*>(hl + k * BS) = acc;
+            *reinterpret_cast<uint64_t*>(hl + k * BS) = window_column_sum<R>(col);
         }
     } else {
         for (int k = 0; k < j.bins; ++k) *reinterpret_cast<uint64_t*>(hl + k * BS) = 0;
@@ -1041,6 +1050,12 @@ __device__ __forceinline__ void batch_stream(const BatchArgs& a, uint8_t* lds) {
 //   LDS: [histogram: bins x 64 lanes x 8 B][ring region][output row: 192 B]
 //        [keys: 64 lanes x 4 x 4 B][bin words: 4 x 64 lanes x 8 B]
 
+// Wavefronts per SIMD the plain four-wavefront kernels are compiled for (the
+// second launch bound): five workgroups of four per CU, which the LDS of a
+// 4-byte ring at r = 15 and 20 levels allows, need at most 96 registers per
+// lane; one register more would leave four resident.
+constexpr int kSplitMinWaves = 5;
+
 // Workgroup barrier for LDS traffic: waits for this wavefront's LDS
 // operations only (global loads fetched ahead stay in flight), then meets
 // the other wavefronts.  Every wavefront of the workgroup reaches every one.
@@ -1145,10 +1160,7 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
 #pragma unroll 1
             for (int k = w; k < scan; k += NW) {
                 const uint64_t* col = reinterpret_cast<const uint64_t*>(colh + k * CW) + lane;
-                uint64_t acc = 0;
-#pragma unroll
-                for (int i = 0; i < SPAN; ++i) acc += col[i];
-                *reinterpret_cast<uint64_t*>(hl + k * BS) = acc;
+                *reinterpret_cast<uint64_t*>(hl + k * BS) = window_column_sum<R>(col);
             }
             // the ring replaces the column histograms
             lds_barrier();

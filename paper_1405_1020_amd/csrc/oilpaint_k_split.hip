@@ -9,7 +9,7 @@ using namespace dev;
 namespace {
 
 template <int R, int MB>
-__global__ __launch_bounds__(64 * kSplitWaves) void k_plain_split8(Job j) {
+__global__ __launch_bounds__(64 * kSplitWaves, kSplitMinWaves) void k_plain_split8(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
     tile_stream_split<R, MB, true>(j, blockIdx.x, lds);
 }
