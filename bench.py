@@ -33,21 +33,21 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "megapixels/sec at (r, L), batched/served vs plain kernel; p50/p99 request latency"
-# How the HBM counter summary is made, from the repository root on the GPU
-# host (the first line fills the tuning cache so that the profiled runs
-# launch only the timed shapes).
+# How the HBM counter summary is made, from the repository root ($REPO) on the
+# GPU host, with $OUT an output directory (the first line fills the tuning
+# cache so that the profiled runs launch only the timed shapes).
 HBM_COMMANDS = [
     "python3 bench.py --quick --steps 5 --warmup 2",
     "cd /tmp && export TMPDIR=/tmp",
-    "timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/hbm/sweep_fetch --output-format csv -- "
+    "timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d $OUT/sweep_fetch --output-format csv -- "
     "python3 $REPO/bench.py --quick --steps 5 --warmup 2",
-    "timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/hbm/sweep_write --output-format csv -- "
+    "timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d $OUT/sweep_write --output-format csv -- "
     "python3 $REPO/bench.py --quick --steps 5 --warmup 2",
-    "timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/hbm/copy_fetch --output-format csv -- "
+    "timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d $OUT/copy_fetch --output-format csv -- "
     "python3 $REPO/bench.py --copy-ref",
-    "timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/hbm/copy_write --output-format csv -- "
+    "timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d $OUT/copy_write --output-format csv -- "
     "python3 $REPO/bench.py --copy-ref",
-    "cd $REPO && python3 bench.py --hbm-summary gpurun_out/hbm",
+    "cd $REPO && python3 bench.py --hbm-summary $OUT",
 ]
 LDS_PEAK_GBS = 256 * 2.4e9 * 256 / 1e9  # 256 CUs x 2.4 GHz x 256 B/clk LDS read path
 
@@ -521,7 +521,7 @@ def main():
                     help="write the HBM counter summary under profiles/ from rocprofv3 --pmc outputs in DIR")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -69,7 +69,7 @@ extern "C" {
 #define OILPAINT_ERR_HIP        -5  /* a HIP runtime call failed */
 #define OILPAINT_ERR_NOMEM      -6  /* the library could not allocate its own scratch */
 #define OILPAINT_ERR_FULL       -7  /* an oilpaint_queue has no free slot */
-#define OILPAINT_ERR_UNSUPPORTED -8 /* a combination this build does not handle (see each call) */
+#define OILPAINT_ERR_UNSUPPORTED -8 /* a combination the library does not handle (see each call) */
 
 /* Flags (oilpaint_desc.flags). */
 #define OILPAINT_FLAG_PAPER 1u  /* the paper's listing taken literally: level

@@ -1,7 +1,7 @@
 """Serving loop: filter requests admitted by a device-memory budget and run
 with continuous batching.
 
-The paper filters one image per call (Section 4, the driver around
+The paper filters one image per call (Section 4, the program around
 ApplyOilPaintOnBuffer); serving many requests is this project's addition.
 
 A `Server` holds:
