@@ -1214,15 +1214,25 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
             if (!RT || i < mb) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
         uint32_t best = 0;
         uint64_t bw = 0;
+        if constexpr (MB >= 8) {
+            // many bins: keep only the key while scanning, then read the
+            // winning bin's word back (the window does not change before the
+            // second barrier)
 #pragma unroll
-        for (int i = 0; i < MB; ++i)
-            if (!RT || i < mb) {
-                const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i);
-                if (key > best) {
-                    best = key;
-                    bw = v[i];
+            for (int i = 0; i < MB; ++i)
+                if (!RT || i < mb) best = max(best, ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i));
+            bw = *reinterpret_cast<const uint64_t*>(hl + (63u - (best & 63u)) * BS);
+        } else {
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (!RT || i < mb) {
+                    const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i);
+                    if (key > best) {
+                        best = key;
+                        bw = v[i];
+                    }
                 }
-            }
+        }
         keys[lane * NW + w] = best;
         words[w * 64 + lane] = bw;
         lds_barrier();  // every wavefront's best is in LDS; the window may change
