@@ -1214,8 +1214,8 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
             if (!RT || i < mb) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
         uint32_t best = 0;
         uint64_t bw = 0;
-        if constexpr (MB >= 8) {
-            // many bins: keep only the key while scanning, then read the
+        if constexpr (MB >= 4) {
+            // four bins or more: keep only the key while scanning, then read the
             // winning bin's word back (the window does not change before the
             // second barrier)
 #pragma unroll
