@@ -151,9 +151,11 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
     const size_t limit = d.ok ? d.lds_per_block : 65536;
     // the column-histogram first window is an optimisation: dropped first
     // when the footprint does not fit
-    if (j.colfirst && lds_bytes(j) + kStaticLds > limit) j.colfirst = 0;
+    if (j.colfirst && !(is_split(j) && j.hist == OILPAINT_HIST_STREAM8) && lds_bytes(j) + kStaticLds > limit)
+        j.colfirst = 0;
     while (lds_bytes(j) + kStaticLds > limit) {
-        if (v.rows != 0 || j.rows == 1) return OILPAINT_ERR_UNSUPPORTED;
+        if (v.rows != 0 || j.rows == 1 || (is_split(j) && j.hist == OILPAINT_HIST_STREAM8))
+            return OILPAINT_ERR_UNSUPPORTED;
         j.rows = std::max(1, j.rows / 2);
         set_layout(j);
         j.colfirst = 0;

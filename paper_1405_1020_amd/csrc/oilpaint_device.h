@@ -1297,6 +1297,195 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
     }
 }
 
+// The four-wavefront form with 8-byte entries (ready bin increments: an
+// update is 3 instructions instead of the 4-byte word's 7) keeps no ring of
+// window rows, which at 8 bytes would not leave five workgroups per CU.  The
+// first window comes from column histograms of the run's first 2r+2 rows,
+// built from registers; afterwards each row step needs only its leaving and
+// its entering row.  They sit in kSplitRows8 row slots: per pair of output
+// rows the two entering rows (slots 2p, 2p+1) and the two leaving rows (slots
+// 4+2p, 5+2p), p the pair's parity, one row per wavefront, fetched from the
+// image one pair ahead (a leaving row comes from the image again: it was
+// read 2r+1 rows earlier and sits in L2).
+//   LDS: [histogram: bins x 64 lanes x 8 B]
+//        [column histograms, then the row slots: kSplitRows8 x (64+2r) x 8 B]
+//        [output row: 192 B][keys: 64 lanes x 4 x 4 B][bin words: 4 x 64 x 8 B]
+template <int R, int MB, bool RT = false>
+__device__ __forceinline__ void tile_stream_split8(const Job& j, int unit, uint8_t* lds) {
+    static_assert(R >= 8 && R <= 15 && MB >= 1 && kSplitWaves * MB <= 32, "F18 bins, at most 32 scanned levels");
+    constexpr int NW = kSplitWaves;
+    constexpr int NT = 64 * NW;
+    constexpr int SPAN = 2 * R + 1;
+    constexpr int TW = 64 + 2 * R;
+    constexpr int C = (SPAN + NW - 1) / NW;
+    constexpr int CMIN = SPAN - (NW - 1) * C;
+    constexpr uint32_t BS = 64u * 8u;
+    using Fmt = BinFmt<false>;
+    constexpr uint32_t M = Fmt::kCountMask;
+    using RF = RingFmt<true>;
+    using T = uint64_t;
+    const int lane = threadIdx.x & 63;
+    const int t = (int)threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int c0 = w * C;
+    const int scan = j.scan;
+    const int mb = RT ? scan / NW : MB;
+    const int tx = unit % j.tiles_x;
+    const int ty = unit / j.tiles_x;
+    const int x0 = tx * 64;
+    const int ya = j.row_begin + ty * j.rows;
+    const int yb = min(ya + j.rows, j.row_end);
+    uint8_t* hl = lds + lane * 8;
+    const uint32_t lane_off = lds_offset(hl);
+    auto bin_ptr = [&](T e) { return lds_word(shl9_add(RF::bin_field(e), lane_off)); };
+    uint8_t* region = lds + (size_t)j.bins * BS;
+    T* rows8 = reinterpret_cast<T*>(region);
+    uint8_t* obuf = region + stream_ring_bytes(j);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(obuf + 192);
+    uint64_t* words = reinterpret_cast<uint64_t*>(obuf + 192 + 64 * NW * 4);
+    auto mine = [&](int c) { return c < CMIN || c0 + c < SPAN; };
+    // the image row each wavefront stages for the pair of output rows y, y+1:
+    // entering y+2+R, y+3+R (wavefronts 0, 1), leaving y+1-R, y+2-R (2, 3)
+    auto staged_row = [&](int y) { return w < 2 ? y + 2 + R + w : y + 1 - R + (w - 2); };
+    auto slot_of = [&](int p) { return rows8 + (size_t)((w < 2 ? 0 : 4) + 2 * p + (w & 1)) * TW; };
+
+    {
+        // first window from column histograms of rows ya-R .. ya+R (one load
+        // round for rows ya-R .. ya+R+1 over all threads, as in
+        // tile_stream_split); rows ya-R and ya+1+R, the leaving and entering
+        // rows of the first step, then go to slots 6 and 2 (parity 1, first
+        // rewritten by the second pair)
+        constexpr int NS = (2 * R + 2) * TW;
+        constexpr int CH = (NS + NT - 1) / NT;
+        constexpr int CW = TW * 8;
+        constexpr int NP = SPAN * TW;
+        T ent[CH];
+        {
+            PixelAt<R, true> px[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) px[i].load(j, x0, ya, min(t + i * NT, NS - 1));
+            const int n16 = (scan + 1) * CW / 16;
+            for (int e = t; e < n16; e += NT) *reinterpret_cast<uint4*>(region + e * 16) = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int i = 0; i < CH; ++i) ent[i] = px[i].entry(j);
+        }
+        lds_barrier();
+        uint8_t* colh = region;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int p = t + i * NT;
+            const uint32_t k = min(RF::bin(ent[i]), (uint32_t)scan);
+            if (p < NP) lds_add(reinterpret_cast<uint64_t*>(colh + k * CW + (p % TW) * 8), RF::template inc<false>(ent[i]));
+        }
+        lds_barrier();
+#pragma unroll 1
+        for (int k = w; k < scan; k += NW) {
+            const uint64_t* col = reinterpret_cast<const uint64_t*>(colh + k * CW) + lane;
+            *reinterpret_cast<uint64_t*>(hl + k * BS) = window_column_sum<R>(col);
+        }
+        lds_barrier();  // the row slots replace the column histograms
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int p = t + i * NT;
+            if (p < NS) {
+                const int row = p / TW, col = p - row * TW;
+                if (row == 0) rows8[6 * TW + col] = ent[i];
+                if (row == 2 * R + 1) rows8[2 * TW + col] = ent[i];
+            }
+        }
+    }
+    RowBytes q;
+    stream_load_row<R>(j, x0, staged_row(ya), q);
+    lds_barrier();
+    T wo[C], wn[C];
+    {
+        const T* so = rows8 + 6 * TW + lane + c0;
+        const T* sn = rows8 + 2 * TW + lane + c0;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (mine(c)) {
+                wo[c] = so[c];
+                wn[c] = sn[c];
+            }
+    }
+
+    // Output row y (k = 0 or 1 within its pair, p the pair's parity), then the
+    // step y -> y+1 and the entries of the next step.
+    auto row_step = [&](int y, int p, int k) {
+        lds_barrier();  // window(y) complete, this pair's rows staged
+        uint64_t v[MB];
+        const uint8_t* hb = hl + (size_t)(w * mb) * BS;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (!RT || i < mb) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
+        uint32_t best = 0;
+        uint64_t bw = 0;
+        if constexpr (MB >= 4) {
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (!RT || i < mb) best = max(best, ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i));
+            bw = *reinterpret_cast<const uint64_t*>(hl + (63u - (best & 63u)) * BS);
+        } else {
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (!RT || i < mb) {
+                    const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i);
+                    if (key > best) {
+                        best = key;
+                        bw = v[i];
+                    }
+                }
+        }
+        keys[lane * NW + w] = best;
+        words[w * 64 + lane] = bw;
+        lds_barrier();  // every wavefront's best is in LDS; the window may change
+        if (w == ((y - ya) & (NW - 1))) {
+            const uint4 kk = *reinterpret_cast<const uint4*>(keys + lane * NW);
+            uint32_t top = kk.x, ww = 0;
+            if (kk.y > top) top = kk.y, ww = 1;
+            if (kk.z > top) top = kk.z, ww = 2;
+            if (kk.w > top) top = kk.w, ww = 3;
+            const uint64_t win = words[ww * 64 + lane];
+            const uint32_t n = top >> Fmt::kCountShift;
+            store_row(j, x0, y, n, finalize_packed<false>(n, win), obuf);
+        }
+        if (y + 1 < yb) {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (mine(c)) {
+                    lds_sub(bin_ptr(wo[c]), RF::template inc<false>(wo[c]));
+                    lds_add(bin_ptr(wn[c]), RF::template inc<false>(wn[c]));
+                }
+            if (y + 2 < yb) {
+                // step y+1 -> y+2: leaving row y+1-R (slot 4+2p+k), entering
+                // row y+2+R (slot 2p+k)
+                const T* so = rows8 + (size_t)(4 + 2 * p + k) * TW + lane + c0;
+                const T* sn = rows8 + (size_t)(2 * p + k) * TW + lane + c0;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (mine(c)) {
+                        wo[c] = so[c];
+                        wn[c] = sn[c];
+                    }
+            }
+        }
+    };
+    const int q1 = ya + (yb - ya) / 4, q2 = ya + (yb - ya) / 2, q3 = ya + 3 * (yb - ya) / 4;
+    int y = ya;
+#pragma unroll 1
+    for (int it = 0; y < yb; y += 2, ++it) {
+        const int p = it & 1;
+        progress_priority(y, q1, q2, q3);
+        // this pair's rows enter their slots (the same parity's slots were last
+        // read two pairs ago, before the barriers since); the next pair's are
+        // fetched
+        if (y + 2 + (w & 1) < yb) stream_write_row<R, true>(j, slot_of(p), q);
+        if (y + 4 + (w & 1) < yb) stream_load_row<R>(j, x0, staged_row(y + 2), q);
+        row_step(y, p, 0);
+        if (y + 1 < yb) row_step(y + 1, p, 1);
+    }
+}
+
 // Persistent batch form: the next tile of the class's queue, taken by the
 // workgroup's first thread and handed to all four wavefronts through LDS.
 // The barrier after the hand-over also orders the previous tile's last LDS
@@ -1313,7 +1502,10 @@ __device__ __forceinline__ void batch_stream_split(const BatchArgs& a, uint8_t* 
         if (t >= a.ntiles) break;
         const int i = job_of(a, t);
         const Job jb = a.jobs[i];
-        tile_stream_split<R, MB, W8, true>(jb, t - a.first_tile[i], lds);
+        if constexpr (W8)
+            tile_stream_split8<R, MB, true>(jb, t - a.first_tile[i], lds);
+        else
+            tile_stream_split<R, MB, false, true>(jb, t - a.first_tile[i], lds);
     }
 }
 

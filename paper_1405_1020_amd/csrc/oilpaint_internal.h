@@ -70,7 +70,7 @@ size_t lds_bytes(const Job& j);
 // radius, levels, paper): the levels 0..L-1 first -- rounded up to a multiple
 // of 8 empty bins on the fast path -- then the paper form's white level,
 // then the bin for pixels outside the image.
-inline bool is_stream(int hist) { return hist == OILPAINT_HIST_STREAM || hist == OILPAINT_HIST_STREAM8; }
+__host__ __device__ inline bool is_stream(int hist) { return hist == OILPAINT_HIST_STREAM || hist == OILPAINT_HIST_STREAM8; }
 
 // Streamed layout worked by several wavefronts per strip (OILPAINT_HIST_STREAM
 // or OILPAINT_HIST_STREAM8 with waves == kSplitWaves): the wavefronts share
@@ -79,7 +79,7 @@ inline bool is_stream(int hist) { return hist == OILPAINT_HIST_STREAM || hist ==
 // padded to kSplitWaves blocks with bins no pixel reaches.  Rows per tile are
 // the run of every wavefront (not multiplied by the wavefront count).
 constexpr int kSplitWaves = 4;
-inline bool is_split(const Job& j) { return is_stream(j.hist) && j.waves == kSplitWaves; }
+__host__ __device__ inline bool is_split(const Job& j) { return is_stream(j.hist) && j.waves == kSplitWaves; }
 inline int split_bins(int levels) {
     return levels <= 8 ? 2 : levels <= 16 ? 4 : levels <= 20 ? 5 : levels <= 32 ? 8 : 16;
 }
@@ -89,12 +89,18 @@ inline int split_bucket(int bins) {
 // LDS of the per-wavefront mode-search results: a 4-byte key per lane and
 // wavefront, and the winning 8-byte bin word per lane and wavefront.
 constexpr size_t kSplitPartBytes = (size_t)kSplitWaves * 64 * 12;
+// With 8-byte entries the four-wavefront form keeps no ring of window rows:
+// row slots for two row steps' entering and leaving rows, double-buffered
+// (the first window always comes from column histograms).
+constexpr int kSplitRows8 = 8;
 
 // Streamed layout: bytes of the ring of (2r+4) rows of 64+2r entries (8 bytes
 // each for OILPAINT_HIST_STREAM8, else 4), and of the column histograms a
 // run's first window may be built from (scan + 1 rows of 64+2r 8-byte
 // entries), which take the ring's place while they live.
 __host__ __device__ inline size_t stream_ring_only_bytes(const Job& j) {
+    if (is_split(j) && j.hist == OILPAINT_HIST_STREAM8)  // kSplitRows8 rows, 8-byte entries
+        return (size_t)kSplitRows8 * (64 + 2 * (size_t)j.radius) * 8;
     return (2 * (size_t)j.radius + 4) * (64 + 2 * (size_t)j.radius) * (j.hist == OILPAINT_HIST_STREAM8 ? 8 : 4);
 }
 __host__ __device__ inline size_t stream_colh_bytes(const Job& j) {
@@ -132,6 +138,7 @@ inline void set_layout(Job& j) {
     j.colfirst = 0;
     if (is_stream(j.hist) && (2 * j.radius + 1) * 10 >= 4 * j.scan + 20)
         j.colfirst = (stream_colh_bytes(j) <= stream_ring_only_bytes(j) || j.rows <= 4 * (2 * j.radius + 1)) ? 1 : 0;
+    if (is_split(j) && j.hist == OILPAINT_HIST_STREAM8) j.colfirst = 1;  // no ring of window rows
 }
 
 // Streamed layout: bytes of the ring region (the ring, or while they live
