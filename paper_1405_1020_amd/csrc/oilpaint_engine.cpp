@@ -23,10 +23,12 @@ oilpaint_variant choose_variant(int width, int height, int reff, int levels, boo
 
 namespace {
 
-// Smallest radius whose batch tiles use four wavefronts per strip: below it
-// a persistent class's long runs leave one wavefront per strip ahead (the
-// two barriers per row cost more than the little work between them).
-constexpr int kBatchSplitMinRadius = 8;
+// Smallest radius whose batch tiles use four wavefronts per strip.  A batch
+// runs several classes at once, which already gives the GPU many wavefronts,
+// so below this the split's barriers and tile hand-off cost more than its
+// latency hiding gains (64-image batch of radii 2-8: 74.5 GP/s with one
+// wavefront per strip from radius 8 on, 67.5 with four).
+constexpr int kBatchSplitMinRadius = 10;
 
 // Layout of a job inside a persistent launch: the streamed layouts as the
 // job's own choice (four wavefronts sharing a strip where that is its plain
