@@ -1077,6 +1077,61 @@ __device__ __forceinline__ void progress_priority(int done, int q1, int q2, int 
         __builtin_amdgcn_s_setprio(0);
 }
 
+// One output row y of the four-wavefront forms: wait for the window (first
+// barrier), scan this wavefront's block of mb bins (MB, or at most MB with
+// RT) for its best key, publish the key and the winning bin word, wait for
+// the other wavefronts (second barrier), and let one wavefront, rotating by
+// row, combine the four and store the row.  With four bins or more the scan
+// keeps only the key and reads the winning word back: the window does not
+// change before the second barrier.
+template <int MB, bool RT, bool F16>
+__device__ __forceinline__ void split_mode_row(const Job& j, int x0, int y, int ya, int w, int mb, uint8_t* hl,
+                                               uint32_t* keys, uint64_t* words, uint8_t* obuf) {
+    constexpr int NW = kSplitWaves;
+    constexpr uint32_t BS = 64u * 8u;
+    using Fmt = BinFmt<F16>;
+    constexpr uint32_t M = Fmt::kCountMask;
+    const int lane = threadIdx.x & 63;
+    lds_barrier();  // window(y) complete
+    uint64_t v[MB];
+    const uint8_t* hb = hl + (size_t)(w * mb) * BS;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+        if (!RT || i < mb) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
+    uint32_t best = 0;
+    uint64_t bw = 0;
+    if constexpr (MB >= 4) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (!RT || i < mb) best = max(best, ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i));
+        bw = *reinterpret_cast<const uint64_t*>(hl + (63u - (best & 63u)) * BS);
+    } else {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (!RT || i < mb) {
+                const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i);
+                if (key > best) {
+                    best = key;
+                    bw = v[i];
+                }
+            }
+    }
+    keys[lane * NW + w] = best;
+    words[w * 64 + lane] = bw;
+    lds_barrier();  // every wavefront's best is in LDS; the window may change
+    if (w == ((y - ya) & (NW - 1))) {
+        const uint4 kk = *reinterpret_cast<const uint4*>(keys + lane * NW);
+        // the largest key (keys of different wavefronts differ in level)
+        uint32_t top = kk.x, ww = 0;
+        if (kk.y > top) top = kk.y, ww = 1;
+        if (kk.z > top) top = kk.z, ww = 2;
+        if (kk.w > top) top = kk.w, ww = 3;
+        const uint64_t win = words[ww * 64 + lane];
+        const uint32_t n = top >> Fmt::kCountShift;
+        store_row(j, x0, y, n, finalize_packed<F16>(n, win), obuf);
+    }
+}
+
 // MB: bins per wavefront, or with RT their maximum, the count being
 // j.scan / kSplitWaves (the persistent batch kernels, one per radius and
 // level bucket).
@@ -1093,8 +1148,6 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
     constexpr int CMIN = SPAN - (NW - 1) * C;    // those of the last wavefront
     constexpr uint32_t BS = 64u * 8u;
     constexpr bool F16 = R <= 7;
-    using Fmt = BinFmt<F16>;
-    constexpr uint32_t M = Fmt::kCountMask;
     using RF = RingFmt<W8>;
     using T = typename RF::T;
     const int lane = threadIdx.x & 63;
@@ -1206,47 +1259,7 @@ __device__ __forceinline__ void tile_stream_split(const Job& j, int unit, uint8_
     // Output row y, then the step y -> y+1 and the entries of the next step.
     auto row_step = [&](int y, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        lds_barrier();  // window(y) complete
-        uint64_t v[MB];
-        const uint8_t* hb = hl + (size_t)(w * mb) * BS;
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-            if (!RT || i < mb) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
-        uint32_t best = 0;
-        uint64_t bw = 0;
-        if constexpr (MB >= 4) {
-            // four bins or more: keep only the key while scanning, then read the
-            // winning bin's word back (the window does not change before the
-            // second barrier)
-#pragma unroll
-            for (int i = 0; i < MB; ++i)
-                if (!RT || i < mb) best = max(best, ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i));
-            bw = *reinterpret_cast<const uint64_t*>(hl + (63u - (best & 63u)) * BS);
-        } else {
-#pragma unroll
-            for (int i = 0; i < MB; ++i)
-                if (!RT || i < mb) {
-                    const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i);
-                    if (key > best) {
-                        best = key;
-                        bw = v[i];
-                    }
-                }
-        }
-        keys[lane * NW + w] = best;
-        words[w * 64 + lane] = bw;
-        lds_barrier();  // every wavefront's best is in LDS; the window may change
-        if (w == ((y - ya) & (NW - 1))) {
-            const uint4 kk = *reinterpret_cast<const uint4*>(keys + lane * NW);
-            // the largest key (keys of different wavefronts differ in level)
-            uint32_t top = kk.x, ww = 0;
-            if (kk.y > top) top = kk.y, ww = 1;
-            if (kk.z > top) top = kk.z, ww = 2;
-            if (kk.w > top) top = kk.w, ww = 3;
-            const uint64_t win = words[ww * 64 + lane];
-            const uint32_t n = top >> Fmt::kCountShift;
-            store_row(j, x0, y, n, finalize_packed<F16>(n, win), obuf);
-        }
+        split_mode_row<MB, RT, F16>(j, x0, y, ya, w, mb, hl, keys, words, obuf);
         if (FULL || y + 1 < yb) {
 #pragma unroll
             for (int c = 0; c < C; ++c)
@@ -1320,8 +1333,6 @@ __device__ __forceinline__ void tile_stream_split8(const Job& j, int unit, uint8
     constexpr int C = (SPAN + NW - 1) / NW;
     constexpr int CMIN = SPAN - (NW - 1) * C;
     constexpr uint32_t BS = 64u * 8u;
-    using Fmt = BinFmt<false>;
-    constexpr uint32_t M = Fmt::kCountMask;
     using RF = RingFmt<true>;
     using T = uint64_t;
     const int lane = threadIdx.x & 63;
@@ -1412,43 +1423,7 @@ __device__ __forceinline__ void tile_stream_split8(const Job& j, int unit, uint8
     // Output row y (k = 0 or 1 within its pair, p the pair's parity), then the
     // step y -> y+1 and the entries of the next step.
     auto row_step = [&](int y, int p, int k) {
-        lds_barrier();  // window(y) complete, this pair's rows staged
-        uint64_t v[MB];
-        const uint8_t* hb = hl + (size_t)(w * mb) * BS;
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-            if (!RT || i < mb) v[i] = *reinterpret_cast<const uint64_t*>(hb + i * BS);
-        uint32_t best = 0;
-        uint64_t bw = 0;
-        if constexpr (MB >= 4) {
-#pragma unroll
-            for (int i = 0; i < MB; ++i)
-                if (!RT || i < mb) best = max(best, ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i));
-            bw = *reinterpret_cast<const uint64_t*>(hl + (63u - (best & 63u)) * BS);
-        } else {
-#pragma unroll
-            for (int i = 0; i < MB; ++i)
-                if (!RT || i < mb) {
-                    const uint32_t key = ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i);
-                    if (key > best) {
-                        best = key;
-                        bw = v[i];
-                    }
-                }
-        }
-        keys[lane * NW + w] = best;
-        words[w * 64 + lane] = bw;
-        lds_barrier();  // every wavefront's best is in LDS; the window may change
-        if (w == ((y - ya) & (NW - 1))) {
-            const uint4 kk = *reinterpret_cast<const uint4*>(keys + lane * NW);
-            uint32_t top = kk.x, ww = 0;
-            if (kk.y > top) top = kk.y, ww = 1;
-            if (kk.z > top) top = kk.z, ww = 2;
-            if (kk.w > top) top = kk.w, ww = 3;
-            const uint64_t win = words[ww * 64 + lane];
-            const uint32_t n = top >> Fmt::kCountShift;
-            store_row(j, x0, y, n, finalize_packed<false>(n, win), obuf);
-        }
+        split_mode_row<MB, RT, false>(j, x0, y, ya, w, mb, hl, keys, words, obuf);
         if (y + 1 < yb) {
 #pragma unroll
             for (int c = 0; c < C; ++c)
