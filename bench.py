@@ -81,6 +81,9 @@ def kernel_name(r: int, L: int, v) -> str:
         return "k_plain_stream<%d, %d>" % (r, 32 if scan <= 32 else 64)
     if v.hist == 3:  # streamed rows, 8-byte entries
         return "k_plain_stream8<%d>" % r
+    if v.hist == 4 and r <= 15 and L <= 64:  # column histograms, radius <= 15 form
+        words = 3 if L <= 9 else 7 if L <= 21 else 11 if L <= 33 else 22
+        return "k_plain_column15<%d, %d>" % (words, v.waves)
     if v.hist == 4:  # column histograms
         return "k_plain_column<%d>" % ((64 + 2 * r + 63) // 64)
     if v.hist == 0 and v.lanes == 64 and r <= 15 and L <= 64:
@@ -93,7 +96,7 @@ def kernel_name(r: int, L: int, v) -> str:
 SWEEP_KERNEL_SOURCES = ("oilpaint_internal.h", "oilpaint_device.h", "oilpaint_k_stream_lo.hip",
                         "oilpaint_k_stream_hi.hip", "oilpaint_k_stream8.hip", "oilpaint_k_split.hip",
                         "oilpaint_k_split_lo.hip", "oilpaint_k_split_hi.hip", "oilpaint_k_fast_lo.hip",
-                        "oilpaint_k_fast_hi.hip")
+                        "oilpaint_k_fast_hi.hip", "oilpaint_column.h", "oilpaint_k_column.hip")
 
 
 def kernel_source_hash() -> str:
@@ -455,9 +458,10 @@ def launch_threads(w: int, h: int, variant) -> int:
     """Work-items of a plain launch of a w x h image with a resolved variant
     (rows, waves, hist, lanes, per_cu): one workgroup of 64 x waves per tile
     (the profiler's grid size); a tile spans waves x rows output rows, except
-    in the streamed layouts (hist 1 and 3), whose wavefronts share one run."""
+    in the streamed and column layouts (hist 1, 3 and 4), whose wavefronts
+    share one run."""
     rows, waves, hist, lanes = variant[0], variant[1], variant[2], variant[3]
-    runs = 1 if hist in (1, 3) else waves
+    runs = 1 if hist in (1, 3, 4) else waves
     tiles = -(-w // lanes) * -(-h // (runs * rows))
     return tiles * 64 * waves
 

@@ -272,6 +272,268 @@ __device__ __forceinline__ void tile_column(const Job& j, int unit, uint8_t* lds
     }
 }
 
+// ---------------------------------------------------------------------------
+// COLUMN layout for radius <= 15 (tile_column15): the same column histograms
+// and prefix sums, shaped for windows of at most 31 x 31.
+// ---------------------------------------------------------------------------
+// Column entries use the streamed layout's F18 bin word (count:10 @54 |
+// 3 x 18-bit sums), so the window word of a level is the plain 64-bit sum of
+// its 2r+1 column entries.  Beside them, each column keeps its counts three
+// levels to a 32-bit word, 10 bits each (word w: levels 3w .. 3w+2).  Pass 1
+// prefix-sums those words across the strip: the sums wrap, but a window
+// count is below 1024 and 32-bit addition is exact modulo 2^32, so the
+// difference of two prefix words holds the three window counts exactly.
+// Pass 2 sums the 2r+1 entries of each lane's winning level directly: a
+// fixed cost, however many distinct winners a row has.  Outside pixels and
+// the paper form's white level are counted nowhere.
+//   LDS: [column histograms: L level rows x 96 columns x 8 B]
+//        [count words: NW x 96 x 4 B][output row buffer: 192 B]
+
+// Prefix sum of the wavefront's column words at column lane + 2R (chunk 0
+// holds columns 0..63, chunk 1 columns 64..): a lane permute of either
+// chunk's inclusive scan.
+__device__ __forceinline__ uint32_t shifted_prefix(uint32_t s0, uint32_t s1, int lane, int r2) {
+    const int src = lane + r2;
+    const int a = (src & 63) << 2;
+    const uint32_t p0 = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)s0);
+    const uint32_t p1 = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)s1);
+    return src < 64 ? p0 : p1;
+}
+
+// NV wavefronts share a strip (1, 2 or 4).  Per output row: pass 1's
+// words are dealt round the wavefronts, each posting the best key of its
+// levels; a barrier; every wavefront takes the largest key, applies its
+// share of the step's count-word updates and sums its share of the 2r+1
+// winning entries; a barrier; one wavefront, rotating by row, adds the
+// partial words and stores the row while all make their share of the entry
+// updates.  The updates of the step y -> y+1 are the two pixels of each
+// column of the strip, leaving row y-R and entering row y+1+R, dealt as
+// (leave/enter, 64-column chunk) pairs.
+//   LDS, after the count words: [keys: NV x 64 x 4 B][partial words:
+//   NV x 64 x 8 B][output row buffer: 192 B]
+template <int NW, int NV>
+__device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* lds) {
+    static_assert(NV == 1 || NV == 2 || NV == 4, "one, two or four wavefronts per strip");
+    constexpr int CS = kColumn15Stride;
+    constexpr int RS = CS * 8;  // bytes per level row
+    constexpr int NT = 64 * NV;
+    constexpr int NPX = 4 / NV;  // step pixels per lane of each wavefront
+    const int R = j.radius;
+    const int TW = 64 + 2 * R;
+    const int L = j.levels;
+    const int lane = threadIdx.x & 63;
+    const int wv = NV == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int tx = unit % j.tiles_x;
+    const int ty = unit / j.tiles_x;
+    const int x0 = tx * 64;
+    const int ya = j.row_begin + ty * j.rows;
+    const int yb = min(ya + j.rows, j.row_end);
+    uint8_t* ch = lds;
+    uint32_t* cw = reinterpret_cast<uint32_t*>(lds + (size_t)L * RS);
+    uint32_t* keys = cw + NW * CS;
+    uint64_t* words = reinterpret_cast<uint64_t*>(keys + NV * 64);
+    uint8_t* obuf = reinterpret_cast<uint8_t*>(words + NV * 64);
+    const bool paper = j.paper != 0;
+    auto barrier = [] {
+        if constexpr (NV > 1)
+            lds_barrier();
+        else
+            lds_order();
+    };
+    // level of a pixel, or L for outside pixels and the paper form's white
+    auto level = [&](const PixelBytes& p) -> uint32_t {
+        const uint32_t lev = level_of(p.c0 + p.c1 + p.c2, (uint32_t)L, paper);
+        return (p.in && lev < (uint32_t)L) ? lev : (uint32_t)L;
+    };
+    auto inc = [](const PixelBytes& p) -> uint64_t {
+        return ((uint64_t)((p.c2 << 4) | (1u << 22)) << 32) | (p.c0 | (p.c1 << 18));
+    };
+    auto count_bit = [](uint32_t k) { return 1u << (10u * (k % 3u)); };
+
+    {
+        const int n16 = (int)(((size_t)L * RS + (size_t)NW * CS * 4) / 16);
+        for (int e = (int)threadIdx.x; e < n16; e += NT)
+            *reinterpret_cast<uint4*>(ch + (size_t)e * 16) = make_uint4(0u, 0u, 0u, 0u);
+    }
+    barrier();
+    {
+        // column histograms of rows ya-R .. ya+R; pixel p = t + NT i sits
+        // at (p / TW, p % TW), tracked in steps of NT
+        const int NP = (2 * R + 1) * TW;
+        constexpr int CH = 16 / NV;
+        const int dq = NT / TW, dr = NT % TW;
+        int row = (int)threadIdx.x / TW, col = (int)threadIdx.x % TW;
+        for (int base = (int)threadIdx.x; base < NP; base += CH * NT) {
+            PixelBytes px[CH];
+            int cl[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                cl[i] = col;
+                px[i].load(j, x0 - R + col, ya - R + row, base + i * NT < NP);
+                row += dq;
+                col += dr;
+                if (col >= TW) {
+                    col -= TW;
+                    ++row;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const uint32_t k = level(px[i]);
+                if (k < (uint32_t)L) {
+                    lds_add(reinterpret_cast<uint64_t*>(ch + k * RS + cl[i] * 8), inc(px[i]));
+                    lds_add(cw + (k / 3u) * CS + cl[i], count_bit(k));
+                }
+            }
+        }
+    }
+    barrier();
+    const int span = 2 * R + 1;
+    const int part = (span + NV - 1) / NV;
+    const int d0 = min(span, wv * part), d1 = min(span, d0 + part);
+    // this wavefront's pixels of each step: (leave/enter) << 1 | chunk
+    int pc[NPX];
+    bool enter[NPX];
+#pragma unroll
+    for (int q = 0; q < NPX; ++q) {
+        const int id = wv * NPX + q;
+        enter[q] = (id >> 1) != 0;
+        pc[q] = lane + 64 * (id & 1);
+    }
+    // the pixels of the step y -> y+1: leaving row y-R or entering row y+1+R
+    auto fetch = [&](int y, PixelBytes (&px)[NPX]) {
+        if (y + 1 < yb) {
+#pragma unroll
+            for (int q = 0; q < NPX; ++q) px[q].load(j, x0 - R + pc[q], enter[q] ? y + 1 + R : y - R, pc[q] < TW);
+        }
+    };
+    // Output row y, then the step y -> y+1 with the pixels px.
+    auto row = [&](int y, const PixelBytes (&px)[NPX]) {
+        const bool step = y + 1 < yb;
+        // pass 1: window counts, three levels per word; the most populated
+        // level, lowest among equals, is the largest key (count << 7) |
+        // (127 - level).  Chunk-1 columns past the strip read whatever
+        // follows in LDS: only scan entries at lanes they precede are used.
+        uint32_t key = 0;
+#pragma unroll
+        for (int i = 0; i < (NW + NV - 1) / NV; ++i) {
+            const int w = i * NV + wv;
+            if (NV == 1 || w < NW) {
+                const uint32_t v0 = cw[w * CS + lane];
+                const uint32_t v1 = cw[w * CS + 64 + lane];
+                const uint32_t s0 = wave_scan_add(v0);
+                const uint32_t s1 = wave_scan_add(v1) + (uint32_t)__builtin_amdgcn_readlane((int)s0, 63);
+                const uint32_t dd = shifted_prefix(s0, s1, lane, 2 * R) - (s0 - v0);
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    key = max(key, (((dd >> (10 * k)) & 1023u) << 7) | (127u - (uint32_t)(3 * w + k)));
+            }
+        }
+        if constexpr (NV > 1) keys[wv * 64 + lane] = key;
+        barrier();
+        if constexpr (NV > 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) key = max(key, keys[v * 64 + lane]);
+        }
+        uint32_t lev[NPX];
+#pragma unroll
+        for (int q = 0; q < NPX; ++q) {
+            lev[q] = (step && pc[q] < TW) ? level(px[q]) : (uint32_t)L;
+            if (lev[q] < (uint32_t)L) {
+                uint32_t* c = cw + (lev[q] / 3u) * CS + pc[q];
+                if (enter[q])
+                    lds_add(c, count_bit(lev[q]));
+                else
+                    lds_sub(c, count_bit(lev[q]));
+            }
+        }
+        // pass 2: this wavefront's share of the winning level's window word
+        const uint32_t n = key >> 7;
+        const uint64_t* ent = reinterpret_cast<const uint64_t*>(ch + (127u - (key & 127u)) * RS) + lane;
+        uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int d = d0;
+#pragma unroll 1
+        for (; d + 4 <= d1; d += 4) {
+            a0 += ent[d];
+            a1 += ent[d + 1];
+            a2 += ent[d + 2];
+            a3 += ent[d + 3];
+        }
+        for (; d < d1; ++d) a0 += ent[d];
+        uint64_t word = (a0 + a1) + (a2 + a3);
+        const int fin = NV == 1 ? 0 : ((y - ya) & (NV - 1));
+        if constexpr (NV > 1)
+            if (wv != fin) words[wv * 64 + lane] = word;
+        barrier();
+        if (wv == fin) {
+            if constexpr (NV > 1) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v != fin) word += words[v * 64 + lane];
+            }
+            store_row(j, x0, y, n, finalize_packed<false>(n, word), obuf);
+        }
+#pragma unroll
+        for (int q = 0; q < NPX; ++q)
+            if (lev[q] < (uint32_t)L) {
+                uint64_t* c = reinterpret_cast<uint64_t*>(ch + lev[q] * RS + pc[q] * 8);
+                if (enter[q])
+                    lds_add(c, inc(px[q]));
+                else
+                    lds_sub(c, inc(px[q]));
+            }
+        lds_order();
+    };
+    PixelBytes pa[NPX];
+    if constexpr (NV == 1) {
+        // one wavefront: a step's pixels are fetched one row ahead, into two
+        // register sets taken in turn
+        PixelBytes pb[NPX];
+        fetch(ya, pa);
+#pragma unroll 1
+        for (int y = ya; y < yb; y += 2) {
+            fetch(y + 1, pb);
+            row(y, pa);
+            if (y + 1 < yb) {
+                fetch(y + 2, pa);
+                row(y + 1, pb);
+            }
+        }
+    } else {
+        // several: the other wavefronts hide the latency of a fetch at the
+        // top of the row (measured faster than fetching a row ahead)
+#pragma unroll 1
+        for (int y = ya; y < yb; ++y) {
+            fetch(y, pa);
+            row(y, pa);
+        }
+    }
+}
+
+template <int NW, int NV>
+__device__ __forceinline__ void batch_column15(const BatchArgs& a, uint8_t* lds) {
+    if constexpr (NV == 1) {
+        for (;;) {
+            const int32_t t = next_tile_wave(a.counter);
+            if (t >= a.ntiles) break;
+            const int i = job_of(a, t);
+            const Job jb = a.jobs[i];
+            tile_column15<NW, 1>(jb, t - a.first_tile[i], lds);
+        }
+    } else {
+        __shared__ int32_t next;
+        for (;;) {
+            if (threadIdx.x == 0) next = (int32_t)atomicAdd(a.counter, 1u);
+            lds_barrier();
+            const int32_t t = __builtin_amdgcn_readfirstlane(next);
+            if (t >= a.ntiles) break;
+            const int i = job_of(a, t);
+            const Job jb = a.jobs[i];
+            tile_column15<NW, NV>(jb, t - a.first_tile[i], lds);
+        }
+    }
+}
+
 // One class of a batch in the column layout.
 template <int NT>
 __device__ __forceinline__ void batch_column(const BatchArgs& a, uint8_t* lds) {

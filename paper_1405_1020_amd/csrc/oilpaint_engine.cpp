@@ -43,6 +43,11 @@ int batch_shape(Job& j, int device) {
         v.waves = 1;
         v.per_cu = 8;
     }
+    if (v.hist == OILPAINT_HIST_COLUMN && v.waves > 1) {
+        // batches run the column layout's one-wavefront form
+        v.waves = 1;
+        v.per_cu = 8;
+    }
     if (!is_stream(v.hist) && v.waves > 1) {
         if (j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
             v.hist = OILPAINT_HIST_STREAM;

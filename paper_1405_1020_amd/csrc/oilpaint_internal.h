@@ -22,6 +22,26 @@ constexpr int kWideMaxRadius = 2051;
 constexpr int kColumnMaxRadius = 255;
 constexpr int kColumnChunks = 9;
 inline int column_chunks(int radius) { return (64 + 2 * radius + 63) / 64; }
+// The column layout's form for radius <= 15 and at most 64 levels
+// (tile_column15): column entries in the F18 bin word, level rows of
+// kColumn15Stride columns, and per column its level counts three to a
+// 32-bit word (column15_words(levels) words, bucketed: 3, 7, 11, 22).
+constexpr int kColumn15Stride = 96;
+constexpr int kColumn15Buckets = 4;
+constexpr int kColumn15MaxLevels = 64;
+inline int column15_bucket(int levels) { return levels <= 9 ? 0 : levels <= 21 ? 1 : levels <= 33 ? 2 : 3; }
+inline int column15_words(int levels) {
+    constexpr int kWords[kColumn15Buckets] = {3, 7, 11, 22};
+    return kWords[column15_bucket(levels)];
+}
+// [column histograms: one row per level][count words][keys and partial
+// words of each wavefront][row buffer]
+inline size_t column15_lds_bytes(int levels, int waves) {
+    return (size_t)levels * kColumn15Stride * 8 + (size_t)column15_words(levels) * kColumn15Stride * 4 +
+           (size_t)waves * 64 * 12 + 192;
+}
+// Wavefronts per strip of the radius <= 15 form: 1, 2 or 4 (index 0, 1, 2).
+inline int column15_wave_index(int waves) { return waves == 1 ? 0 : waves == 2 ? 1 : waves == 4 ? 2 : -1; }
 // Largest window pixel count the packed layout's division table covers.
 constexpr int kPackedMaxCount = 961;
 
@@ -80,6 +100,10 @@ __host__ __device__ inline bool is_stream(int hist) { return hist == OILPAINT_HI
 // the run of every wavefront (not multiplied by the wavefront count).
 constexpr int kSplitWaves = 4;
 __host__ __device__ inline bool is_split(const Job& j) { return is_stream(j.hist) && j.waves == kSplitWaves; }
+// Whether a column-layout job takes the radius <= 15 form.
+inline bool column15(const Job& j) {
+    return j.radius >= 0 && j.radius <= kPackedMaxRadius && j.levels >= 1 && j.levels <= kColumn15MaxLevels;
+}
 inline int split_bins(int levels) {
     return levels <= 8 ? 2 : levels <= 16 ? 4 : levels <= 20 ? 5 : levels <= 32 ? 8 : 16;
 }
@@ -182,10 +206,16 @@ extern const BatchKernel kBatchSplit8[8];
 // Column-layout kernels (oilpaint_k_column.hip), [chunks - 1].
 extern const PlainKernel kColumn[kColumnChunks];
 extern const BatchKernel kBatchColumn[kColumnChunks];
+// Its radius <= 15 form, [column15_wave_index(waves)][column15_bucket(levels)];
+// the batch form has one wavefront per strip.
+extern const PlainKernel kColumn15[3][kColumn15Buckets];
+extern const BatchKernel kBatchColumn15[kColumn15Buckets];
 
 // Kernel class of a batch job: 2 * radius + scan bucket (0: scan <= 32,
 // 1: scan <= 64) for the streamed layout, 32 + radius - 8 for its 8-byte
-// form, 40 + chunks - 1 for the column layout, then the same for the
+// form, 40 + chunks - 1 for the column layout (radius above 15 or more than
+// 64 levels) and 49 + column15_bucket(levels) for its radius <= 15 form,
+// then the same for the
 // four-wavefront streamed layouts (from kSplitClass: 2 * radius + bucket,
 // then 32 + radius - 8), and kGenericClass for every other job (generic
 // tile-staged and wide layouts, one kernel for all).  A batch launches one
@@ -193,7 +223,8 @@ extern const BatchKernel kBatchColumn[kColumnChunks];
 // workgroup.
 constexpr int kStream8Class = 2 * (kPackedMaxRadius + 1);
 constexpr int kColumnClass = kStream8Class + 8;
-constexpr int kSplitClass = kColumnClass + kColumnChunks;
+constexpr int kColumn15Class = kColumnClass + kColumnChunks;
+constexpr int kSplitClass = kColumn15Class + kColumn15Buckets;
 constexpr int kGenericClass = kSplitClass + kStream8Class + 8;
 constexpr int kBatchClasses = kGenericClass + 1;
 inline int batch_class(const Job& j) {
@@ -202,14 +233,15 @@ inline int batch_class(const Job& j) {
         return split + 2 * j.radius + (j.scan <= 32 ? 0 : 1);
     if (j.hist == OILPAINT_HIST_STREAM8 && j.radius >= 8 && j.radius <= kPackedMaxRadius && j.scan <= 32)
         return split + kStream8Class + j.radius - 8;
+    if (j.hist == OILPAINT_HIST_COLUMN && column15(j)) return kColumn15Class + column15_bucket(j.levels);
     if (j.hist == OILPAINT_HIST_COLUMN && j.radius >= 0 && j.radius <= kColumnMaxRadius)
         return kColumnClass + column_chunks(j.radius) - 1;
     return kGenericClass;
 }
 inline int batch_waves(int cls) { return cls >= kSplitClass && cls < kGenericClass ? kSplitWaves : 1; }
-// Output rows of one tile: a run per wavefront, except in the streamed
-// layouts, whose wavefronts share one run.
-inline int runs_per_tile(int hist, int waves) { return is_stream(hist) ? 1 : waves; }
+// Output rows of one tile: a run per wavefront, except in the streamed and
+// column layouts, whose wavefronts share one run.
+inline int runs_per_tile(int hist, int waves) { return is_stream(hist) || hist == OILPAINT_HIST_COLUMN ? 1 : waves; }
 
 // Windowed median of one channel (oilpaint_k_median.hip): one image, one
 // wavefront per workgroup of 64 output columns by `rows` output rows.

@@ -88,6 +88,7 @@ int g_stream8_lds_done[8];
 int g_split_lds_done[8][4];
 int g_split4_lds_done[kPackedMaxRadius + 1][5];
 int g_column_lds_done[kColumnChunks];
+int g_column15_lds_done[3][kColumn15Buckets];
 int g_plain_lds_done;
 int g_batch_lds_done[kBatchClasses];
 
@@ -99,6 +100,7 @@ BatchKernel batch_kernel(int cls) {
         const int r = c >> 1, b = c & 1;
         return r <= 7 ? kBatchSplit_lo[r][b] : kBatchSplit_hi[r - 8][b];
     }
+    if (cls >= kColumn15Class) return kBatchColumn15[cls - kColumn15Class];
     if (cls >= kColumnClass) return kBatchColumn[cls - kColumnClass];
     if (cls >= kStream8Class) return kBatchStream8[cls - kStream8Class];
     const int r = cls >> 1, b = cls & 1;
@@ -112,10 +114,18 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
     PlainKernel k = k_plain;
     int* done = &g_plain_lds_done;
     if (j.hist == OILPAINT_HIST_COLUMN) {
-        if (j.radius < 0 || j.radius > kColumnMaxRadius || waves != 1) return hipErrorInvalidValue;
-        const int nt = column_chunks(j.radius);
-        k = kColumn[nt - 1];
-        done = &g_column_lds_done[nt - 1];
+        if (j.radius < 0 || j.radius > kColumnMaxRadius || waves != j.waves) return hipErrorInvalidValue;
+        if (column15(j)) {
+            const int b = column15_bucket(j.levels), wi = column15_wave_index(waves);
+            if (wi < 0) return hipErrorInvalidValue;
+            k = kColumn15[wi][b];
+            done = &g_column15_lds_done[wi][b];
+        } else {
+            if (waves != 1) return hipErrorInvalidValue;
+            const int nt = column_chunks(j.radius);
+            k = kColumn[nt - 1];
+            done = &g_column_lds_done[nt - 1];
+        }
     } else if (j.hist == OILPAINT_HIST_STREAM && waves == kSplitWaves) {
         const int b = j.scan % kSplitWaves == 0 ? split_bucket(j.scan / kSplitWaves) : -1;
         if (j.radius < 0 || j.radius > kPackedMaxRadius || b < 0 || j.waves != kSplitWaves) return hipErrorInvalidValue;

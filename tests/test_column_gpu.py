@@ -62,6 +62,61 @@ def test_column_matches_oracle(case):
                 assert mm is None, (w, h, r, L, rows, mm)
 
 
+# the radius <= 15 form, with one, two and four wavefronts per strip: every
+# radius 0..15 (some clipped by the image), both sides of each prefix-word
+# bucket edge (9/10, 21/22, 33/34 levels) and 64, run lengths from 1 row
+SMALL = [
+    ((65, 40), (0, 1, 3, 7)),
+    ((130, 57), (8, 11, 15)),
+    ((97, 33), (2, 5, 13, 14)),
+    ((1, 1), (0,)),
+    ((70, 3), (4, 6, 9, 10, 12)),
+]
+
+
+@pytest.mark.parametrize("waves", (1, 2, 4))
+@pytest.mark.parametrize("case", range(len(SMALL)))
+def test_column15_matches_oracle(case, waves):
+    (w, h), radii = SMALL[case]
+    img = image(w, h, seed=400 + case)
+    for r in radii:
+        for L in (1, 9, 10, 21, 22, 33, 34, 64):
+            want = ref(img, r, L)
+            for rows in (1, 2, 5, 300):
+                v = B.Variant(rows, waves, B.HIST_COLUMN, 64)
+                got = run_variant(img, r, L, v, pad=(w + rows) % 5)
+                mm = first_mismatch(got, want)
+                assert mm is None, (w, h, r, L, waves, rows, mm)
+
+
+@pytest.mark.parametrize("waves", (1, 2, 4))
+def test_column15_paper_form_and_bands(waves):
+    # the paper form (white level and borders left alone) and a row band,
+    # through the registered launch shape
+    torch = torch_mod()
+    img = image(150, 90, seed=17)
+    try:
+        for r, L in ((3, 20), (10, 8), (15, 33), (15, 64)):
+            assert B.set_variant(r, L, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.OK
+            src, _ = to_device(img)
+            junk = np.random.default_rng(r + L).integers(0, 256, img.shape, dtype=np.uint8)
+            dst, _ = to_device(junk)
+            B.run(B.Item(src, dst, r, L, flags=B.FLAG_PAPER))
+            torch.cuda.synchronize()
+            want = ref(img, r, L, paper=True, out=junk.copy())
+            mm = first_mismatch(from_device(dst), want)
+            assert mm is None, ("paper", r, L, waves, mm)
+            dst, _ = to_device(junk)
+            B.run(B.Item(src, dst, r, L, row_begin=17, row_end=61))
+            torch.cuda.synchronize()
+            want = junk.copy()
+            want[17:61] = ref(img, r, L)[17:61]
+            mm = first_mismatch(from_device(dst), want)
+            assert mm is None, ("band", r, L, waves, mm)
+    finally:
+        B.clear_variants()
+
+
 def test_column_paper_form():
     torch = torch_mod()
     img = image(150, 90, seed=7)
