@@ -286,8 +286,8 @@ __device__ __forceinline__ void tile_column(const Job& j, int unit, uint8_t* lds
 // Pass 2 sums the 2r+1 entries of each lane's winning level directly: a
 // fixed cost, however many distinct winners a row has.  Outside pixels and
 // the paper form's white level are counted nowhere.
-//   LDS: [column histograms: L level rows x 96 columns x 8 B]
-//        [count words: NW x 96 x 4 B][output row buffer: 192 B]
+//   LDS: [column histograms: L level rows x 94 columns x 8 B]
+//        [count words: NW x 94 x 4 B] ...
 
 // Prefix sum of the wavefront's column words at column lane + 2R (chunk 0
 // holds columns 0..63, chunk 1 columns 64..): a lane permute of either
@@ -310,7 +310,8 @@ __device__ __forceinline__ uint32_t shifted_prefix(uint32_t s0, uint32_t s1, int
 // column of the strip, leaving row y-R and entering row y+1+R, dealt as
 // (leave/enter, 64-column chunk) pairs.
 //   LDS, after the count words: [keys: NV x 64 x 4 B][partial words:
-//   NV x 64 x 8 B][output row buffer: 192 B]
+//   (NV - 1) x 64 x 8 B, slot (w - finalizer - 1) mod NV][output row
+//   buffer: 192 B]
 template <int NW, int NV>
 __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* lds) {
     static_assert(NV == 1 || NV == 2 || NV == 4, "one, two or four wavefronts per strip");
@@ -332,7 +333,7 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
     uint32_t* cw = reinterpret_cast<uint32_t*>(lds + (size_t)L * RS);
     uint32_t* keys = cw + NW * CS;
     uint64_t* words = reinterpret_cast<uint64_t*>(keys + NV * 64);
-    uint8_t* obuf = reinterpret_cast<uint8_t*>(words + NV * 64);
+    uint8_t* obuf = reinterpret_cast<uint8_t*>(words + (NV - 1) * 64);
     const bool paper = j.paper != 0;
     auto barrier = [] {
         if constexpr (NV > 1)
@@ -351,7 +352,8 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
     auto count_bit = [](uint32_t k) { return 1u << (10u * (k % 3u)); };
 
     {
-        const int n16 = (int)(((size_t)L * RS + (size_t)NW * CS * 4) / 16);
+        // (rounded up into the keys, which are written before they are read)
+        const int n16 = (int)(((size_t)L * RS + (size_t)NW * CS * 4 + 15) / 16);
         for (int e = (int)threadIdx.x; e < n16; e += NT)
             *reinterpret_cast<uint4*>(ch + (size_t)e * 16) = make_uint4(0u, 0u, 0u, 0u);
     }
@@ -414,20 +416,21 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
         // level, lowest among equals, is the largest key (count << 7) |
         // (127 - level).  Chunk-1 columns past the strip read whatever
         // follows in LDS: only scan entries at lanes they precede are used.
+        // Every wavefront takes the same number of words, the last one again
+        // where the words run out (a repeated word repeats its keys), so
+        // that the words' scans interleave without branches.
         uint32_t key = 0;
 #pragma unroll
         for (int i = 0; i < (NW + NV - 1) / NV; ++i) {
-            const int w = i * NV + wv;
-            if (NV == 1 || w < NW) {
-                const uint32_t v0 = cw[w * CS + lane];
-                const uint32_t v1 = cw[w * CS + 64 + lane];
-                const uint32_t s0 = wave_scan_add(v0);
-                const uint32_t s1 = wave_scan_add(v1) + (uint32_t)__builtin_amdgcn_readlane((int)s0, 63);
-                const uint32_t dd = shifted_prefix(s0, s1, lane, 2 * R) - (s0 - v0);
+            const int w = min(i * NV + wv, NW - 1);
+            const uint32_t v0 = cw[w * CS + lane];
+            const uint32_t v1 = cw[w * CS + 64 + lane];
+            const uint32_t s0 = wave_scan_add(v0);
+            const uint32_t s1 = wave_scan_add(v1) + (uint32_t)__builtin_amdgcn_readlane((int)s0, 63);
+            const uint32_t dd = shifted_prefix(s0, s1, lane, 2 * R) - (s0 - v0);
 #pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    key = max(key, (((dd >> (10 * k)) & 1023u) << 7) | (127u - (uint32_t)(3 * w + k)));
-            }
+            for (int k = 0; k < 3; ++k)
+                key = max(key, (((dd >> (10 * k)) & 1023u) << 7) | (127u - (uint32_t)(3 * w + k)));
         }
         if constexpr (NV > 1) keys[wv * 64 + lane] = key;
         barrier();
@@ -463,13 +466,12 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
         uint64_t word = (a0 + a1) + (a2 + a3);
         const int fin = NV == 1 ? 0 : ((y - ya) & (NV - 1));
         if constexpr (NV > 1)
-            if (wv != fin) words[wv * 64 + lane] = word;
+            if (wv != fin) words[((wv - fin - 1) & (NV - 1)) * 64 + lane] = word;
         barrier();
         if (wv == fin) {
             if constexpr (NV > 1) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    if (v != fin) word += words[v * 64 + lane];
+                for (int v = 0; v < NV - 1; ++v) word += words[v * 64 + lane];
             }
             store_row(j, x0, y, n, finalize_packed<false>(n, word), obuf);
         }
@@ -501,9 +503,12 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
         }
     } else {
         // several: the other wavefronts hide the latency of a fetch at the
-        // top of the row (measured faster than fetching a row ahead)
+        // top of the row (measured faster than fetching a row ahead); the
+        // wavefront priority follows the run's progress
+        const int q1 = ya + (yb - ya) / 4, q2 = ya + (yb - ya) / 2, q3 = ya + 3 * (yb - ya) / 4;
 #pragma unroll 1
         for (int y = ya; y < yb; ++y) {
+            progress_priority(y, q1, q2, q3);
             fetch(y, pa);
             row(y, pa);
         }

@@ -26,7 +26,7 @@ inline int column_chunks(int radius) { return (64 + 2 * radius + 63) / 64; }
 // (tile_column15): column entries in the F18 bin word, level rows of
 // kColumn15Stride columns, and per column its level counts three to a
 // 32-bit word (column15_words(levels) words, bucketed: 3, 7, 11, 22).
-constexpr int kColumn15Stride = 96;
+constexpr int kColumn15Stride = 94;  // 64 + 2 * 15
 constexpr int kColumn15Buckets = 4;
 constexpr int kColumn15MaxLevels = 64;
 inline int column15_bucket(int levels) { return levels <= 9 ? 0 : levels <= 21 ? 1 : levels <= 33 ? 2 : 3; }
@@ -34,11 +34,12 @@ inline int column15_words(int levels) {
     constexpr int kWords[kColumn15Buckets] = {3, 7, 11, 22};
     return kWords[column15_bucket(levels)];
 }
-// [column histograms: one row per level][count words][keys and partial
-// words of each wavefront][row buffer]
+// [column histograms: one row per level][count words][a key per
+// wavefront][a partial word per wavefront but one][row buffer]: at r <= 15,
+// 20 levels and four wavefronts 20,424 bytes, eight workgroups per CU
 inline size_t column15_lds_bytes(int levels, int waves) {
     return (size_t)levels * kColumn15Stride * 8 + (size_t)column15_words(levels) * kColumn15Stride * 4 +
-           (size_t)waves * 64 * 12 + 192;
+           (size_t)waves * 64 * 4 + (size_t)(waves - 1) * 64 * 8 + 192;
 }
 // Wavefronts per strip of the radius <= 15 form: 1, 2 or 4 (index 0, 1, 2).
 inline int column15_wave_index(int waves) { return waves == 1 ? 0 : waves == 2 ? 1 : waves == 4 ? 2 : -1; }

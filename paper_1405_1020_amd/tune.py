@@ -3,7 +3,7 @@
 For each (radius, levels) the candidates -- streamed rows with several
 workgroup densities (and, for radius 8..15 with at most 32 levels, the
 same with 8-byte on-chip row entries), tile-staged workgroups of 2 or 4
-wavefronts with several densities, column histograms for radii from 8
+wavefronts with several densities, column histograms for radii from 7
 (at most 33 levels; one, two or four wavefronts per strip) and above 15,
 and the wide layout above 15 -- are
 timed by the library itself (oilpaint_tune, HIP
@@ -66,11 +66,11 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
     if radius > 15:
         for per_cu in (1, 2, 4, 8, 16):
             out.append(B.Variant(0, 1, B.HIST_COLUMN, 64, per_cu))
-    elif radius >= 8 and levels <= 33:
+    elif radius >= 7 and levels <= 33:
         # column histograms cost O(levels) per row (and 2r+1 reads for the
         # winning level): they can win at wide windows and few levels; one,
         # two or four wavefronts per strip
-        for waves, per_cu in ((1, 8), (2, 8), (4, 4), (4, 5), (4, 6), (4, 7)):
+        for waves, per_cu in ((1, 8), (2, 8), (4, 4), (4, 6), (4, 7), (4, 8)):
             out.append(B.Variant(0, waves, B.HIST_COLUMN, 64, per_cu))
     if not out or radius > 15:
         for per_cu in (1, 2, 4):
