@@ -37,7 +37,7 @@ METRIC = "megapixels/sec at (r, L), batched/served vs plain kernel; p50/p99 requ
 # GPU host, with $OUT an output directory (the first line fills the tuning
 # cache so that the profiled runs launch only the timed shapes).
 HBM_COMMANDS = [
-    "python3 bench.py --quick --steps 5 --warmup 2",
+    "python3 bench.py --quick --steps 5 --warmup 2 > $OUT/quick.json",
     "cd /tmp && export TMPDIR=/tmp",
     "timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d $OUT/sweep_fetch --output-format csv -- "
     "python3 $REPO/bench.py --quick --steps 5 --warmup 2",
@@ -47,7 +47,7 @@ HBM_COMMANDS = [
     "python3 $REPO/bench.py --copy-ref",
     "timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d $OUT/copy_write --output-format csv -- "
     "python3 $REPO/bench.py --copy-ref",
-    "cd $REPO && python3 bench.py --hbm-summary $OUT",
+    "cd $REPO && python3 bench.py --hbm-summary $OUT --sweep-json $OUT/quick.json",
 ]
 LDS_PEAK_GBS = 256 * 2.4e9 * 256 / 1e9  # 256 CUs x 2.4 GHz x 256 B/clk LDS read path
 
@@ -437,21 +437,97 @@ def hbm_traffic(kernel: str, config: str, variant=None):
     return e.get("hbm_bytes_per_launch")
 
 
+def _kernel_short_name(full: str) -> str:
+    import re
+    m = re.search(r"(k_\w+(?:<[\d, ]+>)?)\(", full)
+    return m.group(1) if m else full
+
+
 def _pmc_rows(folder: str, counter: str):
-    """(kernel name, grid size, value) of every dispatch in a rocprofv3
-    --pmc CSV output under `folder`."""
+    """(file, dispatch id, kernel name, grid size, value) of every dispatch
+    in a rocprofv3 --pmc CSV output under `folder` (a file per process), in
+    dispatch order."""
     import csv
     import glob
-    import re
     out = []
     for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
         for row in csv.DictReader(open(f)):
             if row.get("Counter_Name") != counter:
                 continue
-            m = re.search(r"(k_\w+(?:<[\d, ]+>)?)\(", row["Kernel_Name"])
-            name = m.group(1) if m else row["Kernel_Name"]
-            out.append((name, int(row.get("Grid_Size", 0) or 0), float(row["Counter_Value"])))
+            out.append((f, int(row.get("Dispatch_Id", 0) or 0), _kernel_short_name(row["Kernel_Name"]),
+                        int(row.get("Grid_Size", 0) or 0), float(row["Counter_Value"])))
+    return sorted(out)
+
+
+def _trace_rows(folder: str):
+    """(file, dispatch id, kernel name, grid size, duration in ns) of every
+    dispatch in a rocprofv3 --kernel-trace CSV output under `folder`, in
+    dispatch order."""
+    import csv
+    import glob
+    out = []
+    for f in glob.glob(os.path.join(folder, "**", "*kernel_trace.csv"), recursive=True):
+        for row in csv.DictReader(open(f)):
+            grid = int(row["Grid_Size_X"]) * int(row["Grid_Size_Y"]) * int(row["Grid_Size_Z"])
+            out.append((f, int(row["Dispatch_Id"]), _kernel_short_name(row["Kernel_Name"]), grid,
+                        float(row["End_Timestamp"]) - float(row["Start_Timestamp"])))
+    return sorted(out)
+
+
+def sweep_run_values(rows, runs) -> dict:
+    """Per sweep run, the values of its dispatches.  `rows` are (file,
+    dispatch id, kernel, grid, value) in dispatch order; `runs` are (run,
+    kernel, grid) in the order one step launches them.  A dispatch belongs to
+    the run with its kernel and grid.  Runs that share both (a kernel whose
+    radius is an argument) follow each other in the sweep and are launched
+    the same number of times in each phase of bench_plain (a step launches
+    every run once; then each run is timed alone), so each maximal block of
+    consecutive such dispatches splits into equal parts, in run order; a
+    block that does not split evenly is left out."""
+    out = {run: [] for run, _, _ in runs}
+    index = {}
+    for i, (_, k, g) in enumerate(runs):
+        index.setdefault((k, g), []).append(i)
+    i = 0
+    while i < len(rows):
+        f, _, k, g, _ = rows[i]
+        j = i
+        while j < len(rows) and rows[j][0] == f and rows[j][2] == k and rows[j][3] == g:
+            j += 1
+        idx = index.get((k, g), [])
+        n, m = j - i, len(idx)
+        if m and n % m == 0:
+            for part, ri in enumerate(idx):
+                out[runs[ri][0]].extend(v for *_, v in rows[i + part * (n // m):i + (part + 1) * (n // m)])
+        i = j
     return out
+
+
+def sweep_runs(sweep_json: str, w: int = 1920, h: int = 1080):
+    """(run, kernel, grid work-items, variant) of the 1920x1080 sweep's runs
+    in launch order, as the bench output `sweep_json` (the last JSON line of
+    a `bench.py --quick` run) records them."""
+    from paper_1405_1020_amd import synth
+    line = [x for x in open(sweep_json).read().splitlines() if x.startswith("{")][-1]
+    sweep = json.loads(line)["sweep"]
+    out = []
+    for r, L in synth.FHD_SWEEP:
+        e = sweep["r%d_L%d" % (r, L)]
+        out.append(("r%d_L%d" % (r, L), e["kernel"], launch_threads(w, h, e["variant"]), list(e["variant"])))
+    return out
+
+
+def trace_summary(folder: str, sweep_json: str) -> dict:
+    """Per sweep run, the kernel-trace durations of its dispatches (the
+    `--kernel-trace` output under `folder` of `bench.py --quick`, whose
+    launch shapes `sweep_json` records)."""
+    import statistics
+    runs = sweep_runs(sweep_json)
+    vals = sweep_run_values(_trace_rows(folder), [(n, k, g) for n, k, g, _ in runs])
+    return {n: {"kernel": k, "grid_threads": g, "dispatches": len(vals[n]),
+                "mean_us": round(statistics.fmean(vals[n]) / 1e3, 2) if vals[n] else None,
+                "median_us": round(statistics.median(vals[n]) / 1e3, 2) if vals[n] else None}
+            for n, k, g, _ in runs}
 
 
 def launch_threads(w: int, h: int, variant) -> int:
@@ -466,14 +542,14 @@ def launch_threads(w: int, h: int, variant) -> int:
     return tiles * 64 * waves
 
 
-def hbm_entry(folder: str, name: str, variant, w: int, h: int, scale: dict) -> dict:
-    """Counters per dispatch of one sweep run: the dispatches of its kernel
-    with its grid size."""
+def hbm_entry(folder: str, run: str, runs, w: int, h: int, scale: dict) -> dict:
+    """Counters per dispatch of one sweep run (its dispatches as
+    sweep_run_values attributes them); `runs` as sweep_runs gives them."""
     import statistics
-    grid = launch_threads(w, h, variant)
+    name, grid, variant = next((k, g, v) for n, k, g, v in runs if n == run)
     e = {"kernel": name, "variant": variant, "grid_threads": grid}
     for c, sub in (("FETCH_SIZE", "sweep_fetch"), ("WRITE_SIZE", "sweep_write")):
-        vals = [v for n, g, v in _pmc_rows(os.path.join(folder, sub), c) if n == name and g == grid]
+        vals = sweep_run_values(_pmc_rows(os.path.join(folder, sub), c), [(n, k, g) for n, k, g, _ in runs])[run]
         e[c.lower() + "_kib_per_dispatch"] = round(statistics.median(vals), 1) if vals else None
         e[c.lower() + "_dispatches"] = len(vals)
     if e["fetch_size_kib_per_dispatch"] is not None and e["write_size_kib_per_dispatch"] is not None:
@@ -483,7 +559,7 @@ def hbm_entry(folder: str, name: str, variant, w: int, h: int, scale: dict) -> d
     return e
 
 
-def write_hbm_summary(folder: str, commands: list[str]):
+def write_hbm_summary(folder: str, sweep_json: str, commands: list[str]):
     """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE over
     `bench.py --quick` and over `bench.py --copy-ref`, in the sub-folders
     sweep_fetch, sweep_write, copy_fetch and copy_write of `folder`) into
@@ -491,18 +567,14 @@ def write_hbm_summary(folder: str, commands: list[str]):
     its kernel, scaled so that the copy kernel's counters read its known
     bytes."""
     import statistics
-    from paper_1405_1020_amd import binding as B, synth, tune
-    tune.load()  # the launch shapes the profiled runs used
     copy_bytes = 1 << 30
     scale = {}
     for c, sub in (("FETCH_SIZE", "copy_fetch"), ("WRITE_SIZE", "copy_write")):
-        vals = [v for n, g, v in _pmc_rows(os.path.join(folder, sub), c) if g >= (1 << 20)]
+        vals = [v for _, _, n, g, v in _pmc_rows(os.path.join(folder, sub), c) if g >= (1 << 20)]
         scale[c] = copy_bytes / (statistics.median(vals) * 1024.0)
     w, h = 1920, 1080
-    launches = {}
-    for r, L in synth.FHD_SWEEP:
-        v = B.pick_variant(w, h, r, L)
-        launches["r%d_L%d" % (r, L)] = hbm_entry(folder, kernel_name(r, L, v), list(v.as_tuple()), w, h, scale)
+    runs = sweep_runs(sweep_json, w, h)
+    launches = {n: hbm_entry(folder, n, runs, w, h, scale) for n, _, _, _ in runs}
     out = {"kernel_source_sha": kernel_source_hash(), "workload": "fhd_1920x1080_sweep",
            "commands": commands, "copy_reference": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
                                                      "scale": {k: round(v_, 4) for k, v_ in scale.items()}},
@@ -523,20 +595,28 @@ def main():
                     help="run only a plain 1 GiB device copy kernel (HBM counter scaling) and exit")
     ap.add_argument("--hbm-summary", metavar="DIR",
                     help="write the HBM counter summary under profiles/ from rocprofv3 --pmc outputs in DIR")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="print per sweep run the kernel-trace durations from rocprofv3 --kernel-trace output in DIR")
+    ap.add_argument("--sweep-json", metavar="FILE",
+                    help="with --hbm-summary or --trace-summary: the output of the profiled bench.py --quick run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.hbm_summary or args.trace_summary:
+        if not args.sweep_json:
+            ap.error("--sweep-json is required with --hbm-summary and --trace-summary")
+        if args.hbm_summary:
+            write_hbm_summary(args.hbm_summary, args.sweep_json, HBM_COMMANDS)
+        else:
+            print(json.dumps(trace_summary(args.trace_summary, args.sweep_json), indent=1))
+        return
 
     import torch
     from paper_1405_1020_amd import binding as B, synth, serve
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B.lib()
-
-    if args.hbm_summary:
-        write_hbm_summary(args.hbm_summary, HBM_COMMANDS)
-        return
 
     if args.copy_ref:
         n = 1 << 30
