@@ -37,7 +37,7 @@ METRIC = "megapixels/sec at (r, L), batched/served vs plain kernel; p50/p99 requ
 # GPU host, with $OUT an output directory (the first line fills the tuning
 # cache so that the profiled runs launch only the timed shapes).
 HBM_COMMANDS = [
-    "python3 bench.py --quick --steps 5 --warmup 2 > $OUT/quick.json",
+    "python3 bench.py --quick --steps 20 --warmup 3 > $OUT/quick.json",
     "cd /tmp && export TMPDIR=/tmp",
     "timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d $OUT/sweep_fetch --output-format csv -- "
     "python3 $REPO/bench.py --quick --steps 5 --warmup 2",
