@@ -143,10 +143,14 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *                         prefix sums across the strip, so the work per
  *                         output row does not grow with the radius (column
  *                         histograms after Perreault and Hebert, "Median
- *                         filtering in constant time", 2007); one wavefront
- *                         of 64 lanes per workgroup, radius <= 255, any
- *                         level count whose (levels + 1) x (64 + 2 radius)
- *                         8-byte column histograms fit on chip
+ *                         filtering in constant time", 2007); 64 lanes,
+ *                         radius <= 255, any level count whose (levels + 1)
+ *                         x (64 + 2 radius) 8-byte column histograms fit on
+ *                         chip; one wavefront per workgroup, or, for radius
+ *                         <= 15 and at most 64 levels, 1, 2 or 4 wavefronts
+ *                         sharing the strip (runs as in STREAM: waves x 64
+ *                         threads work one run of `rows` output rows).
+ *                         Batches and plans run these jobs with waves = 1.
  * ------------------------------------------------------------------------- */
 #define OILPAINT_HIST_PACKED  0
 #define OILPAINT_HIST_STREAM  1
