@@ -44,9 +44,20 @@ int batch_shape(Job& j, int device) {
         v.per_cu = 8;
     }
     if (v.hist == OILPAINT_HIST_COLUMN && v.waves > 1) {
-        // batches run the column layout's one-wavefront form
-        v.waves = 1;
-        v.per_cu = 8;
+        // batches have no several-wavefront column kernel: the streamed
+        // layout's classes (four wavefronts from kBatchSplitMinRadius), whose
+        // one-wavefront batch forms beat the column layout's; its
+        // one-wavefront form for the paper form, as below
+        if (!j.paper) {
+            v.hist = OILPAINT_HIST_STREAM;
+            v.lanes = 64;
+            v.rows = 0;
+            v.waves = j.radius >= kBatchSplitMinRadius ? kSplitWaves : 1;
+            v.per_cu = v.waves > 1 ? 5 : 8;
+        } else {
+            v.waves = 1;
+            v.per_cu = 8;
+        }
     }
     if (!is_stream(v.hist) && v.waves > 1) {
         if (j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
