@@ -349,7 +349,12 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
     auto inc = [](const PixelBytes& p) -> uint64_t {
         return ((uint64_t)((p.c2 << 4) | (1u << 22)) << 32) | (p.c0 | (p.c1 << 18));
     };
-    auto count_bit = [](uint32_t k) { return 1u << (10u * (k % 3u)); };
+    // count word and field of level k < 128: k / 3 == (43 k) >> 7
+    auto count_word = [](uint32_t k) { return mul24(k, 43u) >> 7; };
+    auto count_bit = [&](uint32_t k) { return 1u << mul24(10u, k - mul24(3u, count_word(k))); };
+    auto entry_at = [&](uint32_t k, int c) {
+        return reinterpret_cast<uint64_t*>(ch + mul24(k, RS) + (uint32_t)c * 8u);
+    };
 
     {
         // (rounded up into the keys, which are written before they are read)
@@ -383,8 +388,8 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
             for (int i = 0; i < CH; ++i) {
                 const uint32_t k = level(px[i]);
                 if (k < (uint32_t)L) {
-                    lds_add(reinterpret_cast<uint64_t*>(ch + k * RS + cl[i] * 8), inc(px[i]));
-                    lds_add(cw + (k / 3u) * CS + cl[i], count_bit(k));
+                    lds_add(entry_at(k, cl[i]), inc(px[i]));
+                    lds_add(cw + mul24(count_word(k), CS) + cl[i], count_bit(k));
                 }
             }
         }
@@ -443,7 +448,7 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
         for (int q = 0; q < NPX; ++q) {
             lev[q] = (step && pc[q] < TW) ? level(px[q]) : (uint32_t)L;
             if (lev[q] < (uint32_t)L) {
-                uint32_t* c = cw + (lev[q] / 3u) * CS + pc[q];
+                uint32_t* c = cw + mul24(count_word(lev[q]), CS) + pc[q];
                 if (enter[q])
                     lds_add(c, count_bit(lev[q]));
                 else
@@ -452,7 +457,7 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
         }
         // pass 2: this wavefront's share of the winning level's window word
         const uint32_t n = key >> 7;
-        const uint64_t* ent = reinterpret_cast<const uint64_t*>(ch + (127u - (key & 127u)) * RS) + lane;
+        const uint64_t* ent = entry_at(127u - (key & 127u), lane);
         uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
         int d = d0;
 #pragma unroll 1
@@ -478,7 +483,7 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
 #pragma unroll
         for (int q = 0; q < NPX; ++q)
             if (lev[q] < (uint32_t)L) {
-                uint64_t* c = reinterpret_cast<uint64_t*>(ch + lev[q] * RS + pc[q] * 8);
+                uint64_t* c = entry_at(lev[q], pc[q]);
                 if (enter[q])
                     lds_add(c, inc(px[q]));
                 else
@@ -515,27 +520,16 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
     }
 }
 
-template <int NW, int NV>
+// One class of a batch in the column layout's radius <= 15 form (one
+// wavefront per strip).
+template <int NW>
 __device__ __forceinline__ void batch_column15(const BatchArgs& a, uint8_t* lds) {
-    if constexpr (NV == 1) {
-        for (;;) {
-            const int32_t t = next_tile_wave(a.counter);
-            if (t >= a.ntiles) break;
-            const int i = job_of(a, t);
-            const Job jb = a.jobs[i];
-            tile_column15<NW, 1>(jb, t - a.first_tile[i], lds);
-        }
-    } else {
-        __shared__ int32_t next;
-        for (;;) {
-            if (threadIdx.x == 0) next = (int32_t)atomicAdd(a.counter, 1u);
-            lds_barrier();
-            const int32_t t = __builtin_amdgcn_readfirstlane(next);
-            if (t >= a.ntiles) break;
-            const int i = job_of(a, t);
-            const Job jb = a.jobs[i];
-            tile_column15<NW, NV>(jb, t - a.first_tile[i], lds);
-        }
+    for (;;) {
+        const int32_t t = next_tile_wave(a.counter);
+        if (t >= a.ntiles) break;
+        const int i = job_of(a, t);
+        const Job jb = a.jobs[i];
+        tile_column15<NW, 1>(jb, t - a.first_tile[i], lds);
     }
 }
 

@@ -47,6 +47,15 @@
 namespace oilpaint_impl {
 namespace dev {
 
+// Products of operands below 2^24: the masks let the compiler use the
+// full-rate 24-bit multiplies (v_mul_u32_u24, v_mul_hi_u32_u24) instead of
+// the quarter-rate 32-bit ones.  mul24 is exact while the product is below
+// 2^32, mulhi24 gives bits 32..47 of the 48-bit product.
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
+__device__ __forceinline__ uint32_t mulhi24(uint32_t a, uint32_t b) {
+    return (uint32_t)(((uint64_t)(a & 0xFFFFFFu) * (uint64_t)(b & 0xFFFFFFu)) >> 32);
+}
+
 // floor(s / n) for 1 <= n <= 961 and s <= 255 n, without a divide: with rn
 // the hardware reciprocal of n (v_rcp_f32, within 1 ulp), the float estimate
 // s * rn is within 1e-4 of s/n (s < 2^18, relative error of the reciprocal
@@ -55,9 +64,9 @@ namespace dev {
 // integer checks correct either way.
 __device__ __forceinline__ float rcp_approx(uint32_t n) { return __builtin_amdgcn_rcpf((float)n); }
 __device__ __forceinline__ uint32_t div_exact(uint32_t s, uint32_t n, float rn) {
-    uint32_t q = (uint32_t)((float)s * rn);
-    q += ((q + 1u) * n <= s) ? 1u : 0u;
-    q -= (q * n > s) ? 1u : 0u;
+    uint32_t q = (uint32_t)((float)s * rn);  // q, n < 2^18: 24-bit products
+    q += (mul24(q + 1u, n) <= s) ? 1u : 0u;
+    q -= (mul24(q, n) > s) ? 1u : 0u;
     return q;
 }
 
@@ -65,10 +74,11 @@ __device__ __forceinline__ uint32_t div_exact(uint32_t s, uint32_t n, float rn) 
 // step).  Default reading: ((s / 3) * L) / 256, truncating, with
 // s / 3 == (s * 43691) >> 17 for s <= 765.  Paper form: floor(s * L / 765)
 // (equal to the listing's double expression for every s <= 765, L <= 256),
-// with floor(x / 765) == mulhi(x, 5614337) for x <= 765 * 256.
+// with floor(x / 765) == mulhi(x, 5614337) for x <= 765 * 256.  Every
+// operand is below 2^24 (s <= 765, L <= 256), so 24-bit products serve.
 __device__ __forceinline__ uint32_t level_of(uint32_t s, uint32_t L, bool paper) {
-    if (paper) return __umulhi(s * L, 5614337u);
-    return (((s * 43691u) >> 17) * L) >> 8;
+    if (paper) return mulhi24(mul24(s, L), 5614337u);
+    return mul24(mul24(s, 43691u) >> 17, L) >> 8;
 }
 
 // Image pointers as global-address-space pointers, so loads and stores are

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(64 * NV) void k_plain_column15(Job j) {
 template <int NW>
 __global__ __launch_bounds__(64) void k_batch_column15(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    batch_column15<NW, 1>(a, lds);
+    batch_column15<NW>(a, lds);
 }
 
 }  // namespace

@@ -70,7 +70,7 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
         # column histograms cost O(levels) per row (and 2r+1 reads for the
         # winning level): they can win at wide windows and few levels; one,
         # two or four wavefronts per strip
-        for waves, per_cu in ((1, 8), (2, 8), (4, 4), (4, 6), (4, 7), (4, 8)):
+        for waves, per_cu in ((1, 8), (2, 8), (4, 4), (4, 5), (4, 6), (4, 7), (4, 8)):
             out.append(B.Variant(0, waves, B.HIST_COLUMN, 64, per_cu))
     if not out or radius > 15:
         for per_cu in (1, 2, 4):
