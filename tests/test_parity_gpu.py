@@ -47,6 +47,16 @@ def test_fhd_sweep_exact(r, L):
     check(synth.fhd_image(), r, L)
 
 
+# the column layout's radius <= 15 form at full size, in the launch shapes
+# the tuner installs for the sweep (four wavefronts, eight per CU) and with
+# one and two wavefronts per strip; L = 32 takes the 11-word bucket
+@pytest.mark.parametrize("r,L,waves,per_cu", [(10, 20, 4, 8), (15, 20, 4, 8), (15, 20, 1, 8), (15, 20, 2, 8),
+                                              (12, 32, 4, 4), (7, 16, 4, 6)])
+def test_fhd_column15_exact(r, L, waves, per_cu):
+    print("fhd column15", r, L, waves, per_cu, flush=True)
+    check(synth.fhd_image(), r, L, variant=B.Variant(0, waves, B.HIST_COLUMN, 64, per_cu))
+
+
 def test_camera_exact():
     img = synth.camera_image()
     r, L = synth.CAMERA_RL
