@@ -117,6 +117,44 @@ def test_column15_paper_form_and_bands(waves):
         B.clear_variants()
 
 
+def test_batch_with_column15_shapes():
+    # jobs whose registered shape is the r <= 15 column form: a batch runs the
+    # paper form in the column layout's one-wavefront classes and the rest in
+    # the streamed classes; every output against the oracle, then two replays
+    # of a captured plan
+    torch = torch_mod()
+    cases = [((150, 90), 12, 20, 1), ((130, 70), 15, 33, 1), ((97, 60), 7, 9, 0), ((150, 90), 12, 20, 0),
+             ((64, 200), 10, 64, 1), ((200, 40), 15, 21, 0)]
+    items, want = [], []
+    try:
+        for i, ((w, h), r, L, paper) in enumerate(cases):
+            assert B.set_variant(r, L, B.Variant(0, 4, B.HIST_COLUMN, 64, 4)) == B.OK
+            img = image(w, h, seed=500 + i)
+            src, _ = to_device(img)
+            junk = np.random.default_rng(i).integers(0, 256, img.shape, dtype=np.uint8)
+            dst, _ = to_device(junk)
+            items.append(B.Item(src, dst, r, L, flags=B.FLAG_PAPER if paper else 0))
+            want.append(ref(img, r, L, paper=bool(paper), out=junk.copy()) if paper else ref(img, r, L))
+        B.batch(items)
+        torch.cuda.synchronize()
+        for (_, r, L, paper), it, wt in zip(cases, items, want):
+            mm = first_mismatch(from_device(it.dst), wt)
+            assert mm is None, ("batch", r, L, paper, mm)
+        plan = B.Plan(items)
+        for _ in range(2):
+            for (_, r, L, paper), it, wt in zip(cases, items, want):
+                if not paper:
+                    it.dst.zero_()
+            plan.launch()
+            torch.cuda.synchronize()
+            for (_, r, L, paper), it, wt in zip(cases, items, want):
+                mm = first_mismatch(from_device(it.dst), wt)
+                assert mm is None, ("plan", r, L, paper, mm)
+        plan.close()
+    finally:
+        B.clear_variants()
+
+
 def test_column_paper_form():
     torch = torch_mod()
     img = image(150, 90, seed=7)
