@@ -520,16 +520,32 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
     }
 }
 
-// One class of a batch in the column layout's radius <= 15 form (one
-// wavefront per strip).
-template <int NW>
+// One class of a batch in the column layout's radius <= 15 form, NV
+// wavefronts per strip.  With several, thread 0 takes the next tile and
+// hands it on through LDS; every tile passes barriers before its last
+// row, so no wavefront can take a new tile while another still reads the
+// previous handle.
+template <int NW, int NV>
 __device__ __forceinline__ void batch_column15(const BatchArgs& a, uint8_t* lds) {
-    for (;;) {
-        const int32_t t = next_tile_wave(a.counter);
-        if (t >= a.ntiles) break;
-        const int i = job_of(a, t);
-        const Job jb = a.jobs[i];
-        tile_column15<NW, 1>(jb, t - a.first_tile[i], lds);
+    if constexpr (NV == 1) {
+        for (;;) {
+            const int32_t t = next_tile_wave(a.counter);
+            if (t >= a.ntiles) break;
+            const int i = job_of(a, t);
+            const Job jb = a.jobs[i];
+            tile_column15<NW, 1>(jb, t - a.first_tile[i], lds);
+        }
+    } else {
+        __shared__ int32_t next;
+        for (;;) {
+            if (threadIdx.x == 0) next = (int32_t)atomicAdd(a.counter, 1u);
+            lds_barrier();
+            const int32_t t = __builtin_amdgcn_readfirstlane(next);
+            if (t >= a.ntiles) break;
+            const int i = job_of(a, t);
+            const Job jb = a.jobs[i];
+            tile_column15<NW, NV>(jb, t - a.first_tile[i], lds);
+        }
     }
 }
 

@@ -29,6 +29,9 @@ namespace {
 // latency hiding gains (64-image batch of radii 2-8: 74.5 GP/s with one
 // wavefront per strip from radius 8 on, 67.5 with four).
 constexpr int kBatchSplitMinRadius = 10;
+// Smallest radius whose jobs tuned to the column layout's several-wavefront
+// form run in its four-wavefront batch classes.
+constexpr int kBatchColumnMinRadius = 7;
 
 // Layout of a job inside a persistent launch: the streamed layouts as the
 // job's own choice (four wavefronts sharing a strip where that is its plain
@@ -44,11 +47,14 @@ int batch_shape(Job& j, int device) {
         v.per_cu = 8;
     }
     if (v.hist == OILPAINT_HIST_COLUMN && v.waves > 1) {
-        // batches have no several-wavefront column kernel: the streamed
-        // layout's classes (four wavefronts from kBatchSplitMinRadius), whose
-        // one-wavefront batch forms beat the column layout's; its
-        // one-wavefront form for the paper form, as below
-        if (!j.paper) {
+        // the column layout's four-wavefront classes from
+        // kBatchColumnMinRadius; below it the streamed layout's classes,
+        // whose one-wavefront batch forms beat the column layout's (its
+        // one-wavefront form for the paper form)
+        if (j.radius >= kBatchColumnMinRadius && j.radius <= kPackedMaxRadius && j.levels <= kColumn15MaxLevels) {
+            v.waves = 4;
+            v.rows = 0;
+        } else if (!j.paper) {
             v.hist = OILPAINT_HIST_STREAM;
             v.lanes = 64;
             v.rows = 0;
@@ -59,7 +65,7 @@ int batch_shape(Job& j, int device) {
             v.per_cu = 8;
         }
     }
-    if (!is_stream(v.hist) && v.waves > 1) {
+    if (!is_stream(v.hist) && v.hist != OILPAINT_HIST_COLUMN && v.waves > 1) {
         if (j.radius <= kPackedMaxRadius && j.levels <= 64 && !j.paper) {
             v.hist = OILPAINT_HIST_STREAM;
             v.lanes = 64;

@@ -208,15 +208,17 @@ extern const BatchKernel kBatchSplit8[8];
 extern const PlainKernel kColumn[kColumnChunks];
 extern const BatchKernel kBatchColumn[kColumnChunks];
 // Its radius <= 15 form, [column15_wave_index(waves)][column15_bucket(levels)];
-// the batch form has one wavefront per strip.
+// batch forms with one and with four wavefronts per strip.
 extern const PlainKernel kColumn15[3][kColumn15Buckets];
 extern const BatchKernel kBatchColumn15[kColumn15Buckets];
+extern const BatchKernel kBatchColumn15x4[kColumn15Buckets];
 
 // Kernel class of a batch job: 2 * radius + scan bucket (0: scan <= 32,
 // 1: scan <= 64) for the streamed layout, 32 + radius - 8 for its 8-byte
 // form, 40 + chunks - 1 for the column layout (radius above 15 or more than
-// 64 levels) and 49 + column15_bucket(levels) for its radius <= 15 form,
-// then the same for the
+// 64 levels), 49 + column15_bucket(levels) for its radius <= 15 form and
+// 53 + the same for that form with four wavefronts per strip, then the same
+// for the
 // four-wavefront streamed layouts (from kSplitClass: 2 * radius + bucket,
 // then 32 + radius - 8), and kGenericClass for every other job (generic
 // tile-staged and wide layouts, one kernel for all).  A batch launches one
@@ -225,7 +227,8 @@ extern const BatchKernel kBatchColumn15[kColumn15Buckets];
 constexpr int kStream8Class = 2 * (kPackedMaxRadius + 1);
 constexpr int kColumnClass = kStream8Class + 8;
 constexpr int kColumn15Class = kColumnClass + kColumnChunks;
-constexpr int kSplitClass = kColumn15Class + kColumn15Buckets;
+constexpr int kColumn15x4Class = kColumn15Class + kColumn15Buckets;
+constexpr int kSplitClass = kColumn15x4Class + kColumn15Buckets;
 constexpr int kGenericClass = kSplitClass + kStream8Class + 8;
 constexpr int kBatchClasses = kGenericClass + 1;
 inline int batch_class(const Job& j) {
@@ -234,12 +237,16 @@ inline int batch_class(const Job& j) {
         return split + 2 * j.radius + (j.scan <= 32 ? 0 : 1);
     if (j.hist == OILPAINT_HIST_STREAM8 && j.radius >= 8 && j.radius <= kPackedMaxRadius && j.scan <= 32)
         return split + kStream8Class + j.radius - 8;
-    if (j.hist == OILPAINT_HIST_COLUMN && column15(j)) return kColumn15Class + column15_bucket(j.levels);
+    if (j.hist == OILPAINT_HIST_COLUMN && column15(j))
+        return (j.waves == 4 ? kColumn15x4Class : kColumn15Class) + column15_bucket(j.levels);
     if (j.hist == OILPAINT_HIST_COLUMN && j.radius >= 0 && j.radius <= kColumnMaxRadius)
         return kColumnClass + column_chunks(j.radius) - 1;
     return kGenericClass;
 }
-inline int batch_waves(int cls) { return cls >= kSplitClass && cls < kGenericClass ? kSplitWaves : 1; }
+inline int batch_waves(int cls) {
+    if (cls >= kColumn15x4Class && cls < kColumn15x4Class + kColumn15Buckets) return 4;
+    return cls >= kSplitClass && cls < kGenericClass ? kSplitWaves : 1;
+}
 // Output rows of one tile: a run per wavefront, except in the streamed and
 // column layouts, whose wavefronts share one run.
 inline int runs_per_tile(int hist, int waves) { return is_stream(hist) || hist == OILPAINT_HIST_COLUMN ? 1 : waves; }

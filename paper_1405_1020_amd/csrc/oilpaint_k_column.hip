@@ -28,7 +28,13 @@ __global__ __launch_bounds__(64 * NV) void k_plain_column15(Job j) {
 template <int NW>
 __global__ __launch_bounds__(64) void k_batch_column15(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    batch_column15<NW>(a, lds);
+    batch_column15<NW, 1>(a, lds);
+}
+
+template <int NW>
+__global__ __launch_bounds__(256) void k_batch_column15x4(BatchArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    batch_column15<NW, 4>(a, lds);
 }
 
 }  // namespace
@@ -41,6 +47,8 @@ const PlainKernel kColumn15[3][kColumn15Buckets] = {
 // By [column15_bucket(levels)].
 const BatchKernel kBatchColumn15[kColumn15Buckets] = {k_batch_column15<3>, k_batch_column15<7>,
                                                       k_batch_column15<11>, k_batch_column15<22>};
+const BatchKernel kBatchColumn15x4[kColumn15Buckets] = {k_batch_column15x4<3>, k_batch_column15x4<7>,
+                                                        k_batch_column15x4<11>, k_batch_column15x4<22>};
 
 // By [chunks - 1].
 const PlainKernel kColumn[kColumnChunks] = {k_plain_column<1>, k_plain_column<2>, k_plain_column<3>,

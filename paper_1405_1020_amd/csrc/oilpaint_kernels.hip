@@ -100,6 +100,7 @@ BatchKernel batch_kernel(int cls) {
         const int r = c >> 1, b = c & 1;
         return r <= 7 ? kBatchSplit_lo[r][b] : kBatchSplit_hi[r - 8][b];
     }
+    if (cls >= kColumn15x4Class) return kBatchColumn15x4[cls - kColumn15x4Class];
     if (cls >= kColumn15Class) return kBatchColumn15[cls - kColumn15Class];
     if (cls >= kColumnClass) return kBatchColumn[cls - kColumnClass];
     if (cls >= kStream8Class) return kBatchStream8[cls - kStream8Class];
