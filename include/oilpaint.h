@@ -150,8 +150,9 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *                         <= 15 and at most 64 levels, 1, 2 or 4 wavefronts
  *                         sharing the strip (runs as in STREAM: waves x 64
  *                         threads work one run of `rows` output rows).
- *                         Batches and plans run such jobs in the streamed
- *                         layout (or, in the paper form, with waves = 1).
+ *                         Batches and plans run such jobs with 4 wavefronts
+ *                         from radius 7; below it in the streamed layout
+ *                         (with waves = 1 in the paper form).
  * ------------------------------------------------------------------------- */
 #define OILPAINT_HIST_PACKED  0
 #define OILPAINT_HIST_STREAM  1
