@@ -35,11 +35,14 @@ constexpr int kBatchColumnMinRadius = 7;
 
 // Layout of a job inside a persistent launch: the streamed layouts as the
 // job's own choice (four wavefronts sharing a strip where that is its plain
-// shape and the radius is at least kBatchSplitMinRadius, else one), every other layout with one computing wavefront per
-// workgroup (a tile-staged shape of several wavefronts becomes the streamed
-// layout when it applies); shrunk (wavefronts, then rows, then lanes) until
-// its on-chip footprint fits.  The rows are set afterwards for the whole
-// launch (shape_rows).
+// shape and the radius is at least kBatchSplitMinRadius, else one); the
+// column layout's radius <= 15 form with several wavefronts as four from
+// kBatchColumnMinRadius, else the streamed layout (one wavefront of the
+// column form in the paper form); every other layout with one computing
+// wavefront per workgroup (a tile-staged shape of several wavefronts becomes
+// the streamed layout when it applies); shrunk (wavefronts, then rows, then
+// lanes) until its on-chip footprint fits.  The rows are set afterwards for
+// the whole launch (shape_rows).
 int batch_shape(Job& j, int device) {
     oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
     if (is_stream(v.hist) && v.waves > 1 && j.radius < kBatchSplitMinRadius) {
