@@ -294,22 +294,33 @@ typedef struct oilpaint_queue oilpaint_queue;
  * its own non-blocking stream on the current device. */
 int oilpaint_queue_create(int capacity, int64_t step_pixels, oilpaint_queue **out);
 /* Append one request.  *ticket receives its id.  ERR_FULL if `capacity`
- * requests are already held.  The descriptor is copied; the images must stay
- * valid until the request is reported done. */
+ * requests are already held; a descriptor error (as oilpaint_run) is
+ * returned at once and the request is not queued.  The descriptor is
+ * copied; the images must stay valid until the request is reported
+ * complete.  A launch holding rows of a request that fails to be enqueued
+ * fails that request: it is reported complete with the error as its status
+ * (poll, completed), once no kernel of it can still write its dst, and the
+ * queue goes on with the others. */
 int oilpaint_queue_push(oilpaint_queue *q, const oilpaint_desc *desc, uint64_t *ticket);
 /* Make progress without blocking; returns the number of launches enqueued. */
 int oilpaint_queue_step(oilpaint_queue *q);
 /* 1 if the request's output is complete (its bytes are in dst and visible
- * to later work on any stream), 0 if not yet, ERR_ARG for an unknown ticket.
- * Once poll has returned 1 for a ticket the queue forgets it. */
+ * to later work on any stream), 0 if not yet, the request's error code if it
+ * failed (see push), ERR_ARG for an unknown ticket.  Once poll has returned
+ * 1 or a request's error for a ticket the queue forgets it. */
 int oilpaint_queue_poll(oilpaint_queue *q, uint64_t ticket);
 /* Tickets of requests completed since they were last reported (by poll or
  * by this call), in completion order: at most `max` are written to
- * `tickets`, and those are forgotten.  Returns the number written, or an
- * error code.  One call replaces a poll per request. */
-int oilpaint_queue_completed(oilpaint_queue *q, uint64_t *tickets, int max);
-/* Block until every pushed request is complete. */
+ * `tickets`, and those are forgotten.  If `status` is not NULL, status[i]
+ * receives OILPAINT_OK or the error of a failed request.  Returns the number
+ * written, or an error code.  One call replaces a poll per request. */
+int oilpaint_queue_completed(oilpaint_queue *q, uint64_t *tickets, int *status, int max);
+/* Block until every pushed request is complete (or failed). */
 int oilpaint_queue_drain(oilpaint_queue *q);
+/* Failure injection for tests of the error path: the queue's next `n`
+ * launches are treated as failed before anything is enqueued (their
+ * requests fail with ERR_HIP).  No kernel runs for them. */
+int oilpaint_queue_fail_next(oilpaint_queue *q, int n);
 /* The queue's control stream (hipStream_t as void*), which carries the
  * uploads and counter resets; the filter kernels run on side streams.  Use
  * poll or completed to learn that a request's output is ready. */

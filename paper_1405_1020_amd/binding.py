@@ -101,7 +101,9 @@ _SIGS = {
                             ctypes.c_int),
     "oilpaint_queue_step": ([ctypes.c_void_p], ctypes.c_int),
     "oilpaint_queue_poll": ([ctypes.c_void_p, ctypes.c_uint64], ctypes.c_int),
-    "oilpaint_queue_completed": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int], ctypes.c_int),
+    "oilpaint_queue_completed": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int),
+                                  ctypes.c_int], ctypes.c_int),
+    "oilpaint_queue_fail_next": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "oilpaint_queue_drain": ([ctypes.c_void_p], ctypes.c_int),
     "oilpaint_queue_stream": ([ctypes.c_void_p], ctypes.c_void_p),
     "oilpaint_queue_destroy": ([ctypes.c_void_p], ctypes.c_int),
@@ -406,13 +408,24 @@ class Queue:
         return st == 1
 
     def completed(self, max_tickets: int = 4096) -> list[int]:
-        """Tickets completed since last reported (each reported once)."""
+        """Tickets completed since last reported (each reported once),
+        failed requests included (see completed_status)."""
+        return [t for t, _ in self.completed_status(max_tickets)]
+
+    def completed_status(self, max_tickets: int = 4096) -> list[tuple[int, int]]:
+        """(ticket, status) of the requests completed since last reported:
+        status OK, or the error code of a request whose launch failed."""
         if getattr(self, "_buf", None) is None or len(self._buf) < max_tickets:
             self._buf = (ctypes.c_uint64 * max_tickets)()
-        n = lib().oilpaint_queue_completed(self._h, self._buf, max_tickets)
+            self._sbuf = (ctypes.c_int * max_tickets)()
+        n = lib().oilpaint_queue_completed(self._h, self._buf, self._sbuf, max_tickets)
         if n < 0:
             raise OilpaintError(n, "oilpaint_queue_completed")
-        return list(self._buf[:n])
+        return list(zip(self._buf[:n], self._sbuf[:n]))
+
+    def fail_next(self, n: int):
+        """Test hook: the next n launches fail before anything is enqueued."""
+        _check(lib().oilpaint_queue_fail_next(self._h, n), "oilpaint_queue_fail_next")
 
     def drain(self):
         _check(lib().oilpaint_queue_drain(self._h), "oilpaint_queue_drain")

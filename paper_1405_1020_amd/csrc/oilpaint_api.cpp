@@ -261,6 +261,10 @@ int make_job(const oilpaint_desc& d, const oilpaint_variant* v, int device, Job&
     j.row_end = re;
     j.paper = (d.flags & OILPAINT_FLAG_PAPER) ? 1 : 0;
     if (j.radius > kWideMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
+    // The listing's form writes only [r, W-r) x [r, H-r) with the radius as
+    // given: nothing at all when 2r >= W or 2r >= H (clamping the radius
+    // first would open an interior there).
+    if (j.paper && (2 * (int64_t)d.radius >= d.width || 2 * (int64_t)d.radius >= d.height)) empty = true;
     if (empty) return OILPAINT_OK;
     const oilpaint_variant use =
         v ? *v : choose_variant(d.width, d.height, j.radius, d.levels, j.paper != 0, device);

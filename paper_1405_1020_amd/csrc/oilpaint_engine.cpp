@@ -490,6 +490,7 @@ struct QueueReq {
     int launches_left = 0;
     bool all_launched = false;
     bool done = false;
+    int status = OILPAINT_OK;  // an error code once a launch of its rows failed
 };
 
 struct Inflight {
@@ -514,6 +515,7 @@ struct oilpaint_queue {
     size_t held = 0;  // requests not yet complete
     unsigned next_side = 0;  // side stream of the next single-band launch
     bool last_direct = false;  // the last launch was one large request alone
+    int fail_next = 0;  // test hook: launches still to be treated as failed
 };
 
 namespace {
@@ -587,6 +589,28 @@ int launch_direct(oilpaint_queue* q, uint64_t t, int rb, int re, hipStream_t* en
     return OILPAINT_OK;
 }
 
+// A launch that could not be enqueued, or whose completion cannot be
+// tracked, fails the requests that had rows in it: none of their rows is
+// launched again, and each is complete, with `st` as its status, as soon as
+// the launches holding its earlier bands have retired (their kernels may
+// still write its dst until then).
+void fail_launch(oilpaint_queue* q, const std::vector<uint64_t>& tickets, int st) {
+    for (uint64_t t : tickets) {
+        QueueReq& r = q->reqs[t];
+        r.status = st;
+        r.all_launched = true;
+        if (--r.launches_left == 0 && !r.done) {
+            r.done = true;
+            --q->held;
+            q->finished.push_back(t);
+        }
+    }
+    std::deque<uint64_t> still;
+    for (uint64_t t : q->waiting)
+        if (q->reqs[t].status == OILPAINT_OK) still.push_back(t);
+    q->waiting.swap(still);
+}
+
 // One launch of waiting work (returns 1, 0 if there was none, or an error):
 //   * a lone request with nothing in flight: the whole request, plain;
 //   * a large request (kDirectPixels): the whole request, plain -- at most
@@ -594,6 +618,8 @@ int launch_direct(oilpaint_queue* q, uint64_t t, int rb, int re, hipStream_t* en
 //     starves the other;
 //   * otherwise every waiting small request gets an equal share of the
 //     launch's pixels (at least one run of min_run_rows), one batch launch.
+// A launch that fails fails its requests (fail_launch) and still counts as a
+// step: the queue goes on with the other requests.
 int launch_step(oilpaint_queue* q) {
     if (q->waiting.empty()) return 0;
     // The work goes to side streams only, so that nothing on the queue's own
@@ -620,7 +646,12 @@ int launch_step(oilpaint_queue* q) {
     if (lone || (big != q->waiting.end() && (!q->last_direct || !any_small))) {
         const uint64_t t = lone ? q->waiting.front() : *big;
         QueueReq& r = q->reqs[t];
-        st = launch_direct(q, t, r.next_row, r.job.row_end, &ends[0]);
+        if (q->fail_next > 0) {
+            --q->fail_next;
+            st = OILPAINT_ERR_HIP;
+        } else {
+            st = launch_direct(q, t, r.next_row, r.job.row_end, &ends[0]);
+        }
         nends = 1;
         r.next_row = r.job.row_end;
         r.launches_left += 1;
@@ -669,7 +700,10 @@ int launch_step(oilpaint_queue* q) {
         }
         q->waiting.swap(still);
         if (jobs.empty()) return 0;
-        if (jobs.size() == 1) {
+        if (q->fail_next > 0) {
+            --q->fail_next;
+            st = OILPAINT_ERR_HIP;
+        } else if (jobs.size() == 1) {
             st = launch_direct(q, tickets[0], jobs[0].row_begin, jobs[0].row_end, &ends[0]);
             nends = 1;
         } else {
@@ -679,18 +713,32 @@ int launch_step(oilpaint_queue* q) {
             st = enqueue_layout(L, q->device, *q->ring, *q->branches, q->stream, false, ends, &nends);
         }
     }
-    if (st != OILPAINT_OK) return st;
+    if (st != OILPAINT_OK) {
+        fail_launch(q, tickets, st);
+        return 1;
+    }
     Inflight f;
     for (int i = 0; i < nends; ++i) {
-        hipEvent_t ev;
+        hipEvent_t ev = nullptr;
         if (!q->free_events.empty()) {
             ev = q->free_events.back();
             q->free_events.pop_back();
-        } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-            return OILPAINT_ERR_HIP;
+        } else if (note_hip("hipEventCreate", hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+            ev = nullptr;
+        }
+        if (ev && note_hip("hipEventRecord", hipEventRecord(ev, ends[i])) != hipSuccess) {
+            q->free_events.push_back(ev);
+            ev = nullptr;
+        }
+        if (!ev) {
+            // the launch is enqueued but cannot be tracked: wait for it, then
+            // fail its requests
+            for (int k = 0; k < nends; ++k) (void)hipStreamSynchronize(ends[k]);
+            for (hipEvent_t e : f.evs) q->free_events.push_back(e);
+            fail_launch(q, tickets, OILPAINT_ERR_HIP);
+            return 1;
         }
         f.evs.push_back(ev);
-        if (hipEventRecord(ev, ends[i]) != hipSuccess) return OILPAINT_ERR_HIP;
     }
     f.tickets = tickets;
     q->inflight.push_back(f);
@@ -834,8 +882,10 @@ int oilpaint_queue_push(oilpaint_queue* q, const oilpaint_desc* desc, uint64_t* 
         q->finished.push_back(t);
     }
     *ticket = t;
-    st = queue_progress(q);
-    return st < 0 ? st : OILPAINT_OK;
+    // The request is accepted: an error of the progress step below recurs
+    // on the next step, poll or completed call, which reports it.
+    (void)queue_progress(q);
+    return OILPAINT_OK;
 }
 
 int oilpaint_queue_step(oilpaint_queue* q) {
@@ -852,7 +902,8 @@ int oilpaint_queue_poll(oilpaint_queue* q, uint64_t ticket) {
         if (st < 0) return st;
         if (!it->second.done) return 0;
     }
-    // reported complete: the ticket is forgotten
+    // reported complete (or failed): the ticket is forgotten
+    const int status = it->second.status;
     q->reqs.erase(it);
     if (q->finished.size() > 2 * (size_t)q->capacity + 1024) {
         std::deque<uint64_t> keep;
@@ -860,10 +911,10 @@ int oilpaint_queue_poll(oilpaint_queue* q, uint64_t ticket) {
             if (q->reqs.count(t)) keep.push_back(t);
         q->finished.swap(keep);
     }
-    return 1;
+    return status != OILPAINT_OK ? status : 1;
 }
 
-int oilpaint_queue_completed(oilpaint_queue* q, uint64_t* tickets, int max) {
+int oilpaint_queue_completed(oilpaint_queue* q, uint64_t* tickets, int* status, int max) {
     if (!q || (!tickets && max > 0)) return OILPAINT_ERR_NULL;
     if (max < 0) return OILPAINT_ERR_ARG;
     const int st = queue_progress(q);
@@ -874,6 +925,7 @@ int oilpaint_queue_completed(oilpaint_queue* q, uint64_t* tickets, int max) {
         q->finished.pop_front();
         auto it = q->reqs.find(t);
         if (it == q->reqs.end()) continue;  // already reported by poll
+        if (status) status[n] = it->second.status;
         tickets[n++] = t;
         q->reqs.erase(it);
     }
@@ -892,6 +944,13 @@ int oilpaint_queue_drain(oilpaint_queue* q) {
 }
 
 void* oilpaint_queue_stream(oilpaint_queue* q) { return q ? (void*)q->stream : nullptr; }
+
+int oilpaint_queue_fail_next(oilpaint_queue* q, int n) {
+    if (!q) return OILPAINT_ERR_NULL;
+    if (n < 0) return OILPAINT_ERR_ARG;
+    q->fail_next = n;
+    return OILPAINT_OK;
+}
 
 int oilpaint_queue_destroy(oilpaint_queue* q) {
     if (!q) return OILPAINT_OK;

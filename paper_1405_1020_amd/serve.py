@@ -16,10 +16,12 @@ A `Server` holds:
     launch per request, in arrival order, on one stream.
   * per-request timestamps: latency = completion seen by the host - arrival.
 
-Executors only need submit(req) -> handle and poll(handle) -> bool, so the
-scheduling is testable on the CPU with a fake executor.  An executor may also
-offer collect() -> set of handles completed since the last call; the server
-then makes one such call per step instead of a poll per running request.
+Executors only need submit(req) -> handle and poll(handle) -> bool (raising
+for a failed request), so the scheduling is testable on the CPU with a fake
+executor.  An executor may also offer collect() -> the handles completed
+since the last call (a set, or a dict handle -> error message, empty for
+success); the server then makes one such call per step instead of a poll per
+running request.
 """
 from __future__ import annotations
 
@@ -155,14 +157,20 @@ class Server:
             except Exception:  # fall back to polling: failures stay per request
                 completed = None
         for req in self.running:
+            err = ""
             try:
-                done = (req.handle in completed) if completed is not None else self.ex.poll(req.handle)
+                if completed is not None:
+                    done = req.handle in completed
+                    if done and isinstance(completed, dict):
+                        err = completed[req.handle] or ""
+                else:
+                    done = self.ex.poll(req.handle)
             except Exception as e:
                 self._finish(req, failed=str(e))
                 n += 1
                 continue
             if done:
-                self._finish(req)
+                self._finish(req, failed=err)
                 n += 1
             else:
                 still.append(req)
@@ -237,11 +245,14 @@ class QueueExecutor:
     def poll(self, ticket) -> bool:
         return self.q.poll(ticket)
 
-    def collect(self) -> set:
-        done = set()
+    def collect(self) -> dict:
+        """{ticket: error message or ""} of the requests completed since the
+        last call."""
+        done = {}
         while True:
-            got = self.q.completed()
-            done.update(got)
+            got = self.q.completed_status()
+            for t, st in got:
+                done[t] = "" if st == self.B.OK else "%s (%d)" % (self.B.strerror(st), st)
             if len(got) < 4096:
                 return done
 

@@ -83,30 +83,42 @@ def test_row_bands_and_paper_flag():
         assert first_mismatch(from_device(dst2), want2) is None, L2
 
 
-def test_batch_equals_plain_on_full_batch_workload():
-    # the 64-image workload in the launch configuration the benchmark times:
-    # every byte against the plain kernel, sampled pixels against the oracle
+def test_full_batch_workload_every_byte():
+    """The 64-image workload (W ~ U{320..4096}, H ~ U{240..3072}, r ~ U{2,3,5,8},
+    L ~ U{16,20,32}) in the launch configurations the benchmark times: a
+    captured plan replayed twice (junk written into the outputs between the
+    replays) and one oilpaint_batch call.  Every byte of every output is
+    compared with the oracle (the Section 4 definition, clipped window), and
+    with 64 plain launches of the same images."""
     torch = torch_mod()
     specs = synth.batch_items()
-    rng = np.random.default_rng(1)
-    items, plain, imgs = [], [], []
-    for k, it in enumerate(specs):
-        src = synth.batch_image(it)
-        imgs.append(src)
-        d1 = torch.empty_like(src)
-        d2 = torch.empty_like(src)
-        B.oilpaint_async(src, d1, it.radius, it.levels)
-        items.append(B.Item(src, d2, it.radius, it.levels))
-        plain.append(d1)
-    B.batch(items)
+    srcs = [synth.batch_image(it) for it in specs]
+    d_plan = [torch.empty_like(s) for s in srcs]
+    d_batch = [torch.empty_like(s) for s in srcs]
+    d_plain = [torch.empty_like(s) for s in srcs]
+    for s, d, it in zip(srcs, d_plain, specs):
+        B.oilpaint_async(s, d, it.radius, it.levels)
+    plan = B.Plan([B.Item(s, d, it.radius, it.levels) for s, d, it in zip(srcs, d_plan, specs)])
+    plan.launch()
     torch.cuda.synchronize()
-    for k, (it, d1, src, spec) in enumerate(zip(items, plain, imgs, specs)):
-        assert torch.equal(it.dst, d1), k
-        a = it.dst.cpu().numpy()
+    first = [d.clone() for d in d_plan]
+    for d in d_plan:
+        d.fill_(0xA5)
+    torch.cuda.synchronize()
+    plan.launch()
+    B.batch([B.Item(s, d, it.radius, it.levels) for s, d, it in zip(srcs, d_batch, specs)])
+    torch.cuda.synchronize()
+    plan.close()
+    pixels = 0
+    for k, (src, spec) in enumerate(zip(srcs, specs)):
+        assert torch.equal(d_plan[k], first[k]), ("replay", k)
         img = src.cpu().numpy()
-        h, w, _ = img.shape
-        for x, y in [(0, 0), (w - 1, h - 1)] + [(int(rng.integers(0, w)), int(rng.integers(0, h))) for _ in range(6)]:
-            assert tuple(a[y, x]) == tuple(ref_pixel(img, x, y, spec.radius, spec.levels)), (k, x, y)
+        want = ref(img, spec.radius, spec.levels)
+        for name, d in (("plan", d_plan[k]), ("batch", d_batch[k]), ("plain", d_plain[k])):
+            mm = first_mismatch(from_device(d), want)
+            assert mm is None, (name, k, img.shape, spec.radius, spec.levels, mm)
+        pixels += img.shape[0] * img.shape[1]
+    assert pixels > 150_000_000  # the whole workload, about 234 MP
 
 
 def test_plan_graph_replays():
@@ -245,3 +257,42 @@ def test_paper_flag_in_four_wavefront_classes():
     torch.cuda.synchronize()
     for (img, r, L), it, w in zip(cases, items, want):
         assert first_mismatch(from_device(it.dst), w) is None, (img.shape, r, L)
+
+
+def test_queue_failed_launch_fails_only_its_requests():
+    """A launch that fails (forced from the host, before anything is
+    enqueued) fails the requests with rows in it: each is reported complete
+    with the error, its dst is untouched and its slot is free again; the
+    queue goes on, and the other requests equal the oracle."""
+    torch = torch_mod()
+    cases = small_batch(9, seed=13)
+    items, keep = device_items(cases)
+    before = [from_device(it.dst) for it in items]
+    q = B.Queue(capacity=8, step_pixels=20000)
+    # a lone request with nothing in flight goes out at once: its launch fails
+    q.fail_next(1)
+    t0 = q.push(items[0])
+    got = []
+    while not got:
+        got = q.completed_status()
+    assert got == [(t0, B.ERR_HIP)]
+    # the same through poll
+    q.fail_next(1)
+    t1 = q.push(items[1])
+    with pytest.raises(B.OilpaintError) as e:
+        while not q.poll(t1):
+            pass
+    assert e.value.status == B.ERR_HIP
+    # both slots are free again: eight more requests fit the capacity of 8
+    rest = {q.push(it): i for i, it in enumerate(items[1:], start=1)}
+    assert len(rest) == 8
+    done = []
+    while len(done) < len(rest):
+        done += q.completed_status()
+    assert sorted(t for t, _ in done) == sorted(rest) and all(st == B.OK for _, st in done)
+    q.drain()
+    torch.cuda.synchronize()
+    assert np.array_equal(from_device(items[0].dst), before[0])
+    for (img, r, L, _), it in list(zip(cases, items))[1:]:
+        assert first_mismatch(from_device(it.dst), ref(img, r, L)) is None, (img.shape, r, L)
+    q.close()

@@ -252,3 +252,21 @@ def test_row_bands_four_wavefronts():
             B.clear_variants()
         mm = first_mismatch(from_device(dst), want)
         assert mm is None, (r, L, hist, mm)
+
+
+def test_paper_form_tiny_images():
+    # the listing's form filters [r, W-r) x [r, H-r) with the radius as given,
+    # so on images with 2r >= W or 2r >= H nothing is written (the clipped
+    # form clamps the radius to the image instead)
+    torch = torch_mod()
+    for w, h in ((1, 1), (2, 2), (1, 5), (3, 2), (5, 5), (7, 3)):
+        img = synth.make_image(w, h, seed=w * 10 + h, n_blobs=2, sigma=(1, 3))
+        for r in (1, 2, 3):
+            junk = np.random.default_rng(w * 100 + h * 10 + r).integers(0, 256, size=img.shape, dtype=np.uint8)
+            src, _ = to_device(img, pad=1, seed=3)
+            dst, _ = to_device(junk, pad=1, seed=4)
+            B.run(B.Item(src, dst, r, 20, flags=B.FLAG_PAPER))
+            torch.cuda.synchronize()
+            want = ref(img, r, 20, paper=True, out=junk.copy())
+            mm = first_mismatch(from_device(dst), want)
+            assert mm is None, (w, h, r, mm)

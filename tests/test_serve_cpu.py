@@ -194,6 +194,39 @@ def test_executor_failures_are_isolated():
             assert np.array_equal(q.dst, oracle.oilpaint_ref(q.src, q.radius, q.levels))
 
 
+class FakeStatusCollectExecutor(FakeCollectExecutor):
+    """collect() returns {ticket: error message}, as QueueExecutor does: the
+    requests in `fail` are reported complete with an error."""
+
+    def __init__(self, fail=(), polls=2):
+        super().__init__(polls=polls)
+        self.fail = set(fail)
+
+    def collect(self):
+        done = FakeCollectExecutor.collect(self)
+        return {t: ("launch failed" if self.rid_of[t] in self.fail else "") for t in done}
+
+    def submit(self, req):
+        t = super().submit(req)
+        self.rid_of = getattr(self, "rid_of", {})
+        self.rid_of[t] = req.rid
+        return t
+
+
+def test_collect_status_fails_only_the_failed_requests():
+    rs = reqs([(10, 7)] * 5)
+    ex = FakeStatusCollectExecutor(fail={1, 3})
+    freed = []
+    s = serve.Server(ex, budget_bytes=1 << 30, allocate=np_alloc, free=lambda q: freed.append(q.rid),
+                     clock=FakeClock())
+    s.start()
+    drain(s, rs)
+    st = s.stats()
+    assert st["completed"] == 3 and st["failed"] == 2
+    assert [q.status for q in rs] == ["done", "failed", "done", "failed", "done"]
+    assert rs[1].error == "launch failed" and s.used == 0 and sorted(freed) == list(range(5))
+
+
 def test_latency_accounting_open_loop():
     arrivals = [0.0, 0.05, 0.05, 0.2]
     rs = reqs([(6, 6)] * 4, arrivals=arrivals)
