@@ -8,6 +8,8 @@ benchmark's CPU-baseline leg may import this package.  The GPU library
 ctypes on numpy arrays; `brute` is an independent Python brute force for tiny
 images.  `median_ref` wraps median_ref.c, the windowed median filter (the
 second filter of the same class); `brute.brute_median` is its brute force.
+`jpeg_ref` (imported as `oracle.jpeg_ref`) is the plain baseline JPEG codec of
+ITU-T T.81 and JFIF for the decode and encode steps either side of the filter.
 """
 from __future__ import annotations
 
