@@ -236,6 +236,24 @@ int oilpaint_run(const oilpaint_desc *desc, void *stream);
  * array is copied; it may be reused when the call returns. */
 int oilpaint_batch(const oilpaint_desc *descs, int n, void *stream, int *bad_index);
 
+/* oilpaint_batch for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same validation, kernels and results as oilpaint_batch, but the batch's
+ * argument block (a counter per kernel class, the classes' tile prefix sums
+ * and the job descriptors: 256 + 16 per class + 4 (n + classes) + 104 n bytes
+ * or so) lives in a static device array of OILPAINT_NOALLOC_SCRATCH_BYTES
+ * that each GPU the library runs on holds until the process ends, and the
+ * call makes no hipMalloc, hipFree or other allocating call (its first call
+ * on a device takes the array's address there and creates the side streams
+ * the classes run on).  A batch whose block does not fit returns ERR_ARG
+ * (text in oilpaint_last_error) and enqueues nothing.  The block is
+ * uploaded from pageable host memory, so the call returns once the upload
+ * is done.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (on different streams, or from several threads without
+ * ordering) race; calls on one stream are ordered. */
+#define OILPAINT_NOALLOC_SCRATCH_BYTES (1 << 20)
+int oilpaint_batch_noalloc(const oilpaint_desc *descs, int n, void *stream, int *bad_index);
+
 /* A batch plan: the descriptors are validated and laid out once (tile queues
  * in device memory, ordered by estimated cost) and the launch -- a counter
  * reset kernel, then the classes' persistent kernels as parallel graph

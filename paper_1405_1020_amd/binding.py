@@ -90,6 +90,8 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "oilpaint_batch": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
                        ctypes.c_int),
+    "oilpaint_batch_noalloc": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
+                               ctypes.c_int),
     "oilpaint_plan_create": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p,
                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "oilpaint_plan_launch": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -336,6 +338,16 @@ def batch(items, stream=None) -> None:
     st = lib().oilpaint_batch(arr, len(items), _stream_ptr(stream), ctypes.byref(bad))
     if st != OK:
         raise OilpaintError(st, "oilpaint_batch (item %d)" % bad.value)
+
+
+def batch_noalloc(items, stream=None) -> None:
+    """oilpaint_batch_noalloc: oilpaint_batch with its argument block in the
+    library's static device array (no device allocation)."""
+    arr = _desc_array(items)
+    bad = ctypes.c_int(-1)
+    st = lib().oilpaint_batch_noalloc(arr, len(items), _stream_ptr(stream), ctypes.byref(bad))
+    if st != OK:
+        raise OilpaintError(st, "oilpaint_batch_noalloc (item %d)" % bad.value)
 
 
 class Plan:

@@ -15,6 +15,8 @@ namespace {
 thread_local char g_last_error[256] = "";
 }
 
+void note_error(const char* text) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", text); }
+
 hipError_t note_hip(const char* where, hipError_t e) {
     if (e != hipSuccess) {
         std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);

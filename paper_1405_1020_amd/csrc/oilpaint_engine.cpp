@@ -4,6 +4,7 @@
 // queue that packs waiting work into successive persistent launches
 // (oilpaint_queue_*).
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -773,6 +774,82 @@ int oilpaint_batch(const oilpaint_desc* descs, int n, void* stream, int* bad_ind
     std::lock_guard<std::mutex> lock(ring_mutex(device));
     return enqueue_layout(L, device, device_ring(device), device_branches(device), (hipStream_t)stream, true,
                           nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Batches without allocation: the argument block (class counters, tile
+// prefix sums, job descriptors) lives in a file-scope device array instead
+// of the library's argument ring.  Each GPU holds its own copy of the array
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace oilpaint_impl {
+namespace {
+
+static __device__ __align__(256) uint8_t scratch[OILPAINT_NOALLOC_SCRATCH_BYTES];
+
+// Per-device set-up, made once per device with that device current: the
+// array's address on that device, and a host staging block of the same size
+// (pageable, so that an upload from it completes before hipMemcpyAsync
+// returns and the block may be refilled at once).
+struct NoAllocDevice {
+    uint8_t* dev = nullptr;
+    std::vector<uint8_t> host;
+};
+
+NoAllocDevice* noalloc_device(int device) {
+    static std::mutex mu;
+    static std::map<int, NoAllocDevice> m;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = m.find(device);
+    if (it != m.end()) return &it->second;
+    void* p = nullptr;
+    if (note_hip("hipGetSymbolAddress", hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess || !p)
+        return nullptr;
+    NoAllocDevice& d = m[device];
+    d.dev = static_cast<uint8_t*>(p);
+    d.host.assign(OILPAINT_NOALLOC_SCRATCH_BYTES, 0);
+    if (!device_branches(device).ensure(kMaxBranches - 1)) {
+        (void)note_hip("branch streams", hipGetLastError());
+        m.erase(device);
+        return nullptr;
+    }
+    return &d;
+}
+
+}  // namespace
+}  // namespace oilpaint_impl
+
+extern "C" {
+
+int oilpaint_batch_noalloc(const oilpaint_desc* descs, int n, void* stream, int* bad_index) {
+    int device = 0;
+    if (note_hip("hipGetDevice", hipGetDevice(&device)) != hipSuccess) return OILPAINT_ERR_HIP;
+    std::vector<Job> jobs;
+    int st = collect_jobs(descs, n, device, jobs, bad_index);
+    if (st != OILPAINT_OK || jobs.empty()) return st;
+    Layout L;
+    build_layout(jobs, L);
+    if (L.bytes > (size_t)OILPAINT_NOALLOC_SCRATCH_BYTES) {
+        char text[160];
+        std::snprintf(text, sizeof(text),
+                      "oilpaint_batch_noalloc: argument block of %zu bytes exceeds the %d-byte static scratch",
+                      L.bytes, OILPAINT_NOALLOC_SCRATCH_BYTES);
+        note_error(text);
+        return OILPAINT_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lock(ring_mutex(device));
+    NoAllocDevice* d = noalloc_device(device);
+    if (!d) return OILPAINT_ERR_HIP;
+    pack_args(L, d->host.data());
+    const hipStream_t s = (hipStream_t)stream;
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(d->dev, d->host.data(), L.bytes, hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return OILPAINT_ERR_HIP;
+    // the counters are cleared by enqueue_classes' reset kernel
+    return enqueue_classes(L, d->dev, device, device_branches(device), s, true, nullptr, nullptr, nullptr);
 }
 
 int oilpaint_plan_create(const oilpaint_desc* descs, int n, void* stream, oilpaint_plan** out, int* bad_index) {

@@ -288,6 +288,8 @@ hipError_t launch_fill(uint8_t* p, size_t n, int width, hipStream_t stream);
 // Record a failed HIP call (text readable through oilpaint_last_error) and
 // clear the runtime's sticky last-error state.  Returns `e`.
 hipError_t note_hip(const char* where, hipError_t e);
+// Record an error text (readable through oilpaint_last_error).
+void note_error(const char* text);
 
 // Device facts, cached per device.
 struct DeviceInfo {
