@@ -345,6 +345,95 @@ int oilpaint_queue_fail_next(oilpaint_queue *q, int n);
 void *oilpaint_queue_stream(oilpaint_queue *q);
 int oilpaint_queue_destroy(oilpaint_queue *q);
 
+/* ---------------------------------------------------------------------------
+ * JPEG decode and encode around the filter.  The paper's program reads a JPEG
+ * file, filters its pixels and writes a JPEG file, timing decode, filter and
+ * encode apart (Section 3: its decoder, its encoder and the file driver);
+ * here the per-sample steps run on the GPU, so a decoded image is filtered
+ * where it lies and the filtered image is encoded from there.
+ *
+ * Format: baseline sequential DCT-based JPEG (ITU-T T.81 | ISO/IEC 10918-1;
+ * SOF0 or SOF1, Huffman coding, 8-bit samples and 8-bit quantization tables),
+ * one or three components with sampling factors 1..4, restart intervals,
+ * interleaved or per-component scans, in JFIF's YCbCr colour space.
+ * Progressive, lossless, hierarchical and arithmetic-coded files return
+ * ERR_UNSUPPORTED; malformed ones ERR_ARG.
+ *
+ * What is computed (the same definitions as the test oracle):
+ *   decode: entropy decoding on the host (T.81 F.2.2); on the GPU,
+ *     dequantization (A.3.5) and the 8 x 8 inverse DCT (A.3.3) in fp32, each
+ *     sample + 128 rounded half up and clamped to [0, 255]; each chroma sample
+ *     replicated over the Hmax/H x Vmax/V pixels it covers; JFIF YCbCr -> RGB
+ *     (R = Y + 1.402 Cr', G = Y - 0.344136 Cb' - 0.714136 Cr', B = Y + 1.772
+ *     Cb', Cb' = Cb - 128, Cr' = Cr - 128) evaluated exactly in integers,
+ *     rounded half up, clamped; one component gives R = G = B = Y.
+ *   encode: the image extended to whole MCUs by repeating its last column and
+ *     row; JFIF RGB -> YCbCr exactly in integers, rounded half up; each chroma
+ *     sample the mean of the pixels it covers, rounded half up; the 8 x 8
+ *     forward DCT (A.3.3) of sample - 128 in fp32 and quantization to the
+ *     nearest integer, halves away from zero (A.3.4), on the GPU; entropy
+ *     coding on the host with Huffman tables fitted to the image (K.2).
+ *     Quantization tables: T.81 Tables K.1 and K.2 scaled by quality
+ *     (1..100; 50 keeps them, q < 50 scales by 5000/q %, q >= 50 by 200-2q %,
+ *     each entry rounded and kept in [1, 255]).  Subsampling 0, 1, 2: 4:4:4,
+ *     4:2:2, 4:2:0 (Y sampled 1x1, 2x1, 2x2; Cb and Cr 1x1).
+ *   An fp32 inverse or forward DCT value that lies within about 2^-18 x the
+ *   block's sum of |coefficients| (or |samples - 128|) of a rounding
+ *   boundary may round the other way than the exact transform would.
+ *
+ * Coefficient layout (host buffers below and the device buffers inside):
+ * int16, natural (row-major) order, 64 per block; component c's block (bx,
+ * by) of its MCU-padded grid at (first_block[c] + by * blocks_w[c] + bx) x 64.
+ * ------------------------------------------------------------------------- */
+typedef struct oilpaint_jpeg_info {
+    int32_t width, height, components;
+    int32_t h_samp[3], v_samp[3];          /* sampling factors */
+    int32_t comp_width[3], comp_height[3]; /* samples of each component */
+    int32_t blocks_w[3], blocks_h[3];      /* its MCU-padded block grid */
+    int32_t first_block[3];                /* its first block in the coefficient layout */
+    int64_t blocks;                        /* blocks of all components */
+    int32_t restart_interval, scans;
+} oilpaint_jpeg_info;
+
+/* Parse a JPEG file's headers (host memory; pure host work). */
+int oilpaint_jpeg_header(const uint8_t *data, size_t len, oilpaint_jpeg_info *info);
+/* Entropy-decode every scan into host memory `coef` (the layout above;
+ * blocks no scan covers are 0).  *count receives the number of
+ * coefficients; ERR_NOMEM (nothing written) if capacity is smaller.  Pure
+ * host work. */
+int oilpaint_jpeg_coefficients(const uint8_t *data, size_t len, int16_t *coef, size_t capacity, size_t *count);
+/* Decode a JPEG file (host memory) into dst, interleaved RGB on the device
+ * (rows dst_stride >= 3 x width bytes apart; bytes past 3 x width are not
+ * written).  The entropy decoding runs before the call returns; the upload
+ * and the kernels are enqueued on `stream`.  *host_ms, if not NULL, receives
+ * the host time of parsing and entropy decoding.  The library keeps the
+ * coefficient and sample buffers per device (grown as needed); a call waits
+ * for the previous call's work on them. */
+int oilpaint_jpeg_decode(const uint8_t *data, size_t len, uint8_t *dst, int dst_stride, void *stream,
+                         double *host_ms);
+/* The same without colour conversion: each component's own samples
+ * (comp_width x comp_height) into planes[c] (device memory, rows strides[c]
+ * >= comp_width bytes apart). */
+int oilpaint_jpeg_decode_planes(const uint8_t *data, size_t len, uint8_t *const *planes, const int *strides,
+                                void *stream, double *host_ms);
+/* Encode width x height interleaved RGB (device memory, rows `stride` bytes
+ * apart) as a JFIF file into `out` (host memory).  *out_len receives the
+ * file's length; ERR_NOMEM if it exceeds `capacity` (out untouched).  The
+ * kernels and the download run on `stream`, which the call synchronizes;
+ * *host_ms, if not NULL, receives the host time of the entropy coding. */
+int oilpaint_jpeg_encode(const uint8_t *src, int width, int height, int stride, int quality, int subsampling,
+                         uint8_t *out, size_t capacity, size_t *out_len, void *stream, double *host_ms);
+/* A capacity always large enough for oilpaint_jpeg_encode of that size. */
+size_t oilpaint_jpeg_encode_bound(int width, int height);
+/* The frame oilpaint_jpeg_encode writes for these arguments (its block
+ * layout). */
+int oilpaint_jpeg_encode_info(int width, int height, int quality, int subsampling, oilpaint_jpeg_info *info);
+/* The encoder's host half: entropy-code quantized coefficients (host memory,
+ * the layout of oilpaint_jpeg_encode_info's frame) into a JFIF file.  Pure
+ * host work. */
+int oilpaint_jpeg_write(const int16_t *coef, int width, int height, int quality, int subsampling, uint8_t *out,
+                        size_t capacity, size_t *out_len);
+
 #ifdef __cplusplus
 }
 #endif

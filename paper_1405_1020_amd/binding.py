@@ -92,6 +92,21 @@ _SIGS = {
                        ctypes.c_int),
     "oilpaint_batch_noalloc": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
                                ctypes.c_int),
+    "oilpaint_jpeg_header": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_jpeg_coefficients": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "oilpaint_jpeg_decode": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "oilpaint_jpeg_decode_planes": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
+                                    ctypes.c_int),
+    "oilpaint_jpeg_encode": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p,
+                              ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "oilpaint_jpeg_encode_bound": ([ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+    "oilpaint_jpeg_encode_info": ([ctypes.c_int] * 4 + [ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_jpeg_write": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "oilpaint_plan_create": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p,
                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "oilpaint_plan_launch": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -348,6 +363,115 @@ def batch_noalloc(items, stream=None) -> None:
     st = lib().oilpaint_batch_noalloc(arr, len(items), _stream_ptr(stream), ctypes.byref(bad))
     if st != OK:
         raise OilpaintError(st, "oilpaint_batch_noalloc (item %d)" % bad.value)
+
+
+class JpegInfo(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("components", ctypes.c_int32),
+                ("h_samp", ctypes.c_int32 * 3), ("v_samp", ctypes.c_int32 * 3),
+                ("comp_width", ctypes.c_int32 * 3), ("comp_height", ctypes.c_int32 * 3),
+                ("blocks_w", ctypes.c_int32 * 3), ("blocks_h", ctypes.c_int32 * 3),
+                ("first_block", ctypes.c_int32 * 3), ("blocks", ctypes.c_int64),
+                ("restart_interval", ctypes.c_int32), ("scans", ctypes.c_int32)]
+
+
+def jpeg_header(data: bytes) -> JpegInfo:
+    """oilpaint_jpeg_header (host only)."""
+    info = JpegInfo()
+    _check(lib().oilpaint_jpeg_header(data, len(data), ctypes.byref(info)), "oilpaint_jpeg_header")
+    return info
+
+
+def jpeg_coefficients(data: bytes):
+    """oilpaint_jpeg_coefficients (host only): (JpegInfo, int16 numpy array of
+    every block's 64 coefficients, natural order)."""
+    import numpy as np
+    info = jpeg_header(data)
+    out = np.zeros(int(info.blocks) * 64, np.int16)
+    n = ctypes.c_size_t(0)
+    _check(lib().oilpaint_jpeg_coefficients(data, len(data), out.ctypes.data, out.size, ctypes.byref(n)),
+           "oilpaint_jpeg_coefficients")
+    return info, out[:n.value]
+
+
+def jpeg_encode_info(width: int, height: int, quality: int, subsampling: int) -> JpegInfo:
+    info = JpegInfo()
+    _check(lib().oilpaint_jpeg_encode_info(width, height, quality, subsampling, ctypes.byref(info)),
+           "oilpaint_jpeg_encode_info")
+    return info
+
+
+def jpeg_write(coef, width: int, height: int, quality: int, subsampling: int) -> bytes:
+    """oilpaint_jpeg_write (host only): entropy-code int16 coefficients."""
+    import numpy as np
+    coef = np.ascontiguousarray(coef, dtype=np.int16)
+    n = ctypes.c_size_t(0)
+    st = lib().oilpaint_jpeg_write(coef.ctypes.data, width, height, quality, subsampling, None, 0, ctypes.byref(n))
+    if st not in (OK, ERR_NOMEM):
+        raise OilpaintError(st, "oilpaint_jpeg_write")
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().oilpaint_jpeg_write(coef.ctypes.data, width, height, quality, subsampling, buf, n.value,
+                                     ctypes.byref(n)), "oilpaint_jpeg_write")
+    return buf.raw[:n.value]
+
+
+def jpeg_decode(data: bytes, out=None, stream=None, times: dict | None = None):
+    """oilpaint_jpeg_decode: a uint8 [H, W, 3] CUDA tensor (or `out`)."""
+    torch = _torch()
+    info = jpeg_header(data)
+    if out is None:
+        out = torch.empty((info.height, info.width, 3), dtype=torch.uint8, device="cuda")
+    _require_cuda(out)
+    w, h, s = image_geometry(out)
+    if (w, h) != (info.width, info.height):
+        raise ValueError("out must be [%d, %d, 3]" % (info.height, info.width))
+    ms = ctypes.c_double(0)
+    _check(lib().oilpaint_jpeg_decode(data, len(data), out.data_ptr(), s, _stream_ptr(stream), ctypes.byref(ms)),
+           "oilpaint_jpeg_decode")
+    if times is not None:
+        times["host_ms"] = ms.value
+    return out
+
+
+def jpeg_decode_planes(data: bytes, stream=None):
+    """oilpaint_jpeg_decode_planes: one uint8 [comp_height, comp_width] CUDA
+    tensor per component."""
+    torch = _torch()
+    info = jpeg_header(data)
+    planes = [torch.empty((info.comp_height[c], info.comp_width[c]), dtype=torch.uint8, device="cuda")
+              for c in range(info.components)]
+    ptrs = (ctypes.c_void_p * 3)(*([p.data_ptr() for p in planes] + [None] * (3 - len(planes))))
+    strides = (ctypes.c_int * 3)(*([p.shape[1] for p in planes] + [0] * (3 - len(planes))))
+    _check(lib().oilpaint_jpeg_decode_planes(data, len(data), ptrs, strides, _stream_ptr(stream), None),
+           "oilpaint_jpeg_decode_planes")
+    return planes
+
+
+_jpeg_out = None
+
+
+def jpeg_encode(src, quality: int = 90, subsampling: int = 2, stream=None, times: dict | None = None) -> bytes:
+    """oilpaint_jpeg_encode of a uint8 [H, W, 3] CUDA tensor: the file bytes."""
+    import numpy as np
+    _require_cuda(src)
+    w, h, s = image_geometry(src)
+    global _jpeg_out
+    # a reused output block of the raw image's size (a JPEG file rarely
+    # exceeds it); a larger file is encoded again into a block of its size
+    need = 3 * w * h + 65536
+    if _jpeg_out is None or _jpeg_out.size < need:
+        _jpeg_out = np.empty(need, np.uint8)
+    n = ctypes.c_size_t(0)
+    ms = ctypes.c_double(0)
+    for _ in range(2):
+        st = lib().oilpaint_jpeg_encode(src.data_ptr(), w, h, s, quality, subsampling, _jpeg_out.ctypes.data,
+                                        _jpeg_out.size, ctypes.byref(n), _stream_ptr(stream), ctypes.byref(ms))
+        if st != ERR_NOMEM or n.value <= _jpeg_out.size:
+            break
+        _jpeg_out = np.empty(n.value, np.uint8)
+    _check(st, "oilpaint_jpeg_encode")
+    if times is not None:
+        times["host_ms"] = ms.value
+    return _jpeg_out[:n.value].tobytes()
 
 
 class Plan:

@@ -1,0 +1,980 @@
+// JPEG decode and encode around the filter: baseline sequential DCT-based
+// JPEG (ITU-T T.81; Huffman coding, 8-bit samples) in JFIF's YCbCr colour
+// space.  The host parses markers and runs the entropy coding; everything per
+// sample (dequantization, inverse DCT, colour, chroma resampling; colour,
+// chroma averaging, forward DCT, quantization) runs in the kernels of
+// oilpaint_k_jpeg.hip, so a decoded image lands in device memory, ready for
+// the filter, and an encoded one is read from there.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "oilpaint_internal.h"
+#include "oilpaint_jpeg.h"
+
+namespace oilpaint_impl {
+int check_device_ptr(const void* p);
+
+namespace {
+
+// Zig-zag order (T.81 Figure A.6): entry k is the natural (row-major) index
+// of the k-th coefficient of the zig-zag sequence.
+constexpr uint8_t kZigzag[64] = {
+    0,  1,  8,  16, 9,  2,  3,  10, 17, 24, 32, 25, 18, 11, 4,  5,  12, 19, 26, 33, 40, 48,
+    41, 34, 27, 20, 13, 6,  7,  14, 21, 28, 35, 42, 49, 56, 57, 50, 43, 36, 29, 22, 15, 23,
+    30, 37, 44, 51, 58, 59, 52, 45, 38, 31, 39, 46, 53, 60, 61, 54, 47, 55, 62, 63};
+
+// T.81 Annex K, Tables K.1 (luminance) and K.2 (chrominance), natural order.
+constexpr uint8_t kLumaQ[64] = {16, 11, 10, 16, 24,  40,  51,  61,  12, 12, 14, 19, 26,  58,  60,  55,
+                                14, 13, 16, 24, 40,  57,  69,  56,  14, 17, 22, 29, 51,  87,  80,  62,
+                                18, 22, 37, 56, 68,  109, 103, 77,  24, 35, 55, 64, 81,  104, 113, 92,
+                                49, 64, 78, 87, 103, 121, 120, 101, 72, 92, 95, 98, 112, 100, 103, 99};
+constexpr uint8_t kChromaQ[64] = {17, 18, 24, 47, 99, 99, 99, 99, 18, 21, 26, 66, 99, 99, 99, 99,
+                                  24, 26, 56, 99, 99, 99, 99, 99, 47, 66, 99, 99, 99, 99, 99, 99,
+                                  99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99,
+                                  99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------------------
+// Marker syntax
+// ---------------------------------------------------------------------------
+struct HuffSpec {
+    uint8_t bits[16];
+    uint8_t vals[256];
+    int nvals = 0;
+    bool set = false;
+};
+
+struct ScanComp {
+    int comp, td, ta;
+};
+
+struct Scan {
+    std::vector<ScanComp> comps;
+    size_t begin = 0, end = 0;  // entropy-coded bytes (RST markers included)
+    HuffSpec dc[4], ac[4];      // tables in force at this scan
+};
+
+struct Frame {
+    int width = 0, height = 0, ncomp = 0;
+    int id[kJpegMaxComps] = {}, h[kJpegMaxComps] = {}, v[kJpegMaxComps] = {}, tq[kJpegMaxComps] = {};
+    int hmax = 1, vmax = 1, mcux = 0, mcuy = 0, restart = 0;
+    int bw[kJpegMaxComps] = {}, bh[kJpegMaxComps] = {};      // MCU-padded block grid
+    int own_bw[kJpegMaxComps] = {}, own_bh[kJpegMaxComps] = {};  // blocks of the component's own samples
+    int xc[kJpegMaxComps] = {}, yc[kJpegMaxComps] = {};      // component's own samples
+    uint16_t q[4][64] = {};
+    bool qset[4] = {};
+    std::vector<Scan> scans;
+    size_t blocks = 0;
+    int first[kJpegMaxComps + 1] = {};
+};
+
+int parse_frame(const uint8_t* d, size_t n, Frame& f) {
+    if (n < 4 || d[0] != 0xFF || d[1] != 0xD8) return OILPAINT_ERR_ARG;
+    HuffSpec dc[4], ac[4];
+    bool have_frame = false;
+    size_t i = 2;
+    for (;;) {
+        if (i >= n) return OILPAINT_ERR_ARG;
+        if (d[i] != 0xFF) return OILPAINT_ERR_ARG;
+        while (i < n && d[i] == 0xFF) ++i;
+        if (i >= n) return OILPAINT_ERR_ARG;
+        const uint8_t m = d[i++];
+        if (m == 0xD9) break;                                    // EOI
+        if (m == 0x01 || (m >= 0xD0 && m <= 0xD7)) continue;     // TEM, stray RST
+        if (i + 2 > n) return OILPAINT_ERR_ARG;
+        const size_t len = (size_t)d[i] << 8 | d[i + 1];
+        if (len < 2 || i + len > n) return OILPAINT_ERR_ARG;
+        const uint8_t* s = d + i + 2;
+        const size_t sl = len - 2;
+        i += len;
+        if (m == 0xDB) {  // DQT
+            size_t k = 0;
+            while (k < sl) {
+                const int pq = s[k] >> 4, tq = s[k] & 15;
+                if (tq > 3 || pq > 1) return OILPAINT_ERR_ARG;
+                if (pq) return OILPAINT_ERR_UNSUPPORTED;  // 16-bit tables go with 12-bit samples (B.2.4.1)
+                ++k;
+                const size_t need = 64 * (pq ? 2 : 1);
+                if (k + need > sl) return OILPAINT_ERR_ARG;
+                for (int t = 0; t < 64; ++t) {
+                    const int val = pq ? (s[k + 2 * t] << 8 | s[k + 2 * t + 1]) : s[k + t];
+                    if (val == 0) return OILPAINT_ERR_ARG;
+                    f.q[tq][kZigzag[t]] = (uint16_t)val;
+                }
+                f.qset[tq] = true;
+                k += need;
+            }
+        } else if (m == 0xC4) {  // DHT
+            size_t k = 0;
+            while (k < sl) {
+                const int tc = s[k] >> 4, th = s[k] & 15;
+                if (tc > 1 || th > 3 || k + 17 > sl) return OILPAINT_ERR_ARG;
+                HuffSpec& h = tc ? ac[th] : dc[th];
+                int total = 0;
+                for (int l = 0; l < 16; ++l) total += (h.bits[l] = s[k + 1 + l]);
+                if (total > 256 || k + 17 + total > sl) return OILPAINT_ERR_ARG;
+                std::memcpy(h.vals, s + k + 17, total);
+                h.nvals = total;
+                h.set = true;
+                k += 17 + total;
+            }
+        } else if (m == 0xC0 || m == 0xC1) {  // SOF0, SOF1
+            if (have_frame || sl < 6 || s[0] != 8) return OILPAINT_ERR_UNSUPPORTED;
+            f.height = s[1] << 8 | s[2];
+            f.width = s[3] << 8 | s[4];
+            f.ncomp = s[5];
+            if (f.width == 0 || f.height == 0) return OILPAINT_ERR_UNSUPPORTED;  // height from DNL
+            if ((f.ncomp != 1 && f.ncomp != 3) || sl < 6 + 3 * (size_t)f.ncomp) return OILPAINT_ERR_UNSUPPORTED;
+            for (int c = 0; c < f.ncomp; ++c) {
+                f.id[c] = s[6 + 3 * c];
+                f.h[c] = s[7 + 3 * c] >> 4;
+                f.v[c] = s[7 + 3 * c] & 15;
+                f.tq[c] = s[8 + 3 * c];
+                if (f.h[c] < 1 || f.h[c] > 4 || f.v[c] < 1 || f.v[c] > 4 || f.tq[c] > 3) return OILPAINT_ERR_ARG;
+            }
+            have_frame = true;
+        } else if ((m >= 0xC2 && m <= 0xCF) && m != 0xC4 && m != 0xC8 && m != 0xCC) {
+            return OILPAINT_ERR_UNSUPPORTED;  // progressive, lossless, hierarchical, arithmetic
+        } else if (m == 0xDD) {  // DRI
+            if (sl < 2) return OILPAINT_ERR_ARG;
+            f.restart = s[0] << 8 | s[1];
+        } else if (m == 0xDA) {  // SOS
+            if (!have_frame || sl < 1) return OILPAINT_ERR_ARG;
+            Scan sc;
+            const int ns = s[0];
+            if (ns < 1 || ns > f.ncomp || sl < 1 + 2 * (size_t)ns + 3) return OILPAINT_ERR_ARG;
+            for (int k = 0; k < ns; ++k) {
+                int c = 0;
+                while (c < f.ncomp && f.id[c] != s[1 + 2 * k]) ++c;
+                if (c == f.ncomp) return OILPAINT_ERR_ARG;
+                const int td = s[2 + 2 * k] >> 4, ta = s[2 + 2 * k] & 15;
+                if (td > 3 || ta > 3 || !dc[td].set || !ac[ta].set) return OILPAINT_ERR_ARG;
+                sc.comps.push_back({c, td, ta});
+            }
+            for (int t = 0; t < 4; ++t) {
+                sc.dc[t] = dc[t];
+                sc.ac[t] = ac[t];
+            }
+            sc.begin = i;
+            while (i + 1 < n && !(d[i] == 0xFF && d[i + 1] != 0 && !(d[i + 1] >= 0xD0 && d[i + 1] <= 0xD7))) ++i;
+            if (i + 1 >= n) return OILPAINT_ERR_ARG;
+            sc.end = i;
+            f.scans.push_back(sc);
+        }
+        // APPn, COM, DNL and the rest: skipped
+    }
+    if (!have_frame || f.scans.empty()) return OILPAINT_ERR_ARG;
+    for (int c = 0; c < f.ncomp; ++c)
+        if (!f.qset[f.tq[c]]) return OILPAINT_ERR_ARG;
+    f.hmax = f.vmax = 1;
+    for (int c = 0; c < f.ncomp; ++c) {
+        f.hmax = std::max(f.hmax, f.h[c]);
+        f.vmax = std::max(f.vmax, f.v[c]);
+    }
+    f.mcux = (f.width + 8 * f.hmax - 1) / (8 * f.hmax);
+    f.mcuy = (f.height + 8 * f.vmax - 1) / (8 * f.vmax);
+    f.first[0] = 0;
+    for (int c = 0; c < f.ncomp; ++c) {
+        f.bw[c] = f.mcux * f.h[c];
+        f.bh[c] = f.mcuy * f.v[c];
+        f.xc[c] = (int)(((int64_t)f.width * f.h[c] + f.hmax - 1) / f.hmax);
+        f.yc[c] = (int)(((int64_t)f.height * f.v[c] + f.vmax - 1) / f.vmax);
+        f.own_bw[c] = (f.xc[c] + 7) / 8;
+        f.own_bh[c] = (f.yc[c] + 7) / 8;
+        f.first[c + 1] = f.first[c] + f.bw[c] * f.bh[c];
+    }
+    for (int c = f.ncomp; c < kJpegMaxComps; ++c) f.first[c + 1] = f.first[c];
+    f.blocks = (size_t)f.first[f.ncomp];
+    return OILPAINT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Huffman decoding: codes from BITS (Annex C), a 9-bit lookup for short
+// codes, the MAXCODE/VALPTR walk (F.2.2.3) for longer ones.
+// ---------------------------------------------------------------------------
+struct HuffDec {
+    int32_t maxcode[18];
+    int32_t valoff[17];  // value index = code + valoff[len]
+    uint8_t vals[256];
+    uint16_t fast[512];  // (length << 8) | value, 0 if longer than 9 bits
+    bool ok = false;
+};
+
+bool build_dec(const HuffSpec& s, HuffDec& h) {
+    std::memcpy(h.vals, s.vals, sizeof(h.vals));
+    std::memset(h.fast, 0, sizeof(h.fast));
+    int code = 0, k = 0;
+    for (int len = 1; len <= 16; ++len) {
+        const int cnt = s.bits[len - 1];
+        h.valoff[len] = k - code;
+        for (int j = 0; j < cnt; ++j, ++k, ++code) {
+            if (code >= (1 << len)) return false;
+            if (len <= 9) {
+                const int shift = 9 - len;
+                for (int f = code << shift; f < ((code + 1) << shift); ++f) h.fast[f] = (uint16_t)(len << 8 | s.vals[k]);
+            }
+        }
+        h.maxcode[len] = cnt ? code - 1 : -1;
+        code <<= 1;
+    }
+    h.maxcode[17] = 0x7fffffff;
+    h.ok = true;
+    return true;
+}
+
+class BitIn {
+  public:
+    BitIn(const uint8_t* d, size_t begin, size_t end) : d_(d), i_(begin), end_(end) {}
+    // Reads 0 bits beyond a marker or the segment's end.
+    void fill() {
+        while (nbits_ <= 56) {
+            uint64_t b = 0;
+            if (!marker_ && i_ < end_) {
+                b = d_[i_];
+                if (b == 0xFF) {
+                    const uint8_t nx = i_ + 1 < end_ ? d_[i_ + 1] : 0xD9;
+                    if (nx == 0x00) {
+                        i_ += 2;
+                    } else {
+                        marker_ = true;
+                        b = 0;
+                    }
+                } else {
+                    ++i_;
+                }
+            }
+            buf_ |= b << (56 - nbits_);
+            nbits_ += 8;
+        }
+    }
+    uint32_t peek(int n) {
+        if (nbits_ < n) fill();
+        return (uint32_t)(buf_ >> (64 - n));
+    }
+    void skip(int n) {
+        buf_ <<= n;
+        nbits_ -= n;
+    }
+    int receive(int s) {
+        if (s == 0) return 0;
+        const int v = (int)peek(s);
+        skip(s);
+        return v;
+    }
+    int decode(const HuffDec& h) {
+        const uint32_t p = peek(16);
+        const uint16_t e = h.fast[p >> 7];
+        if (e) {
+            skip(e >> 8);
+            return e & 255;
+        }
+        int len = 10;
+        int code = (int)(p >> (16 - len));
+        while (code > h.maxcode[len]) {
+            ++len;
+            if (len > 16) return -1;
+            code = (int)(p >> (16 - len));
+        }
+        skip(len);
+        return h.vals[(code + h.valoff[len]) & 255];
+    }
+    // At a restart boundary: drop the buffered bits and step over RSTn.
+    bool restart() {
+        buf_ = 0;
+        nbits_ = 0;
+        marker_ = false;
+        while (i_ + 1 < end_ && !(d_[i_] == 0xFF && d_[i_ + 1] >= 0xD0 && d_[i_ + 1] <= 0xD7)) ++i_;
+        if (i_ + 1 >= end_) return false;
+        i_ += 2;
+        return true;
+    }
+
+  private:
+    const uint8_t* d_;
+    size_t i_, end_;
+    uint64_t buf_ = 0;
+    int nbits_ = 0;
+    bool marker_ = false;
+};
+
+inline int extend(int v, int t) { return (t && v < (1 << (t - 1))) ? v - (1 << t) + 1 : v; }
+
+// Every scan's blocks into `coef` (natural order, component c's block (bx,
+// by) at (first[c] + by * bw[c] + bx) * 64); blocks no scan covers are 0.
+int entropy_decode(const uint8_t* d, const Frame& f, int16_t* coef) {
+    std::memset(coef, 0, f.blocks * 64 * sizeof(int16_t));
+    for (const Scan& sc : f.scans) {
+        HuffDec dcd[4], acd[4];
+        for (const ScanComp& c : sc.comps) {
+            if (!dcd[c.td].ok && !build_dec(sc.dc[c.td], dcd[c.td])) return OILPAINT_ERR_ARG;
+            if (!acd[c.ta].ok && !build_dec(sc.ac[c.ta], acd[c.ta])) return OILPAINT_ERR_ARG;
+        }
+        BitIn in(d, sc.begin, sc.end);
+        int pred[kJpegMaxComps] = {};
+        auto block = [&](const ScanComp& c, int by, int bx) -> bool {
+            int16_t* out = coef + ((size_t)f.first[c.comp] + (size_t)by * f.bw[c.comp] + bx) * 64;
+            const int t = in.decode(dcd[c.td]);
+            if (t < 0 || t > 11) return false;
+            pred[c.comp] += extend(in.receive(t), t);
+            out[0] = (int16_t)pred[c.comp];
+            for (int k = 1; k < 64;) {
+                const int rs = in.decode(acd[c.ta]);
+                if (rs < 0) return false;
+                const int r = rs >> 4, s = rs & 15;
+                if (s == 0) {
+                    if (r != 15) break;
+                    k += 16;
+                    continue;
+                }
+                k += r;
+                if (k > 63 || s > 10) return false;
+                out[kZigzag[k]] = (int16_t)extend(in.receive(s), s);
+                ++k;
+            }
+            return true;
+        };
+        if (sc.comps.size() == 1) {
+            const ScanComp& c = sc.comps[0];
+            int64_t n = 0;
+            for (int by = 0; by < f.own_bh[c.comp]; ++by)
+                for (int bx = 0; bx < f.own_bw[c.comp]; ++bx, ++n) {
+                    if (f.restart && n && n % f.restart == 0) {
+                        if (!in.restart()) return OILPAINT_ERR_ARG;
+                        pred[c.comp] = 0;
+                    }
+                    if (!block(c, by, bx)) return OILPAINT_ERR_ARG;
+                }
+        } else {
+            int64_t n = 0;
+            for (int my = 0; my < f.mcuy; ++my)
+                for (int mx = 0; mx < f.mcux; ++mx, ++n) {
+                    if (f.restart && n && n % f.restart == 0) {
+                        if (!in.restart()) return OILPAINT_ERR_ARG;
+                        for (int& p : pred) p = 0;
+                    }
+                    for (const ScanComp& c : sc.comps)
+                        for (int v = 0; v < f.v[c.comp]; ++v)
+                            for (int h = 0; h < f.h[c.comp]; ++h)
+                                if (!block(c, my * f.v[c.comp] + v, mx * f.h[c.comp] + h)) return OILPAINT_ERR_ARG;
+                }
+        }
+    }
+    return OILPAINT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Huffman encoding with tables fitted to the image (T.81 K.2: code sizes
+// from symbol frequencies, lengths limited to 16 bits, one code point
+// reserved so that no code is all ones).
+// ---------------------------------------------------------------------------
+struct HuffEnc {
+    uint8_t bits[16];
+    uint8_t vals[256];
+    int nvals = 0;
+    uint16_t code[256];
+    uint8_t size[256];
+};
+
+void fit_table(const int64_t* freq_in, HuffEnc& t) {
+    int64_t freq[257];
+    int codesize[257] = {};
+    int others[257];
+    for (int i = 0; i < 256; ++i) freq[i] = freq_in[i];
+    freq[256] = 1;  // reserved
+    for (int i = 0; i < 257; ++i) others[i] = -1;
+    for (;;) {
+        int v1 = -1, v2 = -1;
+        for (int i = 0; i < 257; ++i)  // least frequency, the larger index on ties
+            if (freq[i] > 0 && (v1 < 0 || freq[i] <= freq[v1])) v1 = i;
+        for (int i = 0; i < 257; ++i)
+            if (freq[i] > 0 && i != v1 && (v2 < 0 || freq[i] <= freq[v2])) v2 = i;
+        if (v2 < 0) break;
+        freq[v1] += freq[v2];
+        freq[v2] = 0;
+        ++codesize[v1];
+        while (others[v1] >= 0) {
+            v1 = others[v1];
+            ++codesize[v1];
+        }
+        others[v1] = v2;
+        ++codesize[v2];
+        while (others[v2] >= 0) {
+            v2 = others[v2];
+            ++codesize[v2];
+        }
+    }
+    int cnt[33] = {};
+    for (int i = 0; i < 257; ++i)
+        if (codesize[i]) ++cnt[std::min(codesize[i], 32)];
+    for (int i = 32; i > 16; --i) {  // limit the lengths to 16
+        while (cnt[i] > 0) {
+            int j = i - 2;
+            while (cnt[j] == 0) --j;
+            cnt[i] -= 2;
+            ++cnt[i - 1];
+            cnt[j + 1] += 2;
+            --cnt[j];
+        }
+    }
+    int i = 16;
+    while (i > 0 && cnt[i] == 0) --i;
+    if (i > 0) --cnt[i];  // drop the reserved code point
+    for (int l = 0; l < 16; ++l) t.bits[l] = (uint8_t)cnt[l + 1];
+    t.nvals = 0;
+    for (int l = 1; l <= 32; ++l)
+        for (int s = 0; s < 256; ++s)
+            if (codesize[s] == l) t.vals[t.nvals++] = (uint8_t)s;
+    // codes (Annex C)
+    std::memset(t.size, 0, sizeof(t.size));
+    int code = 0, k = 0;
+    for (int len = 1; len <= 16; ++len) {
+        for (int j = 0; j < t.bits[len - 1]; ++j, ++k, ++code) {
+            t.code[t.vals[k]] = (uint16_t)code;
+            t.size[t.vals[k]] = (uint8_t)len;
+        }
+        code <<= 1;
+    }
+}
+
+class BitOut {
+  public:
+    explicit BitOut(std::vector<uint8_t>& o) : o_(o) {}
+    void put(uint32_t v, int n) {
+        if (n == 0) return;
+        acc_ = (acc_ << n) | (v & ((1u << n) - 1));
+        nb_ += n;
+        while (nb_ >= 8) {
+            const uint8_t b = (uint8_t)(acc_ >> (nb_ - 8));
+            o_.push_back(b);
+            if (b == 0xFF) o_.push_back(0);
+            nb_ -= 8;
+        }
+    }
+    void flush() {  // pad with one bits
+        if (nb_ > 0) put(0x7F, 8 - nb_);
+    }
+
+  private:
+    std::vector<uint8_t>& o_;
+    uint64_t acc_ = 0;
+    int nb_ = 0;
+};
+
+inline int category(int v) {
+    int a = v < 0 ? -v : v, s = 0;
+    while (a) {
+        ++s;
+        a >>= 1;
+    }
+    return s;
+}
+
+// Walk the blocks of one interleaved scan: fn(component, block coefficients).
+template <typename Fn>
+void for_blocks(const Frame& f, const int16_t* coef, Fn fn) {
+    for (int my = 0; my < f.mcuy; ++my)
+        for (int mx = 0; mx < f.mcux; ++mx)
+            for (int c = 0; c < f.ncomp; ++c)
+                for (int v = 0; v < f.v[c]; ++v)
+                    for (int h = 0; h < f.h[c]; ++h) {
+                        const int by = my * f.v[c] + v, bx = mx * f.h[c] + h;
+                        fn(c, coef + ((size_t)f.first[c] + (size_t)by * f.bw[c] + bx) * 64);
+                    }
+}
+
+void put16(std::vector<uint8_t>& o, int v) {
+    o.push_back((uint8_t)(v >> 8));
+    o.push_back((uint8_t)v);
+}
+
+void entropy_encode(const Frame& f, const int16_t* coef, std::vector<uint8_t>& o) {
+    const int ntab = f.ncomp == 1 ? 1 : 2;
+    std::vector<int64_t> fdc(2 * 256, 0), fac(2 * 256, 0);
+    {
+        int pred[kJpegMaxComps] = {};
+        for_blocks(f, coef, [&](int c, const int16_t* b) {
+            const int t = c ? 1 : 0;
+            ++fdc[t * 256 + category(b[0] - pred[c])];
+            pred[c] = b[0];
+            int run = 0;
+            for (int k = 1; k < 64; ++k) {
+                const int v = b[kZigzag[k]];
+                if (v == 0) {
+                    ++run;
+                    continue;
+                }
+                while (run > 15) {
+                    ++fac[t * 256 + 0xF0];
+                    run -= 16;
+                }
+                ++fac[t * 256 + (run << 4 | category(v))];
+                run = 0;
+            }
+            if (run) ++fac[t * 256 + 0x00];
+        });
+    }
+    HuffEnc dc[2], ac[2];
+    for (int t = 0; t < ntab; ++t) {
+        fit_table(&fdc[t * 256], dc[t]);
+        fit_table(&fac[t * 256], ac[t]);
+    }
+    // headers
+    o.insert(o.end(), {0xFF, 0xD8, 0xFF, 0xE0});
+    put16(o, 16);
+    o.insert(o.end(), {'J', 'F', 'I', 'F', 0, 1, 1, 0, 0, 1, 0, 1, 0, 0});
+    for (int t = 0; t < ntab; ++t) {
+        o.insert(o.end(), {0xFF, 0xDB});
+        put16(o, 67);
+        o.push_back((uint8_t)t);
+        for (int k = 0; k < 64; ++k) o.push_back((uint8_t)f.q[t][kZigzag[k]]);
+    }
+    o.insert(o.end(), {0xFF, 0xC0});
+    put16(o, 8 + 3 * f.ncomp);
+    o.push_back(8);
+    put16(o, f.height);
+    put16(o, f.width);
+    o.push_back((uint8_t)f.ncomp);
+    for (int c = 0; c < f.ncomp; ++c) {
+        o.push_back((uint8_t)(c + 1));
+        o.push_back((uint8_t)(f.h[c] << 4 | f.v[c]));
+        o.push_back((uint8_t)f.tq[c]);
+    }
+    for (int t = 0; t < ntab; ++t)
+        for (int cls = 0; cls < 2; ++cls) {
+            const HuffEnc& h = cls ? ac[t] : dc[t];
+            o.insert(o.end(), {0xFF, 0xC4});
+            put16(o, 2 + 17 + h.nvals);
+            o.push_back((uint8_t)(cls << 4 | t));
+            o.insert(o.end(), h.bits, h.bits + 16);
+            o.insert(o.end(), h.vals, h.vals + h.nvals);
+        }
+    o.insert(o.end(), {0xFF, 0xDA});
+    put16(o, 6 + 2 * f.ncomp);
+    o.push_back((uint8_t)f.ncomp);
+    for (int c = 0; c < f.ncomp; ++c) {
+        o.push_back((uint8_t)(c + 1));
+        const int t = c ? 1 : 0;
+        o.push_back((uint8_t)(t << 4 | t));
+    }
+    o.insert(o.end(), {0, 63, 0});
+    // data
+    BitOut bo(o);
+    int pred[kJpegMaxComps] = {};
+    for_blocks(f, coef, [&](int c, const int16_t* b) {
+        const HuffEnc& hd = dc[c ? 1 : 0];
+        const HuffEnc& ha = ac[c ? 1 : 0];
+        const int diff = b[0] - pred[c];
+        pred[c] = b[0];
+        const int s = category(diff);
+        bo.put(hd.code[s], hd.size[s]);
+        bo.put((uint32_t)(diff < 0 ? diff - 1 : diff), s);
+        int run = 0;
+        for (int k = 1; k < 64; ++k) {
+            const int v = b[kZigzag[k]];
+            if (v == 0) {
+                ++run;
+                continue;
+            }
+            while (run > 15) {
+                bo.put(ha.code[0xF0], ha.size[0xF0]);
+                run -= 16;
+            }
+            const int sz = category(v);
+            const int sym = run << 4 | sz;
+            bo.put(ha.code[sym], ha.size[sym]);
+            bo.put((uint32_t)(v < 0 ? v - 1 : v), sz);
+            run = 0;
+        }
+        if (run) bo.put(ha.code[0], ha.size[0]);
+    });
+    bo.flush();
+    o.insert(o.end(), {0xFF, 0xD9});
+}
+
+// Quality scaling of the Annex K tables (the Independent JPEG Group's
+// convention: 50 keeps them, lower scales them up, higher down).
+void scaled_table(const uint8_t* base, int quality, uint16_t* out) {
+    quality = std::min(100, std::max(1, quality));
+    const int scale = quality < 50 ? 5000 / quality : 200 - 2 * quality;
+    for (int k = 0; k < 64; ++k) out[k] = (uint16_t)std::min(255, std::max(1, (base[k] * scale + 50) / 100));
+}
+
+// The frame the encoder writes: three components, Y sampled (hl, vl) = (1,
+// 1), (2, 1) or (2, 2) for subsampling 0, 1, 2 (4:4:4, 4:2:2, 4:2:0), Cb and
+// Cr (1, 1); tables 0 (luminance) and 1 (chrominance) at `quality`.
+int encode_frame(int width, int height, int quality, int subsampling, Frame& f) {
+    if (width < 1 || height < 1 || width > 65535 || height > 65535) return OILPAINT_ERR_ARG;
+    if (quality < 1 || quality > 100 || subsampling < 0 || subsampling > 2) return OILPAINT_ERR_ARG;
+    f = Frame();
+    f.width = width;
+    f.height = height;
+    f.ncomp = 3;
+    const int hl = subsampling == 0 ? 1 : 2, vl = subsampling == 2 ? 2 : 1;
+    for (int c = 0; c < 3; ++c) {
+        f.id[c] = c + 1;
+        f.h[c] = c ? 1 : hl;
+        f.v[c] = c ? 1 : vl;
+        f.tq[c] = c ? 1 : 0;
+    }
+    scaled_table(kLumaQ, quality, f.q[0]);
+    scaled_table(kChromaQ, quality, f.q[1]);
+    f.qset[0] = f.qset[1] = true;
+    f.hmax = hl;
+    f.vmax = vl;
+    f.mcux = (width + 8 * hl - 1) / (8 * hl);
+    f.mcuy = (height + 8 * vl - 1) / (8 * vl);
+    f.first[0] = 0;
+    for (int c = 0; c < 3; ++c) {
+        f.bw[c] = f.mcux * f.h[c];
+        f.bh[c] = f.mcuy * f.v[c];
+        f.xc[c] = (int)(((int64_t)width * f.h[c] + hl - 1) / hl);
+        f.yc[c] = (int)(((int64_t)height * f.v[c] + vl - 1) / vl);
+        f.own_bw[c] = (f.xc[c] + 7) / 8;
+        f.own_bh[c] = (f.yc[c] + 7) / 8;
+        f.first[c + 1] = f.first[c] + f.bw[c] * f.bh[c];
+    }
+    f.blocks = (size_t)f.first[3];
+    return OILPAINT_OK;
+}
+
+void fill_info(const Frame& f, oilpaint_jpeg_info* info) {
+    std::memset(info, 0, sizeof(*info));
+    info->width = f.width;
+    info->height = f.height;
+    info->components = f.ncomp;
+    for (int c = 0; c < f.ncomp; ++c) {
+        info->h_samp[c] = f.h[c];
+        info->v_samp[c] = f.v[c];
+        info->comp_width[c] = f.xc[c];
+        info->comp_height[c] = f.yc[c];
+        info->blocks_w[c] = f.bw[c];
+        info->blocks_h[c] = f.bh[c];
+        info->first_block[c] = f.first[c];
+    }
+    info->blocks = (int64_t)f.blocks;
+    info->restart_interval = f.restart;
+    info->scans = (int)f.scans.size();
+}
+
+// ---------------------------------------------------------------------------
+// Per-device buffers: coefficients (device and pinned host) and sample
+// planes, grown on demand; `done` marks the end of the last call's device
+// work on them, `uploaded` the end of its host-to-device copy.
+// ---------------------------------------------------------------------------
+struct JpegDevice {
+    std::mutex mu;
+    int16_t* coef = nullptr;
+    int16_t* host = nullptr;
+    size_t coef_cap = 0;  // coefficients
+    uint8_t* planes = nullptr;
+    size_t plane_cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    ~JpegDevice() {
+        if (pending) (void)hipEventSynchronize(done);
+        if (coef) (void)hipFree(coef);
+        if (host) (void)hipHostFree(host);
+        if (planes) (void)hipFree(planes);
+        if (done) (void)hipEventDestroy(done);
+    }
+    int reserve(size_t ncoef, size_t nplane) {
+        if (!done && note_hip("hipEventCreate", hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+        if (ncoef > coef_cap) {
+            if (coef) (void)hipFree(coef);
+            if (host) (void)hipHostFree(host);
+            coef = nullptr;
+            host = nullptr;
+            coef_cap = 0;
+            const size_t cap = std::max(ncoef, (size_t)1 << 20);
+            if (hipMalloc(&coef, cap * sizeof(int16_t)) != hipSuccess) return OILPAINT_ERR_NOMEM;
+            if (hipHostMalloc(reinterpret_cast<void**>(&host), cap * sizeof(int16_t), hipHostMallocDefault) !=
+                hipSuccess)
+                return OILPAINT_ERR_NOMEM;
+            coef_cap = cap;
+        }
+        if (nplane > plane_cap) {
+            if (planes) (void)hipFree(planes);
+            planes = nullptr;
+            plane_cap = 0;
+            const size_t cap = std::max(nplane, (size_t)1 << 20);
+            if (hipMalloc(&planes, cap) != hipSuccess) return OILPAINT_ERR_NOMEM;
+            plane_cap = cap;
+        }
+        return OILPAINT_OK;
+    }
+    // Wait (host) until the previous call's work on the buffers is done.
+    int wait() {
+        if (pending && note_hip("hipEventSynchronize", hipEventSynchronize(done)) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+        pending = false;
+        return OILPAINT_OK;
+    }
+    int mark(hipStream_t s) {
+        if (note_hip("hipEventRecord", hipEventRecord(done, s)) != hipSuccess) return OILPAINT_ERR_HIP;
+        pending = true;
+        return OILPAINT_OK;
+    }
+};
+
+JpegDevice& jpeg_device(int device) {
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<JpegDevice>> m;
+    std::lock_guard<std::mutex> lock(mu);
+    auto& p = m[device];
+    if (!p) p.reset(new JpegDevice);
+    return *p;
+}
+
+// Planes of the frame's components over their MCU-padded grids, one after
+// another in `base`.
+void plane_layout(const Frame& f, uint8_t* base, uint8_t** plane, int32_t* stride, size_t* total) {
+    size_t off = 0;
+    for (int c = 0; c < kJpegMaxComps; ++c) {
+        if (c < f.ncomp) {
+            stride[c] = f.bw[c] * 8;
+            plane[c] = base ? base + off : nullptr;
+            off += ((size_t)f.bw[c] * 8 * f.bh[c] * 8 + 255) & ~(size_t)255;
+        } else {
+            stride[c] = 0;
+            plane[c] = nullptr;
+        }
+    }
+    *total = off;
+}
+
+JpegIdctArgs idct_args(const Frame& f, const int16_t* coef) {
+    JpegIdctArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.coef = coef;
+    for (int c = 0; c <= kJpegMaxComps; ++c) a.first[c] = f.first[c];
+    for (int c = 0; c < f.ncomp; ++c) {
+        a.bw[c] = f.bw[c];
+        std::memcpy(a.q[c], f.q[f.tq[c]], sizeof(a.q[c]));
+    }
+    return a;
+}
+
+// Parse, entropy-decode into the pinned buffer and start the upload and the
+// inverse DCT on `stream`; planes as given (device pointers, component
+// samples only) or the library's own (whole padded grids).
+int decode_to_planes(const uint8_t* data, size_t len, JpegDevice& jd, Frame& f, uint8_t* const* user_planes,
+                     const int* user_strides, hipStream_t stream, double* host_ms) {
+    const auto t0 = std::chrono::steady_clock::now();
+    int st = parse_frame(data, len, f);
+    if (st != OILPAINT_OK) return st;
+    uint8_t* lib_planes[kJpegMaxComps];
+    int32_t lib_strides[kJpegMaxComps];
+    size_t plane_bytes = 0;
+    plane_layout(f, nullptr, lib_planes, lib_strides, &plane_bytes);
+    if ((st = jd.wait()) != OILPAINT_OK) return st;
+    if ((st = jd.reserve(f.blocks * 64, user_planes ? 0 : plane_bytes)) != OILPAINT_OK) return st;
+    if ((st = entropy_decode(data, f, jd.host)) != OILPAINT_OK) return st;
+    if (host_ms) *host_ms = ms_since(t0);
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(jd.coef, jd.host, f.blocks * 64 * sizeof(int16_t),
+                                                  hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return OILPAINT_ERR_HIP;
+    JpegIdctArgs a = idct_args(f, jd.coef);
+    if (user_planes) {
+        for (int c = 0; c < f.ncomp; ++c) {
+            a.plane[c] = user_planes[c];
+            a.stride[c] = user_strides[c];
+            a.limit_w[c] = f.xc[c];
+            a.limit_h[c] = f.yc[c];
+        }
+    } else {
+        plane_layout(f, jd.planes, lib_planes, lib_strides, &plane_bytes);
+        for (int c = 0; c < f.ncomp; ++c) {
+            a.plane[c] = lib_planes[c];
+            a.stride[c] = lib_strides[c];
+            a.limit_w[c] = f.bw[c] * 8;
+            a.limit_h[c] = f.bh[c] * 8;
+        }
+    }
+    if (launch_jpeg_idct(a, stream) != hipSuccess) return OILPAINT_ERR_HIP;
+    return OILPAINT_OK;
+}
+
+}  // namespace
+}  // namespace oilpaint_impl
+
+using namespace oilpaint_impl;
+
+extern "C" {
+
+int oilpaint_jpeg_header(const uint8_t* data, size_t len, oilpaint_jpeg_info* info) {
+    if (!data || !info) return OILPAINT_ERR_NULL;
+    Frame f;
+    const int st = parse_frame(data, len, f);
+    if (st != OILPAINT_OK) return st;
+    fill_info(f, info);
+    return OILPAINT_OK;
+}
+
+int oilpaint_jpeg_coefficients(const uint8_t* data, size_t len, int16_t* coef, size_t capacity, size_t* count) {
+    if (!data || !count) return OILPAINT_ERR_NULL;
+    Frame f;
+    int st = parse_frame(data, len, f);
+    if (st != OILPAINT_OK) return st;
+    *count = f.blocks * 64;
+    if (!coef || capacity < f.blocks * 64) return OILPAINT_ERR_NOMEM;
+    return entropy_decode(data, f, coef);
+}
+
+int oilpaint_jpeg_encode_info(int width, int height, int quality, int subsampling, oilpaint_jpeg_info* info) {
+    if (!info) return OILPAINT_ERR_NULL;
+    Frame f;
+    const int st = encode_frame(width, height, quality, subsampling, f);
+    if (st != OILPAINT_OK) return st;
+    fill_info(f, info);
+    return OILPAINT_OK;
+}
+
+int oilpaint_jpeg_write(const int16_t* coef, int width, int height, int quality, int subsampling, uint8_t* out,
+                        size_t capacity, size_t* out_len) {
+    if (!coef || !out_len) return OILPAINT_ERR_NULL;
+    Frame f;
+    const int st = encode_frame(width, height, quality, subsampling, f);
+    if (st != OILPAINT_OK) return st;
+    std::vector<uint8_t> bytes;
+    bytes.reserve(f.blocks * 16 + 1024);
+    entropy_encode(f, coef, bytes);
+    *out_len = bytes.size();
+    if (!out || bytes.size() > capacity) return OILPAINT_ERR_NOMEM;
+    std::memcpy(out, bytes.data(), bytes.size());
+    return OILPAINT_OK;
+}
+
+int oilpaint_jpeg_decode(const uint8_t* data, size_t len, uint8_t* dst, int dst_stride, void* stream,
+                         double* host_ms) {
+    if (!data || !dst) return OILPAINT_ERR_NULL;
+    int device = 0;
+    if (note_hip("hipGetDevice", hipGetDevice(&device)) != hipSuccess) return OILPAINT_ERR_HIP;
+    Frame hdr;
+    int st = parse_frame(data, len, hdr);
+    if (st != OILPAINT_OK) return st;
+    if (dst_stride < 3 * hdr.width) return OILPAINT_ERR_ARG;
+    if ((st = check_device_ptr(dst)) != OILPAINT_OK) return st;
+    JpegDevice& jd = jpeg_device(device);
+    std::lock_guard<std::mutex> lock(jd.mu);
+    const hipStream_t s = (hipStream_t)stream;
+    Frame f;
+    if ((st = decode_to_planes(data, len, jd, f, nullptr, nullptr, s, host_ms)) != OILPAINT_OK) return st;
+    JpegColorArgs c;
+    std::memset(&c, 0, sizeof(c));
+    uint8_t* planes[kJpegMaxComps];
+    int32_t strides[kJpegMaxComps];
+    size_t bytes = 0;
+    plane_layout(f, jd.planes, planes, strides, &bytes);
+    for (int k = 0; k < f.ncomp; ++k) {
+        c.plane[k] = planes[k];
+        c.stride[k] = strides[k];
+        c.h[k] = f.h[k];
+        c.v[k] = f.v[k];
+    }
+    c.hmax = f.hmax;
+    c.vmax = f.vmax;
+    c.ncomp = f.ncomp;
+    c.width = f.width;
+    c.height = f.height;
+    c.dst = dst;
+    c.dst_stride = dst_stride;
+    if (launch_jpeg_color(c, s) != hipSuccess) return OILPAINT_ERR_HIP;
+    return jd.mark(s);
+}
+
+int oilpaint_jpeg_decode_planes(const uint8_t* data, size_t len, uint8_t* const* planes, const int* strides,
+                                void* stream, double* host_ms) {
+    if (!data || !planes || !strides) return OILPAINT_ERR_NULL;
+    int device = 0;
+    if (note_hip("hipGetDevice", hipGetDevice(&device)) != hipSuccess) return OILPAINT_ERR_HIP;
+    Frame hdr;
+    int st = parse_frame(data, len, hdr);
+    if (st != OILPAINT_OK) return st;
+    for (int c = 0; c < hdr.ncomp; ++c) {
+        if (!planes[c]) return OILPAINT_ERR_NULL;
+        if (strides[c] < hdr.xc[c]) return OILPAINT_ERR_ARG;
+        if ((st = check_device_ptr(planes[c])) != OILPAINT_OK) return st;
+    }
+    JpegDevice& jd = jpeg_device(device);
+    std::lock_guard<std::mutex> lock(jd.mu);
+    const hipStream_t s = (hipStream_t)stream;
+    Frame f;
+    if ((st = decode_to_planes(data, len, jd, f, planes, strides, s, host_ms)) != OILPAINT_OK) return st;
+    return jd.mark(s);
+}
+
+size_t oilpaint_jpeg_encode_bound(int width, int height) {
+    if (width <= 0 || height <= 0) return 0;
+    const size_t blocks = (size_t)((width + 15) / 16) * ((height + 15) / 16) * 6 * 2;  // up to 4:4:4
+    return 1024 + 4 * 17 * 2 + 4 * 256 + blocks * 64 * 8;
+}
+
+int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, int quality, int subsampling,
+                         uint8_t* out, size_t capacity, size_t* out_len, void* stream, double* host_ms) {
+    if (!src || !out_len) return OILPAINT_ERR_NULL;
+    Frame f;
+    int st = encode_frame(width, height, quality, subsampling, f);
+    if (st != OILPAINT_OK) return st;
+    if (stride < 3 * width) return OILPAINT_ERR_ARG;
+    const int hl = f.hmax, vl = f.vmax;
+    int device = 0;
+    if (note_hip("hipGetDevice", hipGetDevice(&device)) != hipSuccess) return OILPAINT_ERR_HIP;
+    if ((st = check_device_ptr(src)) != OILPAINT_OK) return st;
+    JpegDevice& jd = jpeg_device(device);
+    std::lock_guard<std::mutex> lock(jd.mu);
+    const hipStream_t s = (hipStream_t)stream;
+    uint8_t* planes[kJpegMaxComps];
+    int32_t strides[kJpegMaxComps];
+    size_t plane_bytes = 0;
+    plane_layout(f, nullptr, planes, strides, &plane_bytes);
+    if ((st = jd.wait()) != OILPAINT_OK) return st;
+    if ((st = jd.reserve(f.blocks * 64, plane_bytes)) != OILPAINT_OK) return st;
+    plane_layout(f, jd.planes, planes, strides, &plane_bytes);
+    JpegRgbArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.src = src;
+    r.stride = stride;
+    r.width = width;
+    r.height = height;
+    r.ymcu_w = f.bw[0] * 8;
+    r.ymcu_h = f.bh[0] * 8;
+    r.fh = hl;
+    r.fv = vl;
+    JpegFdctArgs q;
+    std::memset(&q, 0, sizeof(q));
+    for (int c = 0; c < 3; ++c) {
+        r.plane[c] = planes[c];
+        r.pstride[c] = strides[c];
+        q.plane[c] = planes[c];
+        q.stride[c] = strides[c];
+        q.bw[c] = f.bw[c];
+        std::memcpy(q.q[c], f.q[f.tq[c]], sizeof(q.q[c]));
+    }
+    for (int c = 0; c <= 3; ++c) q.first[c] = f.first[c];
+    q.coef = jd.coef;
+    if (launch_jpeg_rgb(r, s) != hipSuccess || launch_jpeg_fdct(q, s) != hipSuccess) return OILPAINT_ERR_HIP;
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(jd.host, jd.coef, f.blocks * 64 * sizeof(int16_t),
+                                                  hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+        return OILPAINT_ERR_HIP;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<uint8_t> bytes;
+    bytes.reserve(f.blocks * 16 + 1024);
+    entropy_encode(f, jd.host, bytes);
+    if (host_ms) *host_ms = ms_since(t0);
+    *out_len = bytes.size();
+    if (!out || bytes.size() > capacity) return OILPAINT_ERR_NOMEM;
+    std::memcpy(out, bytes.data(), bytes.size());
+    return OILPAINT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+"""GPU parity of the JPEG steps either side of the filter, through the C-ABI,
+against the JPEG oracle (oracle/jpeg_ref.py: T.81 and JFIF in fp64 and exact
+integers).
+
+Tolerance.  Colour conversion is integer arithmetic on both sides: bit-exact.
+The inverse and forward DCTs run in fp32 on the GPU: every sample (or
+quantized coefficient) must equal the oracle's, except where the oracle's
+exact value lies within the fp32 error bound of a rounding boundary (half an
+integer), where it may differ by one.  The bound is 2^-17 x the block's sum
+of |dequantized coefficients| (inverse) or of |sample - 128| (forward, divided
+by the quantizer), with 2^-20 of the value itself for the division: two
+passes of eight fp32 multiply-adds over basis entries below 1 each round at
+most 2^-24 relative per step, which this exceeds several times over."""
+import io
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.jpeg_ref as J
+from paper_1405_1020_amd import binding as B
+from paper_1405_1020_amd import synth
+from gpu_util import torch_mod
+
+pytestmark = pytest.mark.gpu
+PIL = pytest.importorskip("PIL.Image")
+
+HV = {0: ((1, 1, 1), (1, 1, 1)), 1: ((2, 1, 1), (1, 1, 1)), 2: ((2, 1, 1), (2, 1, 1))}
+
+
+def pil_jpeg(img, quality, subsampling=2, **kw) -> bytes:
+    b = io.BytesIO()
+    PIL.fromarray(img).save(b, format="JPEG", quality=quality, subsampling=subsampling, **kw)
+    return b.getvalue()
+
+
+def near_half(v: np.ndarray, window: np.ndarray) -> np.ndarray:
+    f = v - np.floor(v)
+    return np.abs(f - 0.5) < window
+
+
+def check_planes(data: bytes, planes_gpu) -> int:
+    """Every sample of every component against the oracle; returns how many
+    sat within the fp32 bound of a rounding boundary."""
+    j = J.parse(data)
+    coefs = J.decode_coefficients(j)
+    want = J.reconstruct_planes(j, coefs)
+    vals, sums = J.idct_values(j, coefs)
+    flagged = 0
+    for c, p in enumerate(planes_gpu):
+        got = p.cpu().numpy().astype(np.int64)
+        h, w = got.shape
+        ref = want[c][:h, :w].astype(np.int64)
+        win = np.repeat(np.repeat(sums[c], 8, 0), 8, 1)[:h, :w] * 2.0 ** -17
+        tie = near_half(vals[c][:h, :w], win)
+        d = np.abs(got - ref)
+        assert d.max() <= 1, (c, int(d.max()))
+        bad = (d != 0) & ~tie
+        assert not bad.any(), (c, np.argwhere(bad)[:5].tolist())
+        flagged += int(tie.sum())
+    return flagged
+
+
+CASES = [((203, 117), 75, 2, {}), ((203, 117), 95, 0, {}), ((64, 48), 30, 1, {}), ((1, 1), 80, 2, {}),
+         ((7, 9), 100, 2, {}), ((150, 71), 80, 2, {"restart_marker_blocks": 3}), ((640, 480), 90, 2, {})]
+
+
+@pytest.mark.parametrize("size,quality,ss,kw", CASES)
+def test_decode_matches_oracle(size, quality, ss, kw):
+    torch = torch_mod()
+    w, h = size
+    img = synth.make_image(w, h, seed=w + quality, n_blobs=6, sigma=(2, 40))
+    data = pil_jpeg(img, quality, ss, **kw)
+    planes = B.jpeg_decode_planes(data)
+    rgb = B.jpeg_decode(data)
+    torch.cuda.synchronize()
+    check_planes(data, planes)
+    # colour: exact integers, applied by the oracle to the GPU's own planes
+    j = J.parse(data)
+    want = J.planes_to_rgb(j, [p.cpu().numpy() for p in planes])
+    assert np.array_equal(rgb.cpu().numpy(), want)
+
+
+def test_decode_grey_and_strided_output():
+    torch = torch_mod()
+    img = synth.make_image(97, 53, seed=4, n_blobs=4, sigma=(2, 20))[..., 2].copy()
+    b = io.BytesIO()
+    PIL.fromarray(img).save(b, format="JPEG", quality=85)
+    data = b.getvalue()
+    planes = B.jpeg_decode_planes(data)
+    check_planes(data, planes)
+    buf = torch.full((53, 97 * 3 + 5), 77, dtype=torch.uint8, device="cuda")
+    view = buf[:, :97 * 3].view(53, 97, 3)
+    B.jpeg_decode(data, out=view)
+    torch.cuda.synchronize()
+    y = planes[0].cpu().numpy()
+    got = buf.cpu().numpy()
+    assert np.array_equal(got[:, :97 * 3].reshape(53, 97, 3), np.stack([y, y, y], -1))
+    assert (got[:, 97 * 3:] == 77).all()
+
+
+def test_decode_full_hd():
+    torch = torch_mod()
+    img = synth.fhd_image()
+    data = pil_jpeg(img, 90, 2)
+    planes = B.jpeg_decode_planes(data)
+    rgb = B.jpeg_decode(data)
+    torch.cuda.synchronize()
+    check_planes(data, planes)
+    want = J.planes_to_rgb(J.parse(data), [p.cpu().numpy() for p in planes])
+    assert np.array_equal(rgb.cpu().numpy(), want)
+
+
+def check_encoded(img: np.ndarray, data: bytes, quality: int, ss: int) -> int:
+    """The file's quantized coefficients (read with the oracle's decoder)
+    against the oracle's colour, chroma averaging, FDCT and quantization of
+    the source with the file's tables; returns the near-boundary count."""
+    j = J.parse(data)
+    assert (j.width, j.height) == (img.shape[1], img.shape[0])
+    h, v = HV[ss]
+    assert [c.h for c in j.components] == list(h) and [c.v for c in j.components] == list(v)
+    coefs = J.decode_coefficients(j)
+    planes = J.encode_planes(img, h, v)
+    flagged = 0
+    for c in range(3):
+        q = j.qtables[j.components[c].tq]
+        qc, ratio, sums = J.quantize_blocks(planes[c], q)
+        win = sums[..., None] * 2.0 ** -17 / q[None, None, :] + np.abs(ratio) * 2.0 ** -20
+        tie = near_half(np.abs(ratio), win)
+        d = np.abs(qc - coefs[c])
+        assert d.max() <= 1, (c, int(d.max()))
+        assert not ((d != 0) & ~tie).any(), c
+        flagged += int(tie.sum())
+    return flagged
+
+
+@pytest.mark.parametrize("size,quality,ss", [((203, 117), 75, 2), ((203, 117), 95, 0), ((64, 48), 30, 1),
+                                             ((1, 1), 80, 2), ((7, 9), 100, 2), ((33, 17), 50, 1),
+                                             ((640, 480), 90, 2)])
+def test_encode_matches_oracle(size, quality, ss):
+    torch = torch_mod()
+    w, h = size
+    img = synth.make_image(w, h, seed=3 * w + quality, n_blobs=6, sigma=(2, 40))
+    src = torch.from_numpy(img).cuda()
+    data = B.jpeg_encode(src, quality=quality, subsampling=ss)
+    check_encoded(img, data, quality, ss)
+    # libjpeg reads it, and it is close to the source
+    out = np.asarray(PIL.open(io.BytesIO(data)).convert("RGB")).astype(np.int64)
+    assert out.shape == img.shape
+    if quality >= 90 and w * h > 100:
+        assert np.abs(out - img).mean() < 3.0
+
+
+def test_file_driver_decode_filter_encode():
+    """The paper's program shape: a JPEG file decoded onto the device, the oil
+    paint filter run there, the result encoded: the decoded image against
+    the oracle (as above), the filtered one against the filter's oracle on
+    those decoded pixels (bit-exact), the file against the oracle encoder."""
+    torch = torch_mod()
+    img = synth.make_image(320, 240, seed=77, n_blobs=10, sigma=(5, 60))
+    data = pil_jpeg(img, 90, 2)
+    dec = B.jpeg_decode(data)
+    planes = B.jpeg_decode_planes(data)
+    out = B.oilpaint(dec, 3, 20)
+    enc = B.jpeg_encode(out, quality=90, subsampling=2)
+    torch.cuda.synchronize()
+    check_planes(data, planes)
+    decoded = dec.cpu().numpy()
+    filtered = out.cpu().numpy()
+    assert np.array_equal(filtered, oracle.oilpaint_ref(decoded, 3, 20, nthreads=4))
+    check_encoded(filtered, enc, 90, 2)
+
+
+def test_encode_errors():
+    torch = torch_mod()
+    src = torch.zeros((10, 10, 3), dtype=torch.uint8, device="cuda")
+    for q, ss in ((0, 2), (101, 2), (50, 3), (50, -1)):
+        with pytest.raises(B.OilpaintError) as e:
+            B.jpeg_encode(src, quality=q, subsampling=ss)
+        assert e.value.status == B.ERR_ARG
+    host = torch.zeros((10, 10, 3), dtype=torch.uint8)
+    data = pil_jpeg(np.zeros((10, 10, 3), np.uint8), 80)
+    assert B.lib().oilpaint_jpeg_decode(data, len(data), host.data_ptr(), 30, None, None) == B.ERR_NOT_DEVICE
+    assert B.lib().oilpaint_jpeg_decode(data, len(data), src.data_ptr(), 29, None, None) == B.ERR_ARG
