@@ -153,12 +153,22 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *                         Batches and plans run such jobs with 4 wavefronts
  *                         from radius 7; below it in the streamed layout
  *                         (with waves = 1 in the paper form).
+ *   OILPAINT_HIST_REGS    the PACKED bin word of every level in each lane's
+ *                         own registers instead of LDS (the listing's
+ *                         per-level arrays per thread): a window update adds
+ *                         the pixel's increment to every bin under a mask
+ *                         "level == bin" (a register cannot be addressed by
+ *                         the level), so LDS atomics become VALU work; the
+ *                         rows are streamed as in STREAM.  64 lanes, one
+ *                         wavefront, radius <= 7, levels <= 16.  Batches and
+ *                         plans run such jobs in the streamed layout.
  * ------------------------------------------------------------------------- */
 #define OILPAINT_HIST_PACKED  0
 #define OILPAINT_HIST_STREAM  1
 #define OILPAINT_HIST_WIDE    2
 #define OILPAINT_HIST_STREAM8 3
 #define OILPAINT_HIST_COLUMN  4
+#define OILPAINT_HIST_REGS    5
 
 typedef struct oilpaint_variant {
     int32_t rows;   /* output rows per lane, >= 1; 0: derived from per_cu */

@@ -31,6 +31,7 @@ HIST_STREAM = 1
 HIST_WIDE = 2
 HIST_STREAM8 = 3
 HIST_COLUMN = 4
+HIST_REGS = 5
 FLAG_PAPER = 1
 
 

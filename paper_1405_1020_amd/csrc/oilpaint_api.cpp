@@ -50,6 +50,7 @@ size_t lds_bytes(const Job& j) {
     const size_t nb = (size_t)j.bins;
     const size_t lanes = (size_t)j.lanes;
     if (j.hist == OILPAINT_HIST_WIDE) return (size_t)waves * 2 * nb * lanes * 8;
+    if (j.hist == OILPAINT_HIST_REGS) return stream_ring_bytes(j) + 192;
     if (is_stream(j.hist)) {
         // radius 1 with one wavefront and more than 8 scanned levels keeps its
         // window in registers (no histogram: tile_direct1)
@@ -144,6 +145,9 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
         if (j.radius > kColumnMaxRadius || !ok_waves || v.lanes != 64) return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_WIDE) {
         if (j.radius > kWideMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
+    } else if (v.hist == OILPAINT_HIST_REGS) {
+        if (j.radius > kRegsMaxRadius || j.levels > kRegsMaxLevels || v.lanes != 64 || v.waves != 1)
+            return OILPAINT_ERR_UNSUPPORTED;
     } else {
         return OILPAINT_ERR_UNSUPPORTED;
     }

@@ -1111,6 +1111,11 @@ __device__ __forceinline__ void split_mode_row(const Job& j, int x0, int y, int 
     uint32_t best = 0;
     uint64_t bw = 0;
     if constexpr (MB >= 4) {
+        // whole-word reads: a read of the count halves alone (every other
+        // dword) would meet a two-way bank conflict
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (!RT || i < mb) asm volatile("" ::"v"((uint32_t)v[i]));
 #pragma unroll
         for (int i = 0; i < MB; ++i)
             if (!RT || i < mb) best = max(best, ((uint32_t)(v[i] >> 32) & M) | (uint32_t)(63 - w * mb - i));

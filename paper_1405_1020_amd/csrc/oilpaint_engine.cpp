@@ -46,6 +46,13 @@ constexpr int kBatchColumnMinRadius = 7;
 // the whole launch (shape_rows).
 int batch_shape(Job& j, int device) {
     oilpaint_variant v = choose_variant(j.width, j.height, j.radius, j.levels, j.paper != 0, device);
+    if (v.hist == OILPAINT_HIST_REGS) {  // no persistent form: the streamed layout's classes
+        v.hist = OILPAINT_HIST_STREAM;
+        v.waves = 1;
+        v.lanes = 64;
+        v.rows = 0;
+        v.per_cu = 8;
+    }
     if (is_stream(v.hist) && v.waves > 1 && j.radius < kBatchSplitMinRadius) {
         v.waves = 1;
         v.per_cu = 8;

@@ -143,6 +143,17 @@ __host__ __device__ inline size_t stream_colh_bytes(const Job& j) {
 // place or the runs are short enough (at most 4(2r+1) rows) for the first
 // window to matter more than the larger on-chip footprint.
 inline void set_layout(Job& j) {
+    if (j.hist == OILPAINT_HIST_REGS) {
+        // registers hold bins 0 .. scan-1 (levels rounded up to 8 or 16); the
+        // paper form's white level and outside pixels match no register
+        j.fast = 0;
+        j.scan = j.levels <= 8 ? 8 : 16;
+        j.white = j.scan;
+        j.trash = j.scan + (j.paper ? 1 : 0);
+        j.bins = j.trash + 1;
+        j.colfirst = 0;
+        return;
+    }
     if (j.hist == OILPAINT_HIST_COLUMN) {
         // levels 0 .. L-1, then one sink row for outside pixels and the
         // paper form's white level
@@ -191,6 +202,10 @@ extern const PlainKernel kStream8[8];
 extern const PlainKernel kStream8Split[8][4];
 extern const PlainKernel kStreamSplit_lo[8][5];
 extern const PlainKernel kStreamSplit_hi[8][5];
+// Register-histogram kernels (oilpaint_k_regs.hip): [radius][levels <= 8 ? 0 : 1].
+extern const PlainKernel kRegs[8][2];
+constexpr int kRegsMaxRadius = 7;
+constexpr int kRegsMaxLevels = 16;
 
 // Persistent batch kernels of the streamed layout (oilpaint_k_batch_*.hip),
 // indexed like kStream_*.

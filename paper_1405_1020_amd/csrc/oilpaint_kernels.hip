@@ -90,6 +90,7 @@ int g_split4_lds_done[kPackedMaxRadius + 1][5];
 int g_column_lds_done[kColumnChunks];
 int g_column15_lds_done[3][kColumn15Buckets];
 int g_plain_lds_done;
+int g_regs_lds_done;
 int g_batch_lds_done[kBatchClasses];
 
 BatchKernel batch_kernel(int cls) {
@@ -132,6 +133,11 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
         if (j.radius < 0 || j.radius > kPackedMaxRadius || b < 0 || j.waves != kSplitWaves) return hipErrorInvalidValue;
         k = j.radius <= 7 ? kStreamSplit_lo[j.radius][b] : kStreamSplit_hi[j.radius - 8][b];
         done = &g_split4_lds_done[j.radius][b];
+    } else if (j.hist == OILPAINT_HIST_REGS) {
+        if (j.radius < 0 || j.radius > kRegsMaxRadius || j.levels > kRegsMaxLevels || waves != 1)
+            return hipErrorInvalidValue;
+        k = kRegs[j.radius][j.levels <= 8 ? 0 : 1];
+        done = &g_regs_lds_done;
     } else if (j.hist == OILPAINT_HIST_STREAM8 && waves == kSplitWaves) {
         const int b = j.scan % kSplitWaves == 0 ? split_bucket(j.scan / kSplitWaves) : -1;
         if (j.radius < 8 || j.radius > kPackedMaxRadius || b < 0 || b > 3 || j.waves != kSplitWaves)

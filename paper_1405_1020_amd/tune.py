@@ -2,10 +2,11 @@
 
 For each (radius, levels) the candidates -- streamed rows with several
 workgroup densities (and, for radius 8..15 with at most 32 levels, the
-same with 8-byte on-chip row entries), tile-staged workgroups of 2 or 4
-wavefronts with several densities, column histograms for radii from 7
-(at most 33 levels; one, two or four wavefronts per strip) and above 15,
-and the wide layout above 15 -- are
+same with 8-byte on-chip row entries), histograms in registers for radius
+<= 7 and at most 16 levels, tile-staged workgroups of 2 or 4 wavefronts
+with several densities, column histograms for radii from 3 (at most 64
+levels; one, two or four wavefronts per strip) and above 15, and the wide
+layout above 15 -- are
 timed by the library itself (oilpaint_tune, HIP
 events around repeated launches on a representative image) and the fastest
 is installed with oilpaint_set_variant, so that oilpaint_async, batches and
@@ -59,6 +60,11 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
         # four wavefronts per strip
         for per_cu in (1, 2, 3, 4, 5, 8):
             out.append(B.Variant(0, 4, B.HIST_STREAM8, 64, per_cu))
+    if radius <= 7 and levels <= 16:
+        # each lane's histogram in its registers (window updates as VALU
+        # compare-selects over every bin instead of LDS atomics)
+        for per_cu in (2, 4, 8, 16, 32):
+            out.append(B.Variant(0, 1, B.HIST_REGS, 64, per_cu))
     if radius <= 15 and levels <= 255:
         for waves in (2, 4):
             for per_cu in (1, 2, 4, 8):
@@ -66,7 +72,7 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
     if radius > 15:
         for per_cu in (1, 2, 4, 8, 16):
             out.append(B.Variant(0, 1, B.HIST_COLUMN, 64, per_cu))
-    elif radius >= 7 and levels <= 33:
+    elif radius >= 3 and levels <= 64:
         # column histograms cost O(levels) per row (and 2r+1 reads for the
         # winning level): they can win at wide windows and few levels; one,
         # two or four wavefronts per strip

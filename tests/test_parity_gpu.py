@@ -93,12 +93,12 @@ def test_radius_larger_than_image():
 
 def test_every_variant_same_bytes():
     img = synth.make_image(333, 211, seed=77, n_blobs=8, sigma=(4, 40))
-    for r, L in [(2, 20), (7, 64), (15, 8), (9, 32)]:
+    for r, L in [(2, 20), (7, 64), (15, 8), (9, 32), (3, 16)]:
         want = ref(img, r, L)
         for rows in (1, 3, 8, 16, 64):
             for waves in (1, 2, 4, 8):
                 for lanes in (16, 32, 64):
-                    for hist in (B.HIST_PACKED, B.HIST_STREAM, B.HIST_WIDE, B.HIST_STREAM8):
+                    for hist in (B.HIST_PACKED, B.HIST_STREAM, B.HIST_WIDE, B.HIST_STREAM8, B.HIST_REGS):
                         v = B.Variant(rows, waves, hist, lanes)
                         try:
                             got = run_plain(img, r, L, pad=3, variant=v)
@@ -116,13 +116,15 @@ def test_stream_every_radius(r):
     for (w, h) in [(1, 1), (63, 2 * r + 1), (65, 2 * r + 3), (130, 57)]:
         img = synth.make_image(w, h, seed=100 + r + w, n_blobs=4, sigma=(2, 15)) if w * h > 100 else \
             synth.make_random(w, h, seed=100 + r + w)
-        want = {L: ref(img, r, L) for L in (1, 8, 20, 32, 33, 64)}
+        want = {L: ref(img, r, L) for L in (1, 8, 9, 16, 20, 32, 33, 64)}
         for rows in (1, 2, 5, 16, 300):
-            for L in (1, 8, 20, 32, 33, 64):
-                for hist, waves in ((B.HIST_STREAM, 1), (B.HIST_STREAM, 4), (B.HIST_STREAM8, 1), (B.HIST_STREAM8, 4)):
+            for L in (1, 8, 9, 16, 20, 32, 33, 64):
+                for hist, waves in ((B.HIST_STREAM, 1), (B.HIST_STREAM, 4), (B.HIST_STREAM8, 1), (B.HIST_STREAM8, 4),
+                                    (B.HIST_REGS, 1)):
                     v = B.Variant(rows, waves, hist, 64)
                     reff = min(r, max(w, h) - 1)
-                    if hist == B.HIST_STREAM8 and not (8 <= reff and L <= 32):
+                    if (hist == B.HIST_STREAM8 and not (8 <= reff and L <= 32)) or \
+                            (hist == B.HIST_REGS and not (reff <= 7 and L <= 16)):
                         with pytest.raises(B.OilpaintError) as e:
                             run_plain(img, r, L, pad=(w + rows) % 5, variant=v)
                         assert e.value.status == B.ERR_UNSUPPORTED
