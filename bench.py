@@ -50,6 +50,26 @@ HBM_COMMANDS = [
     "cd $REPO && python3 bench.py --hbm-summary $OUT --sweep-json $OUT/quick.json",
 ]
 LDS_PEAK_GBS = 256 * 2.4e9 * 256 / 1e9  # 256 CUs x 2.4 GHz x 256 B/clk LDS read path
+# Counter passes over the LDS and VALU units (one rocprofv3 --pmc run each,
+# with the kernel trace for durations), as bench.py --counter-summary reads
+# them: sub-folder name -> counters.
+COUNTER_PASSES = {
+    "derived": ["LdsUtil", "VALUBusy", "LdsBankConflict", "OccupancyPercent", "VALUUtilization"],
+    "lds": ["SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS", "SQ_WAVES",
+            "GRBM_GUI_ACTIVE"],
+    "valu": ["SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES",
+             "SQ_INSTS_SALU", "GRBM_GUI_ACTIVE"],
+}
+# GRBM_GUI_ACTIVE is counted by each of the GPU's XCDs and the raw output sums
+# them; rocprofiler-sdk's derived figures take their maximum.
+XCDS = 8
+COUNTER_WORKLOADS = {
+    "sweep": "bench.py --quick --steps 3 --warmup 1",
+    "camera": "bench.py --counter-workload camera",
+    "batched": "bench.py --counter-workload batched",
+}
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "lds_valu_counters.json")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "lds_valu_counters.md")
 
 
 def log(*a):
@@ -68,6 +88,62 @@ def lds_bytes_per_pixel(r: int, L: int) -> int:
 HBM_PROFILE = os.path.join(ROOT, "profiles", "k_plain_fhd_sweep_hbm.json")
 
 
+def lds_probe_leg(torch, B, iters: int = 2048, per_cu: int = 4) -> dict:
+    """Measured LDS rates of this GPU (oilpaint_lds_probe): four 256-lane
+    workgroups of 32 KB per CU, every wavefront issuing iters x 16 LDS
+    operations of one kind on distinct, conflict-free words.  Per CU and
+    shader clock (s_memtime between barriers, per workgroup, median): bytes
+    of 8-byte and of 4-byte reads, and clocks per 64-lane 64-bit atomic add.
+    The shader clock comes from the same counters against the 100 MHz real
+    time."""
+    import statistics
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"cus": cus, "iters": iters, "workgroups_per_cu": per_cu}
+    clocks_hz = []
+    for name, kind, lane_bytes in (("read64", B.PROBE_READ64, 8), ("read32", B.PROBE_READ32, 4),
+                                   ("add64", B.PROBE_ADD64, 0)):
+        B.lds_probe(kind, 64, per_cu)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        wg, clocks = B.lds_probe(kind, iters, per_cu)
+        e1.record()
+        torch.cuda.synchronize()
+        c = clocks.cpu().numpy().astype("float64")
+        cyc = c[:, 1] - c[:, 0]
+        real_s = (c[:, 3] - c[:, 2]) / 100e6
+        med_cyc = statistics.median(cyc.tolist())
+        hz = statistics.median((cyc / real_s).tolist())
+        clocks_hz.append(hz)
+        instr = per_cu * 4 * iters * 16  # per CU
+        per_clk = instr / med_cyc
+        e = {"workgroups": wg, "cycles_median": int(med_cyc), "clock_mhz": round(hz / 1e6, 1),
+             "kernel_ms": round(e0.elapsed_time(e1), 4), "instr_per_clk_per_cu": round(per_clk, 4),
+             "clk_per_instr": round(1.0 / per_clk, 3)}
+        if lane_bytes:
+            e["bytes_per_clk_per_cu"] = round(per_clk * 64 * lane_bytes, 1)
+        out[name] = e
+    hz = statistics.median(clocks_hz)
+    out["clock_mhz"] = round(hz / 1e6, 1)
+    out["read64_gbs"] = round(out["read64"]["bytes_per_clk_per_cu"] * cus * hz / 1e9, 1)
+    out["read32_gbs"] = round(out["read32"]["bytes_per_clk_per_cu"] * cus * hz / 1e9, 1)
+    out["add64_g_lane_ops"] = round(64 * out["add64"]["instr_per_clk_per_cu"] * cus * hz / 1e9, 1)
+    return out
+
+
+def lds_model_ms(r: int, L: int, pixels: float, rates: dict) -> float:
+    """Time the sliding method's LDS work would take at the measured LDS
+    rates: per output pixel U = 2(2r+1) bin updates (64-bit atomic adds, 64
+    lanes per instruction) and U staged-pixel reads (4 bytes, at the 4-byte
+    read rate), plus L bin reads (8 bytes, at the 8-byte read rate); spread
+    over every CU at the probe's shader clock."""
+    u = 2 * (2 * r + 1)
+    cyc = (u * rates["add64"]["clk_per_instr"] / 64.0 + 4.0 * u / rates["read32"]["bytes_per_clk_per_cu"] +
+           8.0 * L / rates["read64"]["bytes_per_clk_per_cu"])
+    return pixels * cyc / (rates["cus"] * rates["clock_mhz"] * 1e6) * 1e3
+
+
 def kernel_name(r: int, L: int, v) -> str:
     """Name of the plain kernel a (radius, levels, variant) launch runs, as
     the profiler reports it."""
@@ -81,6 +157,8 @@ def kernel_name(r: int, L: int, v) -> str:
         return "k_plain_stream<%d, %d>" % (r, 32 if scan <= 32 else 64)
     if v.hist == 3:  # streamed rows, 8-byte entries
         return "k_plain_stream8<%d>" % r
+    if v.hist == 5:  # histograms in registers
+        return "k_plain_regs<%d, %d>" % (r, 8 if L <= 8 else 16)
     if v.hist == 4 and r <= 15 and L <= 64:  # column histograms, radius <= 15 form
         words = 3 if L <= 9 else 7 if L <= 21 else 11 if L <= 33 else 22
         return "k_plain_column15<%d, %d>" % (words, v.waves)
@@ -93,7 +171,7 @@ def kernel_name(r: int, L: int, v) -> str:
 
 # Sources that define the plain kernels the sweep launches; the HBM counter
 # summary is valid while they are unchanged.
-SWEEP_KERNEL_SOURCES = ("oilpaint_internal.h", "oilpaint_device.h", "oilpaint_k_stream_lo.hip",
+SWEEP_KERNEL_SOURCES = ("oilpaint_internal.h", "oilpaint_device.h", "oilpaint_k_regs.hip", "oilpaint_k_stream_lo.hip",
                         "oilpaint_k_stream_hi.hip", "oilpaint_k_stream8.hip", "oilpaint_k_split.hip",
                         "oilpaint_k_split_lo.hip", "oilpaint_k_split_hi.hip", "oilpaint_k_fast_lo.hip",
                         "oilpaint_k_fast_hi.hip", "oilpaint_column.h", "oilpaint_k_column.hip")
@@ -181,24 +259,51 @@ def transfers(torch, img) -> dict:
     return out
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and counts, and the oracle's thread count: the
+    CPUs this process may run on, at most 16 (the host's share per GPU)."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    return {"model": model, "cpu_count": os.cpu_count(), "affinity": aff, "threads": max(1, min(16, aff))}
+
+
 def oracle_timings(oracle_mod, synth, threads: int) -> dict:
-    """The oracle on the 256x256 case, one thread and all threads, and on one
-    1920x1080 run (r = 5, L = 20) on one thread: the paper's serial and
-    row-parallel forms (context beside cpu_baseline)."""
+    """The oracle in the paper's two forms (Section 4's serial loop, T1;
+    Section 5's row-parallel loop, T2, here row bands on `threads` threads):
+    one thread on the 256x256 case and on the whole 1920x1080 sweep; all
+    threads on the 256x256 case, the 4000x3000 camera image and the 64-image
+    batch (the 1920x1080 sweep on all threads is cpu_baseline)."""
     out = {}
-    small, r, L = synth.small_case()
-    for name, th in (("256x256_r2_L20_1thread", 1), ("256x256_r2_L20_allthreads", threads)):
+
+    def timed(name, imgs_rl, th):
         t0 = time.perf_counter()
-        oracle_mod.oilpaint_ref(small, r, L, nthreads=th)
+        px = 0
+        for img, r, L in imgs_rl:
+            oracle_mod.oilpaint_ref(img, r, L, nthreads=th)
+            px += img.shape[0] * img.shape[1]
         dt = time.perf_counter() - t0
-        out[name] = {"s": round(dt, 4), "mp_per_s": round(small.shape[0] * small.shape[1] / 1e6 / dt, 3),
-                     "threads": th}
-    img = synth.fhd_image()
-    t0 = time.perf_counter()
-    oracle_mod.oilpaint_ref(img, 5, 20, nthreads=1)
-    dt = time.perf_counter() - t0
-    out["1920x1080_r5_L20_1thread"] = {"s": round(dt, 3), "mp_per_s": round(img.shape[0] * img.shape[1] / 1e6 / dt, 3),
-                                       "threads": 1}
+        out[name] = {"s": round(dt, 3), "mp_per_s": round(px / 1e6 / dt, 3), "threads": th,
+                     "megapixels": round(px / 1e6, 2)}
+    small, r, L = synth.small_case()
+    fhd = synth.fhd_image()
+    timed("256x256_r2_L20_T1", [(small, r, L)], 1)
+    timed("256x256_r2_L20_T2", [(small, r, L)], threads)
+    timed("1920x1080_sweep_T1", [(fhd, r_, L_) for r_, L_ in synth.FHD_SWEEP], 1)
+    timed("4000x3000_r10_L32_T2", [(synth.camera_image(),) + tuple(synth.CAMERA_RL)], threads)
+    batch = [(synth.batch_image(it).cpu().numpy(), it.radius, it.levels) for it in synth.batch_items()]
+    timed("batch64_T2", batch, threads)
+    for name in ("256x256_r2_L20", ):
+        out[name + "_speedup_T1_over_T2"] = round(out[name + "_T1"]["s"] / out[name + "_T2"]["s"], 2)
     return out
 
 
@@ -300,6 +405,93 @@ def bench_median(torch, B, synth, timer, oracle_mod, threads: int) -> dict:
     return out
 
 
+def bench_register_histograms(B, tune) -> dict:
+    """Histograms in registers (OILPAINT_HIST_REGS) against the tuned launch
+    shape, on a 1920x1080 tuning image (the library's photo-like fill), by
+    the library's own timer: the fastest register-histogram density and the
+    tuned shape's time, per (r, L)."""
+    out = {}
+    for r, L in ((1, 8), (2, 8), (3, 8), (5, 8), (1, 16), (2, 16), (3, 16), (5, 16)):
+        regs = [v for v in tune.candidates(r, L) if v.hist == B.HIST_REGS]
+        t_regs = B.tune_times(1920, 1080, r, L, regs, reps=5)
+        tuned = B.pick_variant(1920, 1080, r, L)
+        t_tuned = B.tune_times(1920, 1080, r, L, [tuned], reps=5)[0]
+        k = min((i for i in range(len(regs)) if t_regs[i] >= 0), key=lambda i: t_regs[i])
+        out["r%d_L%d" % (r, L)] = {"regs_ms": round(t_regs[k], 4), "regs_per_cu": regs[k].per_cu,
+                                   "tuned_ms": round(t_tuned, 4), "tuned_variant": list(tuned.as_tuple()),
+                                   "regs_over_tuned": round(t_regs[k] / t_tuned, 2)}
+    return out
+
+
+PAPER_SIZES = ((640, 480), (800, 600), (1024, 768), (1920, 1080), (2560, 1600))
+
+
+def bench_jpeg(torch, B, synth, oracle_mod, threads: int, reps: int = 5) -> dict:
+    """The paper's program around the filter (Section 3: decode a JPEG file,
+    filter, encode; the three steps timed apart), at the paper's image sizes
+    and radii (r = 2, 4, 6, 8; L = 20, the paper states none): a JPEG file in
+    host memory (the blob image at that size, encoded by PIL at quality 90,
+    4:2:0) is decoded onto the device (host entropy decoding, upload,
+    inverse DCT and colour kernels), filtered there, and encoded from there
+    (colour, FDCT and quantization kernels, download, host entropy coding,
+    same quality and subsampling).  Each step is timed on the host clock
+    around the call and a device synchronization (median of `reps`); the host
+    entropy-coding share of decode and encode is reported beside it.  The
+    filter's output on the 1920x1080 decoded image is checked against the
+    oracle on those decoded pixels."""
+    import io
+    import statistics
+    import numpy as np
+    from PIL import Image
+    out = {"format": "baseline JPEG, quality 90, 4:2:0 (input by PIL; output by this library)", "L": 20,
+           "sizes": {}}
+    for w, h in PAPER_SIZES:
+        img = synth.make_image(w, h, seed=w, **synth.LARGE_BLOBS)
+        b = io.BytesIO()
+        Image.fromarray(img).save(b, format="JPEG", quality=90, subsampling=2)
+        data = b.getvalue()
+        dev = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(dev)
+        dec, dec_host, enc, enc_host = [], [], [], []
+        proc = {r: [] for r in (2, 4, 6, 8)}
+        for k in range(reps + 1):
+            t = {}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.jpeg_decode(data, out=dev, times=t)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            dh = t["host_ms"]
+            for r in proc:
+                t2 = time.perf_counter()
+                B.oilpaint_async(dev, dst, r, 20)
+                torch.cuda.synchronize()
+                if k:
+                    proc[r].append((time.perf_counter() - t2) * 1e3)
+            t3 = time.perf_counter()
+            enc_bytes = B.jpeg_encode(dst, quality=90, subsampling=2, times=t)
+            t4 = time.perf_counter()
+            if k:  # the first round warms up
+                dec.append((t1 - t0) * 1e3)
+                dec_host.append(dh)
+                enc.append((t4 - t3) * 1e3)
+                enc_host.append(t["host_ms"])
+        mp = w * h / 1e6
+        e = {"jpeg_bytes": len(data), "encoded_bytes": len(enc_bytes),
+             "decode_ms": round(statistics.median(dec), 3), "decode_host_entropy_ms": round(statistics.median(dec_host), 3),
+             "encode_ms": round(statistics.median(enc), 3), "encode_host_entropy_ms": round(statistics.median(enc_host), 3),
+             "process_ms": {"r%d" % r: round(statistics.median(v), 4) for r, v in proc.items()}}
+        e["decode_mp_per_s"] = round(mp / (e["decode_ms"] / 1e3), 1)
+        e["encode_mp_per_s"] = round(mp / (e["encode_ms"] / 1e3), 1)
+        if (w, h) == (1920, 1080):
+            B.oilpaint_async(dev, dst, 2, 20)
+            torch.cuda.synchronize()
+            want = oracle_mod.oilpaint_ref(dev.cpu().numpy(), 2, 20, nthreads=threads)
+            e["filter_on_decoded_pixels_differing"] = int((dst.cpu().numpy() != want).any(axis=-1).sum())
+        out["sizes"]["%dx%d" % (w, h)] = e
+    return out
+
+
 def bench_batched(torch, B, synth, timer, reps):
     specs = synth.batch_items()
     srcs = [synth.batch_image(it) for it in specs]
@@ -320,9 +512,16 @@ def bench_batched(torch, B, synth, timer, reps):
     ms_batch = timer.time(lambda: B.batch(items), reps, 2)
     same = same and all(torch.equal(a, b) for a, b in zip(ref, dsts))
     plan.close()
+    model = sum(lds_bytes_per_pixel(it.radius, it.levels) * it.width * it.height for it in specs)
+
+    def frac(ms):
+        return round(model / (ms / 1e3) / 1e9 / LDS_PEAK_GBS, 4)
     return {
         "workload": "64 images, W~U{320..4096}, H~U{240..3072}, r~U{2,3,5,8}, L~U{16,20,32}",
         "megapixels": round(mp, 2),
+        "model_lds_bytes": model,
+        "graph_roofline_frac": frac(ms_graph), "plain_roofline_frac": frac(ms_plain),
+        "batch_call_roofline_frac": frac(ms_batch),
         "plain_ms": round(ms_plain, 4), "plain_mp_per_s": round(mp / (ms_plain / 1e3), 1),
         "graph_ms": round(ms_graph, 4), "graph_mp_per_s": round(mp / (ms_graph / 1e3), 1),
         "batch_call_ms": round(ms_batch, 4), "batch_call_mp_per_s": round(mp / (ms_batch / 1e3), 1),
@@ -332,7 +531,7 @@ def bench_batched(torch, B, synth, timer, reps):
     }
 
 
-def bench_serving(torch, B, synth, serve, n_requests, oracle_mod):
+def bench_serving(torch, B, synth, serve, n_requests, oracle_mod, oracle_threads: int):
     wl = synth.serve_workload(n=n_requests)
     torch.cuda.synchronize()
     budget = 32 * (1 << 30)
@@ -368,26 +567,25 @@ def bench_serving(torch, B, synth, serve, n_requests, oracle_mod):
     torch.cuda.synchronize()
     import numpy as np
     rng = np.random.default_rng(5)
-    # a seeded 5 % of the requests, 8 pixels each (two corners, six random)
-    sample = [rs_q[i] for i in rng.choice(len(rs_q), size=max(1, len(rs_q) // 20), replace=False)]
+    # whole outputs against the oracle: every request of at most 0.5 MP, and
+    # a seeded 5 % of the larger ones
+    small = [q for q in rs_q if q.pixels <= 500_000]
+    large = [q for q in rs_q if q.pixels > 500_000]
+    pick_l = sorted(rng.choice(len(large), size=max(1, len(large) // 20), replace=False).tolist()) if large else []
+    sample = small + [large[i] for i in pick_l]
     oracle_ok = 0
-    checked = 0
+    t0 = time.perf_counter()
     for q in sample:
-        h, w = q.height, q.width
-        pts = [(0, 0), (w - 1, h - 1)] + [(int(rng.integers(0, w)), int(rng.integers(0, h))) for _ in range(6)]
-        for x, y in pts:
-            r = q.radius
-            y0, y1, x0, x1 = max(0, y - r), min(h, y + r + 1), max(0, x - r), min(w, x + r + 1)
-            crop = q.src[y0:y1, x0:x1].contiguous().cpu().numpy()
-            want = oracle_mod.oilpaint_ref(crop, r, q.levels)[y - y0, x - x0]
-            got = q.dst[y, x].cpu().numpy()
-            oracle_ok += int((want == got).all())
-            checked += 1
+        img = q.src.contiguous().cpu().numpy()
+        want = oracle_mod.oilpaint_ref(img, q.radius, q.levels, nthreads=oracle_threads)
+        oracle_ok += int(np.array_equal(want, q.dst.cpu().numpy()))
+    oracle_s = time.perf_counter() - t0
     for q in rs_q:
         q.dst = None
     torch.cuda.synchronize()
     sat_q, _ = one("queue", True)
     sat_p, _ = one("plain", True)
+    model = sum(lds_bytes_per_pixel(q.radius, q.levels) * q.width * q.height for q in wl.requests)
 
     def pick(st):
         return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()
@@ -399,24 +597,28 @@ def bench_serving(torch, B, synth, serve, n_requests, oracle_mod):
         "p99_gain": round(st_p["p99_ms"] / st_q["p99_ms"], 3) if st_q["p99_ms"] > 0 else None,
         "saturation_mp_gain": round(sat_q["mp_per_s"] / sat_p["mp_per_s"], 3) if sat_p["mp_per_s"] > 0 else None,
         "outputs_equal_plain": "%d/%d" % (equal, len(rs_q)),
-        "oracle_pixels": "%d/%d" % (oracle_ok, checked),
+        "oracle_outputs": "%d/%d" % (oracle_ok, len(sample)),
+        "oracle_sample": "whole outputs of all %d requests <= 0.5 MP and a seeded 5 %% (%d) of the %d larger "
+                         "ones, %.1f MP, %.1f s on %d threads" % (len(small), len(pick_l), len(large),
+                                                                 sum(q.pixels for q in sample) / 1e6, oracle_s,
+                                                                 oracle_threads),
+        "model_lds_bytes": model,
+        "saturation_roofline_frac": round(model / sat_q["span_s"] / 1e9 / LDS_PEAK_GBS, 4),
+        "saturation_plain_roofline_frac": round(model / sat_p["span_s"] / 1e9 / LDS_PEAK_GBS, 4),
     })
     return out
 
 
-def cpu_baseline(oracle_mod, img, runs):
-    try:
-        ncpu = len(os.sched_getaffinity(0))
-    except AttributeError:
-        ncpu = os.cpu_count() or 1
-    threads = max(1, min(16, ncpu))
+def cpu_baseline(oracle_mod, img, runs, cpu: dict):
+    threads = cpu["threads"]
     t0 = time.perf_counter()
     for r, L in runs:
         oracle_mod.oilpaint_ref(img, r, L, nthreads=threads)
     dt = time.perf_counter() - t0
     mp = img.shape[0] * img.shape[1] / 1e6 * len(runs)
     return {"value": round(mp / dt, 3), "unit": "MP/s", "cores": threads, "kind": "oracle",
-            "sample": "the full 1920x1080 sweep (7 runs), row bands over %d threads, %.1f s wall" % (threads, dt)}
+            "sample": "the full 1920x1080 sweep (7 runs), row bands over %d threads, %.1f s wall" % (threads, dt),
+            "cpu_model": cpu["model"], "host_cpus": cpu["cpu_count"], "affinity_cpus": cpu["affinity"]}
 
 
 def hbm_traffic(kernel: str, config: str, variant=None):
@@ -584,6 +786,214 @@ def write_hbm_summary(folder: str, sweep_json: str, commands: list[str]):
     print(json.dumps(out))
 
 
+def _pmc_all(folder: str):
+    """{(file, dispatch id): {"kernel", "grid", counter: value, ...}} from a
+    rocprofv3 --pmc CSV output under `folder`."""
+    import csv
+    import glob
+    out = {}
+    for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        for row in csv.DictReader(open(f)):
+            key = (f, int(row.get("Dispatch_Id", 0) or 0))
+            e = out.setdefault(key, {"kernel": _kernel_short_name(row["Kernel_Name"]),
+                                     "grid": int(row.get("Grid_Size", 0) or 0)})
+            e[row["Counter_Name"]] = e.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    return out
+
+
+def _trace_by_kernel(folder: str) -> dict:
+    """{(kernel, grid): [durations in ns]} from a --kernel-trace output."""
+    out = {}
+    for _, _, k, g, d in _trace_rows(folder):
+        out.setdefault((k, g), []).append(d)
+    return out
+
+
+def counter_metrics(disp: list, durations_ns: list, cus: int, pixels: float) -> dict:
+    """Figures of a group of dispatches of one kernel (counters averaged per
+    dispatch).  rocprofiler-sdk's own gfx950 metrics where the derived pass
+    recorded them (LdsUtil, VALUBusy and OccupancyPercent in per cent,
+    LdsBankConflict as a ratio, VALUUtilization in per cent); else the same
+    definitions from the raw counters: LdsUtil = LDS_IDX_ACTIVE /
+    (GRBM_GUI_ACTIVE x CUs), LdsBankConflict = BANK_CONFLICT /
+    (LDS_IDX_ACTIVE - BANK_CONFLICT), VALUBusy = ACTIVE_INST_VALU / (CUs x
+    GRBM_GUI_ACTIVE), VALUUtilization = THREAD_CYCLES_VALU /
+    (ACTIVE_INST_VALU x 64), occupancy = 4 x WAVE_CYCLES / (GRBM_GUI_ACTIVE
+    x CUs x 32), with GRBM_GUI_ACTIVE per XCD (the raw sum over XCDS)."""
+    import statistics
+
+    def mean(c):
+        vals = [d[c] for d in disp if c in d]
+        return statistics.fmean(vals) if vals else None
+    m = {c: mean(c) for c in set().union(*[set(d) for d in disp]) if c not in ("kernel", "grid")}
+    gui = m.get("GRBM_GUI_ACTIVE")
+    if gui:
+        gui /= XCDS
+    out = {"dispatches": len(disp)}
+    if durations_ns:
+        out["trace_mean_us"] = round(statistics.fmean(durations_ns) / 1e3, 2)
+    if gui:
+        if m.get("SQ_LDS_IDX_ACTIVE") is not None:
+            out["lds_util"] = round(m["SQ_LDS_IDX_ACTIVE"] / (gui * cus), 4)
+            act = m["SQ_LDS_IDX_ACTIVE"] - m.get("SQ_LDS_BANK_CONFLICT", 0.0)
+            if act > 0:
+                out["lds_bank_conflict_rate"] = round(m.get("SQ_LDS_BANK_CONFLICT", 0.0) / act, 4)
+        if m.get("SQ_ACTIVE_INST_VALU") is not None:
+            out["valu_busy"] = round(m["SQ_ACTIVE_INST_VALU"] / (cus * gui), 4)
+            if m["SQ_ACTIVE_INST_VALU"] > 0 and m.get("SQ_THREAD_CYCLES_VALU") is not None:
+                out["valu_utilization"] = round(m["SQ_THREAD_CYCLES_VALU"] / (m["SQ_ACTIVE_INST_VALU"] * 64), 4)
+        if m.get("SQ_WAVE_CYCLES") is not None:
+            out["occupancy"] = round(4 * m["SQ_WAVE_CYCLES"] / (gui * cus * 32), 4)
+    if pixels:
+        for c, k in (("SQ_INSTS_LDS", "lds_insts_per_pixel"), ("SQ_INSTS_VALU", "valu_insts_per_pixel"),
+                     ("SQ_INSTS_SALU", "salu_insts_per_pixel")):
+            if m.get(c) is not None:
+                out[k] = round(m[c] / pixels, 3)
+    # rocprofiler-sdk's own figures, where recorded, take precedence
+    for c, k, scale in (("LdsUtil", "lds_util", 0.01), ("VALUBusy", "valu_busy", 0.01),
+                        ("LdsBankConflict", "lds_bank_conflict_rate", 1.0), ("OccupancyPercent", "occupancy", 0.01),
+                        ("VALUUtilization", "valu_utilization", 0.01)):
+        if m.get(c) is not None:
+            if k in out:
+                out[k + "_raw"] = out[k]
+            out[k] = round(m[c] * scale, 4)
+    if "lds_util" in out and "valu_busy" in out:
+        out["binding_unit"] = "lds" if out["lds_util"] >= out["valu_busy"] else "valu"
+    out["counters_mean"] = {c: round(v, 1) for c, v in sorted(m.items()) if v is not None}
+    return out
+
+
+def write_counter_summary(folder: str, sweep_json: str, cus: int = 256):
+    """Per sweep run (and per kernel of the camera and batched workloads) the
+    LDS and VALU counters of COUNTER_PASSES, from rocprofv3 --pmc runs in the
+    sub-folders <workload>_<pass> of `folder` (COUNTER_WORKLOADS), into
+    profiles/lds_valu_counters.json and .md."""
+    from paper_1405_1020_amd import synth
+    runs = sweep_runs(sweep_json)
+    line = [x for x in open(sweep_json).read().splitlines() if x.startswith("{")][-1]
+    per = json.loads(line)["sweep"]
+    out = {"kernel_source_sha": kernel_source_hash(), "cus": cus,
+           "passes": COUNTER_PASSES, "workloads": COUNTER_WORKLOADS, "sweep": {}, "camera": {}, "batched": {}}
+    # sweep: attribute dispatches to runs as the HBM summary does
+    sweep_disp = {}
+    sweep_dur = {}
+    for pname in COUNTER_PASSES:
+        sub = os.path.join(folder, "sweep_" + pname)
+        allc = _pmc_all(sub)
+        rows = sorted((f, i, e["kernel"], e["grid"], e) for (f, i), e in allc.items())
+        vals = sweep_run_values(rows, [(n, k, g) for n, k, g, _ in runs])
+        for n in vals:
+            sweep_disp.setdefault(n, []).extend(vals[n])
+        tr = sweep_run_values(_trace_rows(sub), [(n, k, g) for n, k, g, _ in runs])
+        for n in tr:
+            sweep_dur.setdefault(n, []).extend(tr[n])
+    for n, k, g, v in runs:
+        e = counter_metrics(sweep_disp.get(n, []), sweep_dur.get(n, []), cus, 1920 * 1080)
+        e.update({"kernel": k, "variant": v, "event_ms": per[n]["ms"]})
+        out["sweep"][n] = e
+    camera_px = 4000 * 3000
+    batch_px = sum(it.width * it.height for it in synth.batch_items())
+    for wl, px in (("camera", camera_px), ("batched", batch_px)):
+        groups, durs = {}, {}
+        for pname in COUNTER_PASSES:
+            sub = os.path.join(folder, wl + "_" + pname)
+            for (_, _), e in _pmc_all(sub).items():
+                if e["kernel"].startswith(("k_plain", "k_batch")):
+                    groups.setdefault(e["kernel"], []).append(e)
+            for (k, g), d in _trace_by_kernel(sub).items():
+                if k.startswith(("k_plain", "k_batch")):
+                    durs.setdefault(k, []).extend(d)
+        for k, disp in groups.items():
+            out[wl][k] = counter_metrics(disp, durs.get(k, []), cus, px if wl == "camera" else 0)
+    with open(COUNTER_PROFILE, "w") as f:
+        json.dump(out, f, indent=1)
+    md = ["# LDS and VALU counters: 1920x1080 sweep, 4000x3000 camera, 64-image batch", "",
+          "Counter passes (one `rocprofv3 --pmc` run each, with `--kernel-trace` for durations), per workload "
+          "(`$REPO` the repository root, `$OUT` an output folder; the first line fills the tuning cache and "
+          "records the sweep's launch shapes):", "", "```",
+          "python3 bench.py --quick --steps 20 --warmup 3 > $OUT/quick.json", "cd /tmp && export TMPDIR=/tmp"]
+    for wl, cmd in COUNTER_WORKLOADS.items():
+        for pname, cs in COUNTER_PASSES.items():
+            md.append("timeout -s KILL 120 rocprofv3 --kernel-trace --pmc %s -d $OUT/%s_%s --output-format csv -- "
+                      "python3 $REPO/%s" % (" ".join(cs), wl, pname, cmd))
+    md += ["cd $REPO && python3 bench.py --counter-summary $OUT --sweep-json $OUT/quick.json", "```", "",
+           "Figures per dispatch (averages over a kernel's dispatches; %d CUs): LDS busy, bank conflicts, VALU "
+           "busy, VALU lanes and occupancy are rocprofiler-sdk's gfx950 metrics LdsUtil (SQ_LDS_IDX_ACTIVE / "
+           "(GRBM_GUI_ACTIVE x CUs)), LdsBankConflict (SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - "
+           "SQ_LDS_BANK_CONFLICT)), VALUBusy (SQ_ACTIVE_INST_VALU / (GRBM_GUI_ACTIVE x CUs)), VALUUtilization "
+           "(SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU)) and OccupancyPercent (4 x SQ_WAVE_CYCLES / "
+           "(GRBM_GUI_ACTIVE x CUs x 32)), from the derived pass; instructions per output pixel from the raw "
+           "passes (SQ_INSTS_LDS, SQ_INSTS_VALU: wavefront instructions). Traced us: the kernel trace of the "
+           "counter runs (counter collection serializes and slows dispatches a little). The binding unit is the "
+           "busier of LDS and VALU." % cus, "",
+           "| Workload | Kernel | Dispatches | Traced us | LDS busy | Bank conflicts | VALU busy | "
+           "VALU lanes | Occupancy | LDS instr/px | VALU instr/px | Binding |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+
+    def row(wl, k, e):
+        def f(x, pct=False):
+            if x is None:
+                return "-"
+            return "%.1f %%" % (100 * x) if pct else str(x)
+        return "| %s | `%s` | %s | %s | %s | %s | %s | %s | %s | %s | %s | %s |" % (
+            wl, k, e.get("dispatches"), f(e.get("trace_mean_us")),
+            f(e.get("lds_util"), True), f(e.get("lds_bank_conflict_rate"), True), f(e.get("valu_busy"), True),
+            f(e.get("valu_utilization"), True), f(e.get("occupancy"), True), f(e.get("lds_insts_per_pixel")),
+            f(e.get("valu_insts_per_pixel")), e.get("binding_unit", "-"))
+    for n, e in out["sweep"].items():
+        md.append(row("sweep " + n, e["kernel"], e))
+    for wl in ("camera", "batched"):
+        for k, e in sorted(out[wl].items()):
+            md.append(row(wl, k, e))
+    md += ["", "Kernel source hash of these figures: `%s`." % out["kernel_source_sha"], ""]
+    with open(COUNTER_SUMMARY, "w") as f:
+        f.write("\n".join(md))
+    print(json.dumps(out))
+
+
+def counter_fields(run: str):
+    """Counter-derived figures of a sweep run from the committed summary, if
+    it was taken on the current kernel sources (else None)."""
+    try:
+        d = json.load(open(COUNTER_PROFILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    e = d.get("sweep", {}).get(run)
+    if not e:
+        return None
+    return {k: e[k] for k in ("lds_util", "lds_bank_conflict_rate", "valu_busy", "valu_utilization", "occupancy",
+                              "binding_unit", "kernel") if k in e}
+
+
+def counter_workload(name: str, torch, B, synth):
+    """The camera (4000x3000, r = 10, L = 32: five plain launches) or the
+    64-image batch (three replays of its captured plan), after tuning, for
+    the counter passes."""
+    from paper_1405_1020_amd import tune
+    if name == "camera":
+        tune.ensure([synth.CAMERA_RL], 4000, 3000)
+        src = torch.from_numpy(synth.camera_image()).cuda()
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            B.oilpaint_async(src, dst, *synth.CAMERA_RL)
+    elif name == "batched":
+        tune.ensure([(r, L) for r in (2, 3, 5, 8) for L in (16, 20, 32)], 2048, 1536)
+        specs = synth.batch_items()
+        srcs = [synth.batch_image(it) for it in specs]
+        items = [B.Item(s_, torch.empty_like(s_), it.radius, it.levels) for s_, it in zip(srcs, specs)]
+        plan = B.Plan(items)
+        for _ in range(3):
+            plan.launch()
+        torch.cuda.synchronize()
+        plan.close()
+    else:
+        raise ValueError(name)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_workload": name}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -597,6 +1007,10 @@ def main():
                     help="write the HBM counter summary under profiles/ from rocprofv3 --pmc outputs in DIR")
     ap.add_argument("--trace-summary", metavar="DIR",
                     help="print per sweep run the kernel-trace durations from rocprofv3 --kernel-trace output in DIR")
+    ap.add_argument("--counter-summary", metavar="DIR",
+                    help="write the LDS/VALU counter summary under profiles/ from the counter passes in DIR")
+    ap.add_argument("--counter-workload", choices=["camera", "batched"],
+                    help="run only that workload (for a counter pass) and exit")
     ap.add_argument("--sweep-json", metavar="FILE",
                     help="with --hbm-summary or --trace-summary: the output of the profiled bench.py --quick run")
     args = ap.parse_args()
@@ -604,6 +1018,11 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.counter_summary:
+        if not args.sweep_json:
+            ap.error("--sweep-json is required with --counter-summary")
+        write_counter_summary(args.counter_summary, args.sweep_json)
+        return
     if args.hbm_summary or args.trace_summary:
         if not args.sweep_json:
             ap.error("--sweep-json is required with --hbm-summary and --trace-summary")
@@ -617,6 +1036,10 @@ def main():
     from paper_1405_1020_amd import binding as B, synth, serve
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B.lib()
+
+    if args.counter_workload:
+        counter_workload(args.counter_workload, torch, B, synth)
+        return
 
     if args.copy_ref:
         n = 1 << 30
@@ -656,6 +1079,20 @@ def main():
                        "traffic": hbm_traffic(d["kernel"], dom, d["variant"]), "kernel": d["kernel"], "run": dom,
                        "lds_bytes_per_launch": d_bytes, "avg_launch_ms": d["ms"],
                        "sweep_achieved": round(achieved, 1), "sweep_avg_launch_ms": round(launch_ms, 5)}
+    # the same LDS work priced at this GPU's measured LDS rates, and the
+    # counters of the committed summary (when taken on these sources)
+    log("lds probe ...")
+    rates = lds_probe_leg(torch, B)
+    px = img.shape[0] * img.shape[1]
+    for name, e in per.items():
+        e["lds_model_ms_measured_rates"] = round(lds_model_ms(e["r"], e["L"], px, rates), 5)
+        e["lds_frac_measured_rates"] = round(e["lds_model_ms_measured_rates"] / e["ms"], 4)
+        c = counter_fields(name)
+        if c:
+            e["counters"] = c
+    res["roofline"]["measured_lds_rates"] = rates
+    res["roofline"]["frac_at_measured_rates"] = d["lds_frac_measured_rates"]
+    res["roofline"]["counters"] = counter_fields(dom)
     res["sweep"] = per
     res["tuned_variants"] = tuned
     if not args.quick:
@@ -669,13 +1106,18 @@ def main():
         log("large radii ...")
         res["large_radius_1920x1080"] = bench_large_radius(torch, B, synth, timer, oracle_mod)
         log("median ...")
-        res["median_1920x1080_channel1"] = bench_median(torch, B, synth, timer, oracle_mod,
-                                                        max(1, min(16, len(os.sched_getaffinity(0)))))
+        cpu = host_cpu()
+        res["median_1920x1080_channel1"] = bench_median(torch, B, synth, timer, oracle_mod, cpu["threads"])
+        log("register histograms ...")
+        from paper_1405_1020_amd import tune as tune_mod
+        res["register_histograms_1920x1080"] = bench_register_histograms(B, tune_mod)
+        log("jpeg ...")
+        res["jpeg_decode_process_encode"] = bench_jpeg(torch, B, synth, oracle_mod, cpu["threads"])
         log("serving ...")
-        res["serving"] = bench_serving(torch, B, synth, serve, args.serve_requests, oracle_mod)
+        res["serving"] = bench_serving(torch, B, synth, serve, args.serve_requests, oracle_mod, cpu["threads"])
         log("cpu baseline ...")
-        res["cpu_baseline"] = cpu_baseline(oracle_mod, img, synth.FHD_SWEEP)
-        res["oracle_timings"] = oracle_timings(oracle_mod, synth, res["cpu_baseline"]["cores"])
+        res["cpu_baseline"] = cpu_baseline(oracle_mod, img, synth.FHD_SWEEP, cpu)
+        res["oracle_timings"] = oracle_timings(oracle_mod, synth, cpu["threads"])
         res["transfers_1920x1080"] = transfers(torch, img)
         # parity of the timed configuration: the sweep's outputs against the oracle
         bad = 0

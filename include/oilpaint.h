@@ -444,6 +444,28 @@ int oilpaint_jpeg_encode_info(int width, int height, int quality, int subsamplin
 int oilpaint_jpeg_write(const int16_t *coef, int width, int height, int quality, int subsampling, uint8_t *out,
                         size_t capacity, size_t *out_len);
 
+/* ---------------------------------------------------------------------------
+ * LDS rate probe (measurement, not part of the filter).  The filter's sliding
+ * window is bound by LDS instruction throughput (its bin updates are 64-bit
+ * LDS atomics, its mode search reads bins from LDS); this probe measures the
+ * rates its roofline is priced against on the GPU at hand.
+ * ------------------------------------------------------------------------- */
+#define OILPAINT_PROBE_READ64 0 /* 8-byte LDS reads, 64 consecutive words per instruction */
+#define OILPAINT_PROBE_ADD64 1  /* 64-bit LDS atomic adds, result unused */
+#define OILPAINT_PROBE_READ32 2 /* 4-byte LDS reads */
+
+/* Enqueue on `stream` a kernel of per_cu (1..4) workgroups of 256 lanes per
+ * CU, each holding 32 KB of LDS; each of its four wavefronts issues iters x 16
+ * 64-lane LDS operations of kind `kind` (OILPAINT_PROBE_*) on distinct
+ * words.  Workgroup w writes, from its first wavefront between two barriers
+ * around the loop, the shader clock (s_memtime) at start and end and the
+ * 100 MHz real-time counter at start and end to clocks[4w .. 4w+3] (device
+ * memory, at least 4 x max_workgroups uint64).  *workgroups receives the
+ * grid size (per_cu x CUs); ERR_ARG if it exceeds max_workgroups or an
+ * argument is out of range, ERR_NOT_DEVICE if clocks is not device memory. */
+int oilpaint_lds_probe(int kind, int iters, int per_cu, uint64_t *clocks, int max_workgroups, int *workgroups,
+                       void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,8 @@ _SIGS = {
                        ctypes.c_int),
     "oilpaint_batch_noalloc": ([ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
                                ctypes.c_int),
+    "oilpaint_lds_probe": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                            ctypes.POINTER(ctypes.c_int), ctypes.c_void_p], ctypes.c_int),
     "oilpaint_jpeg_header": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "oilpaint_jpeg_coefficients": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -473,6 +475,24 @@ def jpeg_encode(src, quality: int = 90, subsampling: int = 2, stream=None, times
     if times is not None:
         times["host_ms"] = ms.value
     return _jpeg_out[:n.value].tobytes()
+
+
+PROBE_READ64 = 0
+PROBE_ADD64 = 1
+PROBE_READ32 = 2
+
+
+def lds_probe(kind: int, iters: int, per_cu: int = 4, stream=None):
+    """oilpaint_lds_probe: returns (workgroups, clocks) with clocks a device
+    tensor [workgroups, 4] (shader clock start/end, 100 MHz real time
+    start/end per workgroup), after the kernel has run."""
+    torch = _torch()
+    n = 4096
+    clocks = torch.zeros((n, 4), dtype=torch.int64, device="cuda")
+    wg = ctypes.c_int(0)
+    _check(lib().oilpaint_lds_probe(kind, iters, per_cu, clocks.data_ptr(), n, ctypes.byref(wg),
+                                    _stream_ptr(stream)), "oilpaint_lds_probe")
+    return wg.value, clocks[:wg.value]
 
 
 class Plan:

@@ -62,3 +62,23 @@ def test_sweep_run_values_files_and_uneven_blocks():
     out = bench.sweep_run_values(rows, runs)
     assert out["b"] == [1.0, 4.0]
     assert out["c"] == [2.0, 5.0]
+
+
+def test_counter_metrics_per_xcd_and_sdk_precedence():
+    # raw counters of two dispatches: GRBM_GUI_ACTIVE is the sum over the
+    # XCDs, so per XCD it is 1/XCDS of it
+    cus = 256
+    gui = 1000.0 * bench.XCDS
+    d = [{"kernel": "k", "grid": 1, "GRBM_GUI_ACTIVE": gui, "SQ_LDS_IDX_ACTIVE": 0.5 * 1000 * cus,
+          "SQ_LDS_BANK_CONFLICT": 0.1 * 1000 * cus, "SQ_ACTIVE_INST_VALU": 0.25 * 1000 * cus,
+          "SQ_INSTS_LDS": 64.0, "SQ_INSTS_VALU": 128.0}] * 2
+    e = bench.counter_metrics(d, [1000.0, 3000.0], cus, 32)
+    assert e["dispatches"] == 2 and e["trace_mean_us"] == 2.0
+    assert e["lds_util"] == 0.5 and e["valu_busy"] == 0.25 and e["binding_unit"] == "lds"
+    assert e["lds_bank_conflict_rate"] == round(0.1 / 0.4, 4)
+    assert e["lds_insts_per_pixel"] == 2.0 and e["valu_insts_per_pixel"] == 4.0
+    # rocprofiler-sdk's derived figures (per cent) take precedence
+    d2 = [dict(d[0], LdsUtil=40.0, VALUBusy=60.0, LdsBankConflict=0.05)]
+    e2 = bench.counter_metrics(d2, [], cus, 0)
+    assert e2["lds_util"] == 0.4 and e2["lds_util_raw"] == 0.5 and e2["valu_busy"] == 0.6
+    assert e2["lds_bank_conflict_rate"] == 0.05 and e2["binding_unit"] == "valu"
