@@ -19,7 +19,7 @@ import subprocess
 
 import numpy as np
 
-from .brute import brute, brute_median, level_of  # noqa: F401
+from .brute import brute, brute_median, level_of, median_at  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oilpaint_ref.c")

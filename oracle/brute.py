@@ -58,3 +58,13 @@ def brute_median(img, radius: int, channel: int):
                           for xx in range(max(0, x - radius), min(w, x + radius + 1)))
             out[y][x] = vals[(len(vals) - 1) // 2]
     return out
+
+
+def median_at(img, x: int, y: int, radius: int, channel: int) -> int:
+    """The lower median of one output pixel by sorting its clipped window
+    (numpy array [H, W, C]): element floor((n - 1) / 2) of the sorted values."""
+    import numpy as np
+    h, w = img.shape[0], img.shape[1]
+    win = np.asarray(img[max(0, y - radius):min(h, y + radius + 1), max(0, x - radius):min(w, x + radius + 1), channel])
+    vals = np.sort(win.reshape(-1))
+    return int(vals[(vals.size - 1) // 2])

@@ -71,3 +71,14 @@ def test_threads_and_bad_args():
     with pytest.raises(ValueError):
         oracle.median_ref(img, 2, 3)
     assert oracle.median_ref(np.zeros((0, 5, 3), np.uint8), 2, 0).shape == (0, 5)
+
+
+def test_median_at_matches_brute_and_table():
+    rng = np.random.default_rng(4)
+    for (w, h, c, r) in [(7, 5, 3, 1), (9, 9, 1, 3), (4, 11, 2, 6)]:
+        img = rng.integers(0, 256, (h, w, c), dtype=np.uint8)
+        want = oracle.brute_median(img.tolist(), r, c - 1)
+        table = oracle.median_ref(img, r, c - 1)
+        for y in range(h):
+            for x in range(w):
+                assert oracle.median_at(img, x, y, r, c - 1) == want[y][x] == table[y, x]
