@@ -384,26 +384,40 @@ def bench_large_radius(torch, B, synth, timer, oracle_mod) -> dict:
 
 def bench_median(torch, B, synth, timer, oracle_mod, threads: int) -> dict:
     """The windowed median of one channel (the second filter of the class) on
-    the 1920x1080 image, channel 1: MP/s per radius, and the whole output
-    against the median oracle at r = 1, 5 and 15."""
+    the 1920x1080 image, channel 1, with each radius's tuned kernel form (one
+    or four wavefronts per strip, or column histograms): MP/s per radius; the
+    whole output against the median oracle at r = 1, 5, 15 and 32, sampled
+    pixels (each by sorting its window) at r = 64 and 127."""
     import numpy as np
+    from paper_1405_1020_amd import tune
     img = synth.fhd_image()
     src = torch.from_numpy(img).cuda()
     h, w = img.shape[:2]
     dst = torch.empty(h, w, dtype=torch.uint8, device="cuda")
     mp = w * h / 1e6
+    radii = (1, 2, 5, 10, 15, 16, 32, 64, 127)
+    tuned = tune.ensure_median(radii, w, h)
+    rng = np.random.default_rng(17)
     out = {}
-    for r in (1, 2, 5, 10, 15):
-        ms = timer.time(lambda: B.median_async(src, dst, r, 1), 20, 3)
-        e = {"ms": round(ms, 5), "mp_per_s": round(mp / (ms / 1e3), 1)}
-        if r in (1, 5, 15):
-            B.median_async(src, dst, r, 1)
-            got = dst.cpu().numpy()
+    for r in radii:
+        reps = 20 if r <= 32 else 5
+        ms = timer.time(lambda: B.median_async(src, dst, r, 1), reps, 2)
+        e = {"ms": round(ms, 5), "mp_per_s": round(mp / (ms / 1e3), 1), "kind": tuned[str(r)]["kind"],
+             "forms_ms": {str(k): round(t, 4) for k, t in tuned[str(r)]["all"]}}
+        B.median_async(src, dst, r, 1)
+        torch.cuda.synchronize()
+        got = dst.cpu().numpy()
+        if r in (1, 5, 15, 32):
             want = oracle_mod.median_ref(img, r, 1, nthreads=threads)
             e["pixels_differing"] = int((got != want).sum())
+        elif r in (64, 127):
+            pts = [(0, 0), (w - 1, h - 1)] + [(int(rng.integers(0, w)), int(rng.integers(0, h))) for _ in range(14)]
+            ok = 0
+            for x, y in pts:
+                ok += int(oracle_mod.median_at(img, x, y, r, 1) == got[y, x])
+            e["oracle_pixels"] = "%d/%d" % (ok, len(pts))
         out["r%d" % r] = e
     return out
-
 
 def bench_register_histograms(B, tune) -> dict:
     """Histograms in registers (OILPAINT_HIST_REGS) against the tuned launch

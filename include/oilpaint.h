@@ -290,11 +290,40 @@ int oilpaint_plan_destroy(oilpaint_plan *plan);
  * src_stride bytes apart (>= channels * width); dst: one byte per pixel, rows
  * dst_stride bytes apart (>= width); bytes [width, dst_stride) of a dst row
  * are not written.  Device pointers, disjoint.  Effective radius (the radius
- * clamped to max(width, height) - 1) at most 15, else ERR_UNSUPPORTED.
+ * clamped to max(width, height) - 1) at most 127, else ERR_UNSUPPORTED.
  * Enqueues on `stream`; errors as oilpaint_async (ERR_NULL, ERR_ARG for a
- * size, stride or channel, ERR_OVERLAP, ERR_NOT_DEVICE, ERR_HIP). */
+ * size, stride or channel, ERR_OVERLAP, ERR_NOT_DEVICE, ERR_HIP).  The
+ * kernel form is the one installed for the radius (oilpaint_median_set_kind)
+ * or else the built-in choice (one or four wavefronts per strip up to radius
+ * 15, column histograms above). */
 int oilpaint_median_async(const uint8_t *src, int src_stride, int channels, int channel, uint8_t *dst,
                           int dst_stride, int width, int height, int radius, void *stream);
+/* Kernel forms of the median:
+ *   OILPAINT_MEDIAN_ONE     two-level count histogram per lane in LDS, rows
+ *                           sliding down, one wavefront per 64-column strip
+ *                           (radius <= 15);
+ *   OILPAINT_MEDIAN_FOUR    the same worked by four wavefronts per strip
+ *                           (radius <= 15);
+ *   OILPAINT_MEDIAN_COLUMN  one-byte fine and coarse histograms of every
+ *                           column's window rows; each lane's window counts
+ *                           are differences of prefix sums across the strip,
+ *                           so the work per row does not grow with the radius
+ *                           (radius <= 127).
+ * OILPAINT_MEDIAN_AUTO selects the installed or built-in form. */
+#define OILPAINT_MEDIAN_AUTO   0
+#define OILPAINT_MEDIAN_ONE    1
+#define OILPAINT_MEDIAN_FOUR   2
+#define OILPAINT_MEDIAN_COLUMN 3
+/* oilpaint_median_async with an explicit form (ERR_UNSUPPORTED where the form
+ * does not cover the effective radius). */
+int oilpaint_median_async_kind(const uint8_t *src, int src_stride, int channels, int channel, uint8_t *dst,
+                               int dst_stride, int width, int height, int radius, int kind, void *stream);
+/* Install the form used for `radius` (0..127) from now on (the tuner's
+ * choice); OILPAINT_MEDIAN_AUTO restores the built-in one. */
+int oilpaint_median_set_kind(int radius, int kind);
+/* The form oilpaint_median_async uses for an effective radius, or
+ * ERR_UNSUPPORTED. */
+int oilpaint_median_pick_kind(int radius);
 /* The same on the default stream, then wait for it. */
 int oilpaint_median(const uint8_t *src, int src_stride, int channels, int channel, uint8_t *dst,
                     int dst_stride, int width, int height, int radius);

@@ -85,6 +85,11 @@ _SIGS = {
     "oilpaint_median_async": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
                               ctypes.c_int),
+    "oilpaint_median_async_kind": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_void_p], ctypes.c_int),
+    "oilpaint_median_set_kind": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "oilpaint_median_pick_kind": ([ctypes.c_int], ctypes.c_int),
     "oilpaint_median": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "oilpaint_tune": ([ctypes.c_int] * 4 + [ctypes.POINTER(Variant), ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -256,10 +261,17 @@ def _plane_geometry(t, channels: int | None) -> tuple[int, int, int, int]:
     return w, h, (st[0] if h > 1 else c * w), c
 
 
-def median_async(src, dst, radius: int, channel: int, stream=None) -> int:
-    """oilpaint_median_async: the windowed median of channel `channel` of
-    src (uint8 [H, W, C] CUDA tensor) into dst (uint8 [H, W] or [H, W, 1]),
-    each with its own row stride, on `stream`."""
+MEDIAN_AUTO = 0
+MEDIAN_ONE = 1
+MEDIAN_FOUR = 2
+MEDIAN_COLUMN = 3
+
+
+def median_async(src, dst, radius: int, channel: int, stream=None, kind: int = MEDIAN_AUTO) -> int:
+    """oilpaint_median_async (or, with a kind, oilpaint_median_async_kind):
+    the windowed median of channel `channel` of src (uint8 [H, W, C] CUDA
+    tensor) into dst (uint8 [H, W] or [H, W, 1]), each with its own row
+    stride, on `stream`."""
     _require_cuda(src, dst)
     w, h, s, c = _plane_geometry(src, None)
     w2, h2, s2, c2 = _plane_geometry(dst, None)
@@ -267,18 +279,34 @@ def median_async(src, dst, radius: int, channel: int, stream=None) -> int:
         raise ValueError("dst must be a one-channel image of src's width and height")
     if w == 0 or h == 0:
         return OK
-    st = lib().oilpaint_median_async(ctypes.c_void_p(src.data_ptr()), s, c, channel,
-                                     ctypes.c_void_p(dst.data_ptr()), s2, w, h, radius, _stream_ptr(stream))
+    if kind == MEDIAN_AUTO:
+        st = lib().oilpaint_median_async(ctypes.c_void_p(src.data_ptr()), s, c, channel,
+                                         ctypes.c_void_p(dst.data_ptr()), s2, w, h, radius, _stream_ptr(stream))
+    else:
+        st = lib().oilpaint_median_async_kind(ctypes.c_void_p(src.data_ptr()), s, c, channel,
+                                              ctypes.c_void_p(dst.data_ptr()), s2, w, h, radius, kind,
+                                              _stream_ptr(stream))
     return _check(st, "oilpaint_median_async")
 
 
-def median(src, radius: int, channel: int, out=None, stream=None):
+def median_set_kind(radius: int, kind: int):
+    _check(lib().oilpaint_median_set_kind(radius, kind), "oilpaint_median_set_kind")
+
+
+def median_pick_kind(radius: int) -> int:
+    st = lib().oilpaint_median_pick_kind(radius)
+    if st < 0:
+        raise OilpaintError(st, "oilpaint_median_pick_kind")
+    return st
+
+
+def median(src, radius: int, channel: int, out=None, stream=None, kind: int = MEDIAN_AUTO):
     """Windowed median of one channel; returns `out` (uint8 [H, W],
     allocated if None)."""
     torch = _torch()
     if out is None:
         out = torch.empty(src.shape[0], src.shape[1], dtype=torch.uint8, device=src.device)
-    median_async(src, out, radius, channel, stream=stream)
+    median_async(src, out, radius, channel, stream=stream, kind=kind)
     return out
 
 

@@ -346,19 +346,49 @@ static int launch_one(const uint8_t* src, uint8_t* dst, int width, int height, i
     return launch_desc(d, v, stream);
 }
 
-int oilpaint_median_async(const uint8_t* src, int src_stride, int channels, int channel, uint8_t* dst,
-                          int dst_stride, int width, int height, int radius, void* stream) {
+}  // extern "C"
+
+namespace oilpaint_impl {
+namespace {
+
+std::mutex g_median_mu;
+int g_median_kind[kMedianColumnMaxRadius + 1];  // installed kinds (0: the built-in choice)
+
+// The built-in choice: radius <= 15 one or four wavefronts per strip (as
+// measured per radius, median_split), above it the column form.
+int median_default_kind(int reff) {
+    if (reff <= kMedianMaxRadius) return median_split(reff) ? OILPAINT_MEDIAN_FOUR : OILPAINT_MEDIAN_ONE;
+    return OILPAINT_MEDIAN_COLUMN;
+}
+
+bool median_kind_ok(int kind, int reff) {
+    if (kind == OILPAINT_MEDIAN_ONE || kind == OILPAINT_MEDIAN_FOUR) return reff <= kMedianMaxRadius;
+    if (kind == OILPAINT_MEDIAN_COLUMN) return reff <= kMedianColumnMaxRadius;
+    return false;
+}
+
+int median_chosen_kind(int reff) {
+    if (reff > kMedianColumnMaxRadius) return 0;
+    std::lock_guard<std::mutex> lock(g_median_mu);
+    const int k = g_median_kind[reff];
+    return k ? k : median_default_kind(reff);
+}
+
+int median_launch(const uint8_t* src, int src_stride, int channels, int channel, uint8_t* dst, int dst_stride,
+                  int width, int height, int radius, int kind, hipStream_t stream) {
     if (!src || !dst) return OILPAINT_ERR_NULL;
     if (width < 0 || height < 0 || radius < 0 || channels < 1 || channels > 4 || channel < 0 ||
         channel >= channels)
         return OILPAINT_ERR_ARG;
+    if (kind < OILPAINT_MEDIAN_AUTO || kind > OILPAINT_MEDIAN_COLUMN) return OILPAINT_ERR_ARG;
     if ((int64_t)src_stride < (int64_t)channels * width || dst_stride < width) return OILPAINT_ERR_ARG;
     if (width == 0 || height == 0) return OILPAINT_OK;
     const size_t slen = (size_t)src_stride * (size_t)(height - 1) + (size_t)channels * (size_t)width;
     const size_t dlen = (size_t)dst_stride * (size_t)(height - 1) + (size_t)width;
     if (ranges_overlap(src, slen, dst, dlen)) return OILPAINT_ERR_OVERLAP;
     const int reff = effective_radius(width, height, radius);
-    if (reff > kMedianMaxRadius) return OILPAINT_ERR_UNSUPPORTED;
+    if (kind == OILPAINT_MEDIAN_AUTO) kind = median_chosen_kind(reff);
+    if (kind == 0 || !median_kind_ok(kind, reff)) return OILPAINT_ERR_UNSUPPORTED;
     int st = check_device_ptr(src);
     if (st == OILPAINT_OK) st = check_device_ptr(dst);
     if (st != OILPAINT_OK) return st;
@@ -377,15 +407,41 @@ int oilpaint_median_async(const uint8_t* src, int src_stride, int channels, int 
     j.radius = reff;
     // as many workgroups per CU as are resident at once (the kernel's
     // occupancy at this LDS size, at most 8), so that the whole grid runs in
-    // one wave and runs are as long as that allows: 8 .. 1024 rows; one or
-    // four wavefronts per strip (median_split)
-    const bool split = median_split(reff);
-    const MedianKernel kern = split ? kMedian4[reff] : kMedian[reff];
+    // one wave and runs are as long as that allows: 8 .. 1024 rows (the
+    // column form's run start, 2r+1 rows of two atomics per column, costs
+    // less than one of its output rows)
+    MedianKernel kern;
+    int threads = 64;
+    size_t lds;
+    if (kind == OILPAINT_MEDIAN_COLUMN) {
+        const int nt = (64 + 2 * reff + 63) / 64;
+        kern = kMedianColumn[nt - 1];
+        lds = median_column_lds_bytes(reff);
+        static int done[kMedianColumnChunks];
+        if (lds > 65536 && !__atomic_load_n(&done[nt - 1], __ATOMIC_ACQUIRE)) {
+            hipFuncAttributes fa;
+            if (note_hip("hipFuncGetAttributes", hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern))) !=
+                hipSuccess)
+                return OILPAINT_ERR_HIP;
+            const size_t total = d.ok ? d.lds_per_block : 65536;
+            if (lds + fa.sharedSizeBytes > total) return OILPAINT_ERR_UNSUPPORTED;
+            if (note_hip("hipFuncSetAttribute",
+                         hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(total - fa.sharedSizeBytes))) != hipSuccess)
+                return OILPAINT_ERR_HIP;
+            __atomic_store_n(&done[nt - 1], 1, __ATOMIC_RELEASE);
+        }
+    } else {
+        const bool split = kind == OILPAINT_MEDIAN_FOUR;
+        kern = split ? kMedian4[reff] : kMedian[reff];
+        threads = split ? 256 : 64;
+        lds = median_lds_bytes(reff);
+    }
     const long strips = (width + 63) / 64;
-    const size_t lds = median_lds_bytes(reff);
     int fit = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void*>(kern), split ? 256 : 64,
-                                                     lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void*>(kern), threads, lds) !=
+            hipSuccess ||
         fit < 1) {
         (void)hipGetLastError();
         fit = (int)std::max<size_t>(1, (d.ok ? d.lds_per_block : 65536) / lds);
@@ -394,8 +450,40 @@ int oilpaint_median_async(const uint8_t* src, int src_stride, int channels, int 
     j.rows = (int)std::max(8L, std::min((strips * height + want - 1) / want, 1024L));
     j.tiles_x = (int)strips;
     j.tiles_y = (height + j.rows - 1) / j.rows;
-    hipLaunchKernelGGL(kern, dim3(j.tiles_x * j.tiles_y), dim3(split ? 256 : 64), lds, (hipStream_t)stream, j);
+    hipLaunchKernelGGL(kern, dim3(j.tiles_x * j.tiles_y), dim3(threads), lds, stream, j);
     return note_hip("median launch", hipGetLastError()) == hipSuccess ? OILPAINT_OK : OILPAINT_ERR_HIP;
+}
+
+}  // namespace
+}  // namespace oilpaint_impl
+
+extern "C" {
+
+int oilpaint_median_async(const uint8_t* src, int src_stride, int channels, int channel, uint8_t* dst,
+                          int dst_stride, int width, int height, int radius, void* stream) {
+    return median_launch(src, src_stride, channels, channel, dst, dst_stride, width, height, radius,
+                         OILPAINT_MEDIAN_AUTO, (hipStream_t)stream);
+}
+
+int oilpaint_median_async_kind(const uint8_t* src, int src_stride, int channels, int channel, uint8_t* dst,
+                               int dst_stride, int width, int height, int radius, int kind, void* stream) {
+    return median_launch(src, src_stride, channels, channel, dst, dst_stride, width, height, radius, kind,
+                         (hipStream_t)stream);
+}
+
+int oilpaint_median_set_kind(int radius, int kind) {
+    if (radius < 0 || radius > kMedianColumnMaxRadius || kind < OILPAINT_MEDIAN_AUTO || kind > OILPAINT_MEDIAN_COLUMN)
+        return OILPAINT_ERR_ARG;
+    if (kind != OILPAINT_MEDIAN_AUTO && !median_kind_ok(kind, radius)) return OILPAINT_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_median_mu);
+    g_median_kind[radius] = kind;
+    return OILPAINT_OK;
+}
+
+int oilpaint_median_pick_kind(int radius) {
+    if (radius < 0) return OILPAINT_ERR_ARG;
+    const int k = median_chosen_kind(radius);
+    return k ? k : OILPAINT_ERR_UNSUPPORTED;
 }
 
 int oilpaint_median(const uint8_t* src, int src_stride, int channels, int channel, uint8_t* dst, int dst_stride,

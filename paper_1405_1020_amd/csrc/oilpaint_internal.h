@@ -290,6 +290,12 @@ inline bool median_split(int radius) {
     return radius >= 0 && radius <= kMedianMaxRadius && kSplit[radius];
 }
 size_t median_lds_bytes(int radius);
+// The column-histogram form (oilpaint_k_median_column.hip): any radius up to
+// 127, by 64-column chunks of the strip with its halo, minus one.
+constexpr int kMedianColumnMaxRadius = 127;
+constexpr int kMedianColumnChunks = 5;
+extern const MedianKernel kMedianColumn[kMedianColumnChunks];
+size_t median_column_lds_bytes(int radius);
 
 // Kernel launches (oilpaint_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream);

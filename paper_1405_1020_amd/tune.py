@@ -88,22 +88,24 @@ def _key(radius: int, levels: int) -> str:
     return "%d,%d" % (radius, levels)
 
 
-def _load_file() -> dict:
+def _load_file(section: str = "entries") -> dict:
     try:
         d = json.load(open(cache_path()))
     except (OSError, ValueError):
         return {}
     if d.get("arch") != arch() or d.get("code") != code_hash():
         return {}
-    return d.get("entries", {})
+    return d.get(section, {})
 
 
-def _save_file(entries: dict):
+def _save_file(entries: dict, section: str = "entries"):
     p = cache_path()
     try:
         os.makedirs(os.path.dirname(p), exist_ok=True)
+        d = {"arch": arch(), "code": code_hash(), "entries": _load_file("entries"), "median": _load_file("median")}
+        d[section] = entries
         tmp = p + ".tmp%d" % os.getpid()
-        json.dump({"arch": arch(), "code": code_hash(), "entries": entries}, open(tmp, "w"), indent=1)
+        json.dump(d, open(tmp, "w"), indent=1)
         os.replace(tmp, p)
     except OSError:
         pass
@@ -162,3 +164,57 @@ def ensure(pairs, width: int = 1920, height: int = 1080, reps: int = 5, retune: 
         _save_file(entries)
     install({k: entries[k] for k in (_key(r, L) for r, L in pairs)})
     return {k: entries[k] for k in (_key(r, L) for r, L in pairs)}
+
+
+# ---------------------------------------------------------------------------
+# The windowed median: which kernel form per radius (one or four wavefronts
+# per strip with per-lane histograms up to radius 15, column histograms up to
+# 127), timed on a photo-like image with HIP events.
+# ---------------------------------------------------------------------------
+def median_candidates(radius: int) -> list[int]:
+    out = []
+    if radius <= 15:
+        out += [B.MEDIAN_ONE, B.MEDIAN_FOUR]
+    if radius <= 127:
+        out.append(B.MEDIAN_COLUMN)
+    return out
+
+
+def tune_median(radius: int, width: int = 1920, height: int = 1080, reps: int = 5) -> dict:
+    """Time every form for `radius` on channel 1 of a width x height blob
+    image and return {"kind": best, "ms": ..., "all": [(kind, ms), ...]}."""
+    import torch
+    from . import synth
+    src = synth.make_image_device(width, height, seed=7)
+    dst = torch.empty((height, width), dtype=torch.uint8, device=src.device)
+    timed = []
+    for kind in median_candidates(radius):
+        B.median_async(src, dst, radius, 1, kind=kind)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            B.median_async(src, dst, radius, 1, kind=kind)
+        e1.record()
+        torch.cuda.synchronize()
+        timed.append((kind, e0.elapsed_time(e1) / reps))
+    best, ms = pick(timed)
+    return {"kind": best, "ms": ms, "size": [width, height], "all": timed}
+
+
+def ensure_median(radii, width: int = 1920, height: int = 1080, reps: int = 5, retune: bool = False) -> dict:
+    """Make sure every radius has its median form installed: from the cache,
+    or tuned now and added to it."""
+    entries = {} if retune else _load_file("median")
+    changed = False
+    for r in radii:
+        k = str(r)
+        if k not in entries:
+            entries[k] = tune_median(r, width, height, reps)
+            changed = True
+    if changed:
+        _save_file(entries, "median")
+    for r in radii:
+        B.median_set_kind(r, entries[str(r)]["kind"])
+    return {str(r): entries[str(r)] for r in radii}

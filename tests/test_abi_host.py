@@ -81,8 +81,15 @@ def test_median_argument_checks():
     assert call(src, 30, 3, 0, dst, 10, -1, 5, 2) == B.ERR_ARG
     assert call(src, 30, 3, 0, dst, 10, 0, 5, 2) == B.OK         # empty: nothing to do
     assert call(src, 30, 3, 0, ctypes.c_void_p(a + 100), 10, 10, 5, 2) == B.ERR_OVERLAP
-    # radius 16 on a 20 x 20 image is 16 effective: beyond the median kernels
-    assert call(src, 60, 3, 0, dst, 20, 20, 20, 16) == B.ERR_UNSUPPORTED
+    # radius 128 on a 129 x 1 image is 128 effective: beyond the median kernels
+    assert call(src, 387, 3, 0, dst, 129, 129, 1, 128) == B.ERR_UNSUPPORTED
+    # an explicit form that does not cover the radius, and an unknown form
+    kcall = lambda r, k: L.oilpaint_median_async_kind(src, 60, 3, 0, dst, 20, 20, 20, r, k, None)
+    assert kcall(16, B.MEDIAN_ONE) == B.ERR_UNSUPPORTED and kcall(16, B.MEDIAN_FOUR) == B.ERR_UNSUPPORTED
+    assert kcall(2, 4) == B.ERR_ARG and kcall(2, -1) == B.ERR_ARG
+    assert L.oilpaint_median_set_kind(16, B.MEDIAN_ONE) == B.ERR_UNSUPPORTED
+    assert L.oilpaint_median_set_kind(128, B.MEDIAN_COLUMN) == B.ERR_ARG
+    assert L.oilpaint_median_pick_kind(16) == B.MEDIAN_COLUMN and L.oilpaint_median_pick_kind(128) == B.ERR_UNSUPPORTED
     # on a 10 x 5 image it is 9 effective: valid, and host memory is refused
     assert call(src, 30, 3, 0, dst, 10, 10, 5, 16) == B.ERR_NOT_DEVICE
 

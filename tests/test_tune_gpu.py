@@ -60,3 +60,23 @@ def test_density_shapes_exact(per_cu):
             B.oilpaint_async(src, dst, r, L, variant=v)
             torch_mod().cuda.synchronize()
             assert first_mismatch(from_device(dst), want) is None, (r, L, v)
+
+
+def test_ensure_median_installs_and_stays_exact(tmp_path, monkeypatch):
+    import oracle
+    torch = torch_mod()
+    monkeypatch.setenv("OILPAINT_TUNE_CACHE", str(tmp_path / "tune.json"))
+    try:
+        res = tune.ensure_median([3, 12, 24], 640, 480, reps=2)
+        for r in (3, 12, 24):
+            kind = res[str(r)]["kind"]
+            assert kind in tune.median_candidates(r) and B.median_pick_kind(r) == kind
+            assert {k for k, _ in res[str(r)]["all"]} == set(tune.median_candidates(r))
+            img = synth.make_image(211, 167, seed=r, n_blobs=5, sigma=(3, 30))
+            src = torch.from_numpy(img).cuda()
+            out = B.median(src, r, 1)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), oracle.median_ref(img, r, 1, nthreads=4)), r
+    finally:
+        for r in range(128):
+            B.median_set_kind(r, B.MEDIAN_AUTO)
