@@ -410,8 +410,10 @@ int oilpaint_queue_destroy(oilpaint_queue *q);
  *     row; JFIF RGB -> YCbCr exactly in integers, rounded half up; each chroma
  *     sample the mean of the pixels it covers, rounded half up; the 8 x 8
  *     forward DCT (A.3.3) of sample - 128 in fp32 and quantization to the
- *     nearest integer, halves away from zero (A.3.4), on the GPU; entropy
- *     coding on the host with Huffman tables fitted to the image (K.2).
+ *     nearest integer, halves away from zero (A.3.4), on the GPU; Huffman
+ *     coding (F.1.2) with tables fitted to the image (K.2): the symbol
+ *     statistics, the codes, their placement and the byte stuffing (B.1.1.5)
+ *     on the GPU, the table fitting and the headers on the host.
  *     Quantization tables: T.81 Tables K.1 and K.2 scaled by quality
  *     (1..100; 50 keeps them, q < 50 scales by 5000/q %, q >= 50 by 200-2q %,
  *     each entry rounded and kept in [1, 255]).  Subsampling 0, 1, 2: 4:4:4,
@@ -458,8 +460,11 @@ int oilpaint_jpeg_decode_planes(const uint8_t *data, size_t len, uint8_t *const 
 /* Encode width x height interleaved RGB (device memory, rows `stride` bytes
  * apart) as a JFIF file into `out` (host memory).  *out_len receives the
  * file's length; ERR_NOMEM if it exceeds `capacity` (out untouched).  The
- * kernels and the download run on `stream`, which the call synchronizes;
- * *host_ms, if not NULL, receives the host time of the entropy coding. */
+ * kernels and the downloads run on `stream`, which the call synchronizes
+ * (twice: for the symbol counts and for the coded stream); *host_ms, if not
+ * NULL, receives the host time of fitting the tables and writing the
+ * headers.  The same coefficients give the same bytes as
+ * oilpaint_jpeg_write. */
 int oilpaint_jpeg_encode(const uint8_t *src, int width, int height, int stride, int quality, int subsampling,
                          uint8_t *out, size_t capacity, size_t *out_len, void *stream, double *host_ms);
 /* A capacity always large enough for oilpaint_jpeg_encode of that size. */

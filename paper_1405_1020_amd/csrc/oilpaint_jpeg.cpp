@@ -1,9 +1,11 @@
 // JPEG decode and encode around the filter: baseline sequential DCT-based
 // JPEG (ITU-T T.81; Huffman coding, 8-bit samples) in JFIF's YCbCr colour
-// space.  The host parses markers and runs the entropy coding; everything per
-// sample (dequantization, inverse DCT, colour, chroma resampling; colour,
-// chroma averaging, forward DCT, quantization) runs in the kernels of
-// oilpaint_k_jpeg.hip, so a decoded image lands in device memory, ready for
+// space.  The host parses markers, decodes the entropy-coded data, fits the
+// encoder's Huffman tables and writes the headers; everything per sample
+// (dequantization, inverse DCT, colour, chroma resampling; colour, chroma
+// averaging, forward DCT, quantization) runs in the kernels of
+// oilpaint_k_jpeg.hip and the encoder's Huffman coding in those of
+// oilpaint_k_huff.hip, so a decoded image lands in device memory, ready for
 // the filter, and an encoded one is read from there.
 #include <algorithm>
 #include <chrono>
@@ -495,38 +497,35 @@ void put16(std::vector<uint8_t>& o, int v) {
     o.push_back((uint8_t)v);
 }
 
-void entropy_encode(const Frame& f, const int16_t* coef, std::vector<uint8_t>& o) {
-    const int ntab = f.ncomp == 1 ? 1 : 2;
-    std::vector<int64_t> fdc(2 * 256, 0), fac(2 * 256, 0);
-    {
-        int pred[kJpegMaxComps] = {};
-        for_blocks(f, coef, [&](int c, const int16_t* b) {
-            const int t = c ? 1 : 0;
-            ++fdc[t * 256 + category(b[0] - pred[c])];
-            pred[c] = b[0];
-            int run = 0;
-            for (int k = 1; k < 64; ++k) {
-                const int v = b[kZigzag[k]];
-                if (v == 0) {
-                    ++run;
-                    continue;
-                }
-                while (run > 15) {
-                    ++fac[t * 256 + 0xF0];
-                    run -= 16;
-                }
-                ++fac[t * 256 + (run << 4 | category(v))];
-                run = 0;
+// Symbol counts of the scan (DC and AC, luminance and chrominance tables).
+void count_symbols(const Frame& f, const int16_t* coef, int64_t* fdc, int64_t* fac) {
+    int pred[kJpegMaxComps] = {};
+    for_blocks(f, coef, [&](int c, const int16_t* b) {
+        const int t = c ? 1 : 0;
+        ++fdc[t * 256 + category(b[0] - pred[c])];
+        pred[c] = b[0];
+        int run = 0;
+        for (int k = 1; k < 64; ++k) {
+            const int v = b[kZigzag[k]];
+            if (v == 0) {
+                ++run;
+                continue;
             }
-            if (run) ++fac[t * 256 + 0x00];
-        });
-    }
-    HuffEnc dc[2], ac[2];
-    for (int t = 0; t < ntab; ++t) {
-        fit_table(&fdc[t * 256], dc[t]);
-        fit_table(&fac[t * 256], ac[t]);
-    }
-    // headers
+            while (run > 15) {
+                ++fac[t * 256 + 0xF0];
+                run -= 16;
+            }
+            ++fac[t * 256 + (run << 4 | category(v))];
+            run = 0;
+        }
+        if (run) ++fac[t * 256 + 0x00];
+    });
+}
+
+// Everything before the entropy-coded data: SOI, JFIF APP0, the quantization
+// tables, SOF0, the fitted Huffman tables and SOS.
+void write_headers(const Frame& f, const HuffEnc* dc, const HuffEnc* ac, std::vector<uint8_t>& o) {
+    const int ntab = f.ncomp == 1 ? 1 : 2;
     o.insert(o.end(), {0xFF, 0xD8, 0xFF, 0xE0});
     put16(o, 16);
     o.insert(o.end(), {'J', 'F', 'I', 'F', 0, 1, 1, 0, 0, 1, 0, 1, 0, 0});
@@ -565,7 +564,19 @@ void entropy_encode(const Frame& f, const int16_t* coef, std::vector<uint8_t>& o
         o.push_back((uint8_t)(t << 4 | t));
     }
     o.insert(o.end(), {0, 63, 0});
-    // data
+}
+
+// The whole file on the host (oilpaint_jpeg_write).
+void entropy_encode(const Frame& f, const int16_t* coef, std::vector<uint8_t>& o) {
+    const int ntab = f.ncomp == 1 ? 1 : 2;
+    std::vector<int64_t> fdc(2 * 256, 0), fac(2 * 256, 0);
+    count_symbols(f, coef, fdc.data(), fac.data());
+    HuffEnc dc[2], ac[2];
+    for (int t = 0; t < ntab; ++t) {
+        fit_table(&fdc[t * 256], dc[t]);
+        fit_table(&fac[t * 256], ac[t]);
+    }
+    write_headers(f, dc, ac, o);
     BitOut bo(o);
     int pred[kJpegMaxComps] = {};
     for_blocks(f, coef, [&](int c, const int16_t* b) {
@@ -597,6 +608,32 @@ void entropy_encode(const Frame& f, const int16_t* coef, std::vector<uint8_t>& o
     });
     bo.flush();
     o.insert(o.end(), {0xFF, 0xD9});
+}
+
+// The scan as the device coder walks it (every component interleaved).
+JpegScanMap scan_map(const Frame& f) {
+    JpegScanMap m;
+    std::memset(&m, 0, sizeof(m));
+    int j = 0;
+    for (int c = 0; c < f.ncomp; ++c) {
+        for (int v = 0; v < f.v[c]; ++v)
+            for (int h = 0; h < f.h[c]; ++h, ++j) {
+                m.comp[j] = c;
+                m.dx[j] = h;
+                m.dy[j] = v;
+                m.prev[j] = (v || h) ? j - 1 : -1;
+            }
+        m.last[c] = j - 1;
+        m.h[c] = f.h[c];
+        m.v[c] = f.v[c];
+        m.bw[c] = f.bw[c];
+        m.first[c] = f.first[c];
+        m.tab[c] = c ? 1 : 0;
+    }
+    m.bpm = j;
+    m.mcux = f.mcux;
+    m.blocks = (int64_t)f.mcux * f.mcuy * j;
+    return m;
 }
 
 // Quality scaling of the Annex K tables (the Independent JPEG Group's
@@ -678,12 +715,57 @@ struct JpegDevice {
     size_t plane_cap = 0;
     hipEvent_t done = nullptr;
     bool pending = false;
+    // Huffman coding on the device: symbol counts, code tables and the two
+    // totals (bits, 0xFF bytes) in `small` (device) and `small_host`
+    // (pinned); per-block bits and offsets, prefix-sum tiles, the stream's
+    // words and the stuffed bytes.
+    struct Small {
+        unsigned long long freq[4 * 256];
+        uint32_t tabs[4 * 256];
+        uint64_t totals[2];
+    };
+    Small* small = nullptr;
+    Small* small_host = nullptr;
+    uint32_t* bits = nullptr;
+    uint64_t* offset = nullptr;
+    uint64_t* tiles = nullptr;
+    uint32_t* words = nullptr;
+    uint8_t* stuffed = nullptr;
+    size_t bits_cap = 0, offset_cap = 0, tiles_cap = 0, words_cap = 0, stuffed_cap = 0;
+    int cus = 0;
     ~JpegDevice() {
         if (pending) (void)hipEventSynchronize(done);
         if (coef) (void)hipFree(coef);
         if (host) (void)hipHostFree(host);
         if (planes) (void)hipFree(planes);
         if (done) (void)hipEventDestroy(done);
+        if (small) (void)hipFree(small);
+        if (small_host) (void)hipHostFree(small_host);
+        for (void* p : {(void*)bits, (void*)offset, (void*)tiles, (void*)words, (void*)stuffed})
+            if (p) (void)hipFree(p);
+    }
+    template <typename T>
+    static int grow(T*& p, size_t& cap, size_t n) {
+        if (n <= cap) return OILPAINT_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t c = std::max(n, (size_t)1 << 16);
+        if (hipMalloc(reinterpret_cast<void**>(&p), c * sizeof(T)) != hipSuccess) return OILPAINT_ERR_NOMEM;
+        cap = c;
+        return OILPAINT_OK;
+    }
+    int reserve_coder(int device) {
+        if (!small) {
+            if (hipMalloc(reinterpret_cast<void**>(&small), sizeof(Small)) != hipSuccess) return OILPAINT_ERR_NOMEM;
+            if (hipHostMalloc(reinterpret_cast<void**>(&small_host), sizeof(Small), hipHostMallocDefault) !=
+                hipSuccess)
+                return OILPAINT_ERR_NOMEM;
+        }
+        if (!cus && note_hip("hipDeviceGetAttribute", hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                                                            device)) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+        return OILPAINT_OK;
     }
     int reserve(size_t ncoef, size_t nplane) {
         if (!done && note_hip("hipEventCreate", hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess)
@@ -962,18 +1044,72 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
     for (int c = 0; c <= 3; ++c) q.first[c] = f.first[c];
     q.coef = jd.coef;
     if (launch_jpeg_rgb(r, s) != hipSuccess || launch_jpeg_fdct(q, s) != hipSuccess) return OILPAINT_ERR_HIP;
-    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(jd.host, jd.coef, f.blocks * 64 * sizeof(int16_t),
-                                                  hipMemcpyDeviceToHost, s)) != hipSuccess ||
+    // symbol statistics on the device, the tables fitted here
+    if ((st = jd.reserve_coder(device)) != OILPAINT_OK) return st;
+    JpegDevice::Small* dev = jd.small;
+    JpegDevice::Small* hs = jd.small_host;
+    const JpegScanMap m = scan_map(f);
+    if (note_hip("hipMemsetAsync", hipMemsetAsync(dev->freq, 0, sizeof(dev->freq), s)) != hipSuccess ||
+        launch_huff_stats(m, jd.coef, dev->freq, jd.cus, s) != hipSuccess ||
+        note_hip("hipMemcpyAsync", hipMemcpyAsync(hs->freq, dev->freq, sizeof(hs->freq), hipMemcpyDeviceToHost,
+                                                  s)) != hipSuccess ||
         note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
         return OILPAINT_ERR_HIP;
     const auto t0 = std::chrono::steady_clock::now();
-    std::vector<uint8_t> bytes;
-    bytes.reserve(f.blocks * 16 + 1024);
-    entropy_encode(f, jd.host, bytes);
+    HuffEnc dc[2], ac[2];
+    int64_t freq[4 * 256];
+    for (int i = 0; i < 4 * 256; ++i) freq[i] = (int64_t)hs->freq[i];
+    uint64_t nbits = 0;
+    for (int t = 0; t < 2; ++t) {
+        fit_table(freq + t * 256, dc[t]);
+        fit_table(freq + (2 + t) * 256, ac[t]);
+        for (int sym = 0; sym < 256; ++sym) {
+            nbits += (uint64_t)freq[t * 256 + sym] * (uint64_t)(dc[t].size[sym] + sym);
+            nbits += (uint64_t)freq[(2 + t) * 256 + sym] * (uint64_t)(ac[t].size[sym] + (sym & 15));
+        }
+    }
+    for (int t = 0; t < 4; ++t) {
+        const HuffEnc& h = t < 2 ? dc[t] : ac[t - 2];
+        for (int sym = 0; sym < 256; ++sym) hs->tabs[t * 256 + sym] = (uint32_t)h.size[sym] << 16 | h.code[sym];
+    }
+    std::vector<uint8_t> head;
+    write_headers(f, dc, ac, head);
     if (host_ms) *host_ms = ms_since(t0);
-    *out_len = bytes.size();
-    if (!out || bytes.size() > capacity) return OILPAINT_ERR_NOMEM;
-    std::memcpy(out, bytes.data(), bytes.size());
+    // the coding passes
+    const uint64_t nbytes = (nbits + 7) / 8;
+    const size_t nwords = (size_t)(nbits / 32) + 2;
+    if ((st = JpegDevice::grow(jd.bits, jd.bits_cap, (size_t)m.blocks)) != OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.offset, jd.offset_cap, (size_t)m.blocks)) != OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.tiles, jd.tiles_cap,
+                               (size_t)std::max(huff_scan_tiles(m.blocks), huff_scan_tiles((int64_t)nbytes)))) !=
+            OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.words, jd.words_cap, nwords)) != OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.stuffed, jd.stuffed_cap, (size_t)(2 * nbytes + 16))) != OILPAINT_OK)
+        return st;
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(dev->tabs, hs->tabs, sizeof(hs->tabs), hipMemcpyHostToDevice,
+                                                  s)) != hipSuccess ||
+        note_hip("hipMemsetAsync", hipMemsetAsync(jd.words, 0, nwords * sizeof(uint32_t), s)) != hipSuccess ||
+        launch_huff_code(m, jd.coef, dev->tabs, jd.bits, jd.offset, jd.tiles, &dev->totals[0], jd.words, s) !=
+            hipSuccess ||
+        launch_huff_stuff(jd.words, nbits, jd.tiles, &dev->totals[1], jd.stuffed, s) != hipSuccess ||
+        note_hip("hipMemcpyAsync", hipMemcpyAsync(hs->totals, dev->totals, sizeof(hs->totals),
+                                                  hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+        return OILPAINT_ERR_HIP;
+    if (hs->totals[0] != nbits) {
+        note_error("oilpaint_jpeg_encode: the device's bit count disagrees with the symbol statistics");
+        return OILPAINT_ERR_HIP;
+    }
+    const size_t data = (size_t)(nbytes + hs->totals[1]);
+    *out_len = head.size() + data + 2;
+    if (!out || *out_len > capacity) return OILPAINT_ERR_NOMEM;
+    std::memcpy(out, head.data(), head.size());
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(out + head.size(), jd.stuffed, data, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+        return OILPAINT_ERR_HIP;
+    out[*out_len - 2] = 0xFF;
+    out[*out_len - 1] = 0xD9;
     return OILPAINT_OK;
 }
 

@@ -3,8 +3,9 @@
 // replication (decode); JFIF colour conversion with chroma averaging, the
 // forward DCT and quantization (T.81 A.3.3, A.3.4) (encode).  One wavefront
 // per 8 x 8 block (lane = one sample or coefficient), separable passes through
-// LDS; colour conversion one lane per pixel.  The entropy coding runs on the
-// host (oilpaint_jpeg.cpp).
+// LDS; colour conversion one lane per pixel.  Entropy decoding runs on the
+// host (oilpaint_jpeg.cpp), the encoder's Huffman coding in
+// oilpaint_k_huff.hip.
 #include "oilpaint_internal.h"
 #include "oilpaint_jpeg.h"
 

@@ -151,6 +151,30 @@ def test_encode_matches_oracle(size, quality, ss):
         assert np.abs(out - img).mean() < 3.0
 
 
+@pytest.mark.parametrize("size,quality,ss,noise", [((203, 117), 75, 2, False), ((64, 48), 30, 1, False),
+                                                   ((1, 1), 80, 2, False), ((7, 9), 100, 0, True),
+                                                   ((640, 480), 100, 0, True), ((1920, 1080), 90, 2, False)])
+def test_device_coder_matches_host_coder(size, quality, ss, noise):
+    """The device's Huffman coding (statistics, code sizes, bit placement,
+    byte stuffing) against the library's host coder on the same quantized
+    coefficients: the files are the same bytes.  Noise at quality 100 fills
+    the stream with 0xFF bytes (about one in 256) and long codes; 1920x1080
+    spans many prefix-sum tiles of blocks and of bytes."""
+    torch = torch_mod()
+    w, h = size
+    if noise:
+        img = np.random.default_rng(w * h).integers(0, 256, (h, w, 3), dtype=np.uint8)
+    else:
+        img = synth.make_image(w, h, seed=5 * w + quality, n_blobs=6, sigma=(2, 40))
+    data = B.jpeg_encode(torch.from_numpy(img).cuda(), quality=quality, subsampling=ss)
+    _, coef = B.jpeg_coefficients(data)
+    assert data == B.jpeg_write(coef, w, h, quality, ss)
+    if noise and w * h > 1000:
+        scan = data[data.index(b"\xff\xda"):]
+        assert scan.count(b"\xff\x00") > 100
+    check_encoded(img, data, quality, ss)
+
+
 def test_file_driver_decode_filter_encode():
     """The paper's program shape: a JPEG file decoded onto the device, the oil
     paint filter run there, the result encoded: the decoded image against
