@@ -399,8 +399,10 @@ int oilpaint_queue_destroy(oilpaint_queue *q);
  * ERR_UNSUPPORTED; malformed ones ERR_ARG.
  *
  * What is computed (the same definitions as the test oracle):
- *   decode: entropy decoding on the host (T.81 F.2.2); on the GPU,
- *     dequantization (A.3.5) and the 8 x 8 inverse DCT (A.3.3) in fp32, each
+ *   decode: Huffman decoding (F.2.2) on the GPU, parallel over subsequences
+ *     of the entropy-coded data that resynchronize round by round (the host
+ *     strips the byte stuffing and RST markers and plans the subsequences);
+ *     on the GPU too, dequantization (A.3.5) and the 8 x 8 inverse DCT (A.3.3) in fp32, each
  *     sample + 128 rounded half up and clamped to [0, 255]; each chroma sample
  *     replicated over the Hmax/H x Vmax/V pixels it covers; JFIF YCbCr -> RGB
  *     (R = Y + 1.402 Cr', G = Y - 0.344136 Cb' - 0.714136 Cr', B = Y + 1.772
@@ -445,11 +447,13 @@ int oilpaint_jpeg_header(const uint8_t *data, size_t len, oilpaint_jpeg_info *in
 int oilpaint_jpeg_coefficients(const uint8_t *data, size_t len, int16_t *coef, size_t capacity, size_t *count);
 /* Decode a JPEG file (host memory) into dst, interleaved RGB on the device
  * (rows dst_stride >= 3 x width bytes apart; bytes past 3 x width are not
- * written).  The entropy decoding runs before the call returns; the upload
- * and the kernels are enqueued on `stream`.  *host_ms, if not NULL, receives
- * the host time of parsing and entropy decoding.  The library keeps the
- * coefficient and sample buffers per device (grown as needed); a call waits
- * for the previous call's work on them. */
+ * written).  The call waits on `stream` for the Huffman decoding (to report
+ * a malformed stream as ERR_ARG); the inverse DCT and colour kernels are
+ * left enqueued on it.  *host_ms, if not NULL, receives the host time of
+ * parsing, stripping the markers and planning the subsequences.  The
+ * library keeps the coefficient and sample buffers per device (grown as
+ * needed); a call waits for the previous call's work on them.  The
+ * coefficients are those oilpaint_jpeg_coefficients gives. */
 int oilpaint_jpeg_decode(const uint8_t *data, size_t len, uint8_t *dst, int dst_stride, void *stream,
                          double *host_ms);
 /* The same without colour conversion: each component's own samples
@@ -457,6 +461,11 @@ int oilpaint_jpeg_decode(const uint8_t *data, size_t len, uint8_t *dst, int dst_
  * >= comp_width bytes apart). */
 int oilpaint_jpeg_decode_planes(const uint8_t *data, size_t len, uint8_t *const *planes, const int *strides,
                                 void *stream, double *host_ms);
+/* Length in bits of the subsequences the device's Huffman decoding splits
+ * the data into, 64 .. 16384 (default 512; ERR_ARG outside): shorter ones
+ * give more threads, each with less to decode, and more links to follow.
+ * Process-wide. */
+int oilpaint_jpeg_set_subsequence_bits(int bits);
 /* Encode width x height interleaved RGB (device memory, rows `stride` bytes
  * apart) as a JFIF file into `out` (host memory).  *out_len receives the
  * file's length; ERR_NOMEM if it exceeds `capacity` (out untouched).  The

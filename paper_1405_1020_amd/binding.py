@@ -112,6 +112,7 @@ _SIGS = {
                               ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p,
                               ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "oilpaint_jpeg_encode_bound": ([ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+    "oilpaint_jpeg_set_subsequence_bits": ([ctypes.c_int], ctypes.c_int),
     "oilpaint_jpeg_encode_info": ([ctypes.c_int] * 4 + [ctypes.c_void_p], ctypes.c_int),
     "oilpaint_jpeg_write": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                              ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -443,6 +444,11 @@ def jpeg_write(coef, width: int, height: int, quality: int, subsampling: int) ->
     _check(lib().oilpaint_jpeg_write(coef.ctypes.data, width, height, quality, subsampling, buf, n.value,
                                      ctypes.byref(n)), "oilpaint_jpeg_write")
     return buf.raw[:n.value]
+
+
+def jpeg_set_subsequence_bits(bits: int) -> None:
+    """oilpaint_jpeg_set_subsequence_bits (process-wide)."""
+    _check(lib().oilpaint_jpeg_set_subsequence_bits(int(bits)), "oilpaint_jpeg_set_subsequence_bits")
 
 
 def jpeg_decode(data: bytes, out=None, stream=None, times: dict | None = None):

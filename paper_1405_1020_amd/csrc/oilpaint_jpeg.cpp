@@ -8,6 +8,8 @@
 // oilpaint_k_huff.hip, so a decoded image lands in device memory, ready for
 // the filter, and an encoded one is read from there.
 #include <algorithm>
+#include <atomic>
+#include <climits>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -733,6 +735,20 @@ struct JpegDevice {
     uint8_t* stuffed = nullptr;
     size_t bits_cap = 0, offset_cap = 0, tiles_cap = 0, words_cap = 0, stuffed_cap = 0;
     int cus = 0;
+    // Huffman decoding on the device: the staged upload (stripped data,
+    // tables, subsequences, intervals) in `stage` (pinned) and `dstage`, the
+    // rounds' state, block bases and DC sums.
+    uint8_t* stage = nullptr;
+    uint8_t* dstage = nullptr;
+    size_t stage_cap = 0, dstage_cap = 0;
+    JpegTrack* tracks = nullptr;   // 2 x bpm per subsequence
+    JpegLink* links = nullptr;
+    JpegEntry* entries = nullptr;
+    uint32_t* dflags = nullptr;    // [0] malformed, [2..3] a prefix-sum total
+    uint32_t* dcdiff = nullptr;    // 2 x blocks: differences, then their component order
+    uint64_t* dsum = nullptr;      // blocks: prefix sums
+    uint8_t* hwork = nullptr;      // pinned: tracks and links down, entries up
+    size_t tracks_cap = 0, links_cap = 0, entries_cap = 0, dcdiff_cap = 0, dsum_cap = 0, hwork_cap = 0;
     ~JpegDevice() {
         if (pending) (void)hipEventSynchronize(done);
         if (coef) (void)hipFree(coef);
@@ -741,8 +757,11 @@ struct JpegDevice {
         if (done) (void)hipEventDestroy(done);
         if (small) (void)hipFree(small);
         if (small_host) (void)hipHostFree(small_host);
-        for (void* p : {(void*)bits, (void*)offset, (void*)tiles, (void*)words, (void*)stuffed})
+        for (void* p : {(void*)bits, (void*)offset, (void*)tiles, (void*)words, (void*)stuffed, (void*)dstage,
+                        (void*)tracks, (void*)links, (void*)entries, (void*)dflags, (void*)dcdiff, (void*)dsum})
             if (p) (void)hipFree(p);
+        if (stage) (void)hipHostFree(stage);
+        if (hwork) (void)hipHostFree(hwork);
     }
     template <typename T>
     static int grow(T*& p, size_t& cap, size_t n) {
@@ -754,6 +773,29 @@ struct JpegDevice {
         if (hipMalloc(reinterpret_cast<void**>(&p), c * sizeof(T)) != hipSuccess) return OILPAINT_ERR_NOMEM;
         cap = c;
         return OILPAINT_OK;
+    }
+    int reserve_hwork(size_t n) {
+        if (n <= hwork_cap) return OILPAINT_OK;
+        if (hwork) (void)hipHostFree(hwork);
+        hwork = nullptr;
+        hwork_cap = 0;
+        const size_t c = std::max(n, (size_t)1 << 20);
+        if (hipHostMalloc(reinterpret_cast<void**>(&hwork), c, hipHostMallocDefault) != hipSuccess)
+            return OILPAINT_ERR_NOMEM;
+        hwork_cap = c;
+        return OILPAINT_OK;
+    }
+    int reserve_stage(size_t n) {
+        if (n > stage_cap) {
+            if (stage) (void)hipHostFree(stage);
+            stage = nullptr;
+            stage_cap = 0;
+            const size_t c = std::max(n, (size_t)1 << 20);
+            if (hipHostMalloc(reinterpret_cast<void**>(&stage), c, hipHostMallocDefault) != hipSuccess)
+                return OILPAINT_ERR_NOMEM;
+            stage_cap = c;
+        }
+        return grow(dstage, dstage_cap, n);
     }
     int reserve_coder(int device) {
         if (!small) {
@@ -845,10 +887,381 @@ JpegIdctArgs idct_args(const Frame& f, const int16_t* coef) {
     return a;
 }
 
-// Parse, entropy-decode into the pinned buffer and start the upload and the
-// inverse DCT on `stream`; planes as given (device pointers, component
-// samples only) or the library's own (whole padded grids).
-int decode_to_planes(const uint8_t* data, size_t len, JpegDevice& jd, Frame& f, uint8_t* const* user_planes,
+// ---------------------------------------------------------------------------
+// Huffman decoding on the device (oilpaint_k_huffdec.hip): the host strips
+// the markers and plans the subsequences, the kernels decode.
+// ---------------------------------------------------------------------------
+std::atomic<int> g_sub_bits{kJpegSubBits};
+
+// Scan sc's entropy-coded bytes without the stuffed zero bytes and the RST
+// markers (T.81 B.1.1.5, E.1.4), appended to out; starts receives the byte
+// offset in out of each restart interval's data, then the end.  Inside a
+// scan's data every 0xFF is followed by 0x00 or RSTn (the parser ends the
+// data at any other marker).
+void strip_scan(const uint8_t* d, const Scan& sc, std::vector<uint8_t>& out, std::vector<size_t>& starts) {
+    starts.push_back(out.size());
+    size_t i = sc.begin;
+    while (i < sc.end) {
+        const void* hit = std::memchr(d + i, 0xFF, sc.end - i);
+        const size_t k = hit ? (size_t)(static_cast<const uint8_t*>(hit) - d) : sc.end;
+        out.insert(out.end(), d + i, d + k);
+        if (k + 1 >= sc.end) break;
+        if (d[k + 1] == 0x00) {
+            out.push_back(0xFF);
+        } else {
+            starts.push_back(out.size());  // RSTn
+        }
+        i = k + 2;
+    }
+    starts.push_back(out.size());
+}
+
+void to_dev_table(const HuffDec& h, JpegHuffTable& t) {
+    std::memcpy(t.fast, h.fast, sizeof(t.fast));
+    for (int l = 0; l < 18; ++l) t.maxcode[l] = l < 17 ? h.maxcode[l] : INT32_MAX;
+    std::memcpy(t.valoff, h.valoff, sizeof(t.valoff));
+    std::memcpy(t.vals, h.vals, sizeof(t.vals));
+}
+
+// One scan's plan: its map, tables, subsequences and intervals, and where its
+// pieces sit in the staged upload.
+struct ScanPlan {
+    JpegDecScan s;
+    int sub_bits = kJpegSubBits;
+    size_t words_off = 0, tables_off = 0, subs_off = 0, segs_off = 0;
+    std::vector<JpegSub> subs;
+    std::vector<JpegSeg> segs;
+    JpegHuffTable tables[8];
+    HuffDec hdec[8];  // the same tables for the host's own decoding
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Plans every scan, stages the upload in jd.stage and returns its size.
+int plan_scans(const uint8_t* data, const Frame& f, std::vector<ScanPlan>& plans, std::vector<uint8_t>& bytes,
+               size_t* stage_bytes) {
+    const uint64_t sub_bits = (uint64_t)g_sub_bits.load();
+    plans.resize(f.scans.size());
+    for (size_t si = 0; si < f.scans.size(); ++si) {
+        const Scan& sc = f.scans[si];
+        ScanPlan& pl = plans[si];
+        JpegDecScan& s = pl.s;
+        std::memset(&s, 0, sizeof(s));
+        // tables: the scan's DC and AC tables in force
+        std::memset(pl.tables, 0, sizeof(pl.tables));
+        for (int t = 0; t < 8; ++t)
+            for (int l = 0; l < 18; ++l) pl.tables[t].maxcode[l] = -1;
+        bool built[8] = {};
+        for (const ScanComp& c : sc.comps) {
+            for (int cls = 0; cls < 2; ++cls) {
+                const int id = cls ? 4 + c.ta : c.td;
+                if (built[id]) continue;
+                HuffDec& h = pl.hdec[id];
+                if (!build_dec(cls ? sc.ac[c.ta] : sc.dc[c.td], h)) return OILPAINT_ERR_ARG;
+                to_dev_table(h, pl.tables[id]);
+                built[id] = true;
+            }
+        }
+        // the MCU: every scan component's blocks in turn
+        int j = 0;
+        s.ns = (int)sc.comps.size();
+        const bool inter = s.ns > 1;
+        for (int k = 0; k < s.ns; ++k) {
+            const ScanComp& c = sc.comps[k];
+            const int hh = inter ? f.h[c.comp] : 1, vv = inter ? f.v[c.comp] : 1;
+            s.off[k] = j;
+            s.nb[k] = hh * vv;
+            if (j + hh * vv > kJpegMaxMcuBlocks) return OILPAINT_ERR_ARG;  // T.81 B.2.3: at most 10
+            for (int v = 0; v < vv; ++v)
+                for (int h = 0; h < hh; ++h, ++j) {
+                    s.comp[j] = c.comp;
+                    s.dx[j] = h;
+                    s.dy[j] = v;
+                    s.dct[j] = c.td;
+                    s.act[j] = c.ta;
+                }
+            s.h[c.comp] = hh;
+            s.v[c.comp] = vv;
+        }
+        for (int c = 0; c < f.ncomp; ++c) {
+            s.bw[c] = f.bw[c];
+            s.first[c] = f.first[c];
+        }
+        s.bpm = j;
+        for (int b = 0; b < j; ++b) {
+            s.dsel |= (uint32_t)s.dct[b] << (2 * b);
+            s.asel |= (uint32_t)s.act[b] << (2 * b);
+        }
+        s.mcux = inter ? f.mcux : f.own_bw[sc.comps[0].comp];
+        s.mcus = inter ? (int64_t)f.mcux * f.mcuy
+                       : (int64_t)f.own_bw[sc.comps[0].comp] * f.own_bh[sc.comps[0].comp];
+        s.blocks = s.mcus * s.bpm;
+        s.restart = f.restart;
+        // the data, word aligned, and its restart intervals
+        bytes.resize(align_up(bytes.size(), 4));
+        pl.words_off = bytes.size();
+        std::vector<size_t> starts;
+        strip_scan(data, sc, bytes, starts);
+        bytes.insert(bytes.end(), 16, 0);  // readable words past the end
+        s.nwords = (int64_t)((bytes.size() - pl.words_off) / 4);
+        const int64_t nseg = f.restart ? (s.mcus + f.restart - 1) / f.restart : 1;
+        if ((int64_t)starts.size() - 1 < nseg) return OILPAINT_ERR_ARG;  // a restart marker is missing
+        for (int64_t g = 0; g < nseg; ++g) {
+            JpegSeg seg;
+            seg.first_block = (f.restart ? g * f.restart : 0) * s.bpm;
+            seg.end_block = std::min<int64_t>(s.mcus, f.restart ? (g + 1) * f.restart : s.mcus) * s.bpm;
+            seg.first_sub = (int32_t)pl.subs.size();
+            seg.pad = 0;
+            pl.segs.push_back(seg);
+            const uint64_t b0 = 8 * (uint64_t)(starts[g] - starts[0]);
+            const uint64_t b1 = 8 * (uint64_t)(starts[g + 1] - starts[0]);
+            const uint64_t n = std::max<uint64_t>(1, (b1 - b0 + sub_bits - 1) / sub_bits);
+            for (uint64_t q = 0; q < n; ++q) {
+                JpegSub sb;
+                sb.begin = b0 + q * sub_bits;
+                sb.end = q + 1 == n ? b1 : b0 + (q + 1) * sub_bits;
+                sb.seg_end = b1;
+                sb.seg = (int32_t)g;
+                sb.flags = (q == 0 ? 1 : 0) | (q + 1 == n ? 2 : 0);
+                pl.subs.push_back(sb);
+            }
+        }
+        if (pl.subs.size() > (size_t)INT32_MAX / 2) return OILPAINT_ERR_UNSUPPORTED;
+        s.nsub = (int32_t)pl.subs.size();
+        s.check_bits = (int32_t)std::min<uint64_t>(kJpegCheckBits, sub_bits / 2);
+        pl.sub_bits = (int)sub_bits;
+    }
+    // tables, subsequences and intervals after the data
+    size_t off = align_up(bytes.size(), 16);
+    for (ScanPlan& pl : plans) {
+        pl.tables_off = off;
+        off += sizeof(pl.tables);
+        pl.subs_off = off = align_up(off, 16);
+        off += pl.subs.size() * sizeof(JpegSub);
+        pl.segs_off = off = align_up(off, 16);
+        off += pl.segs.size() * sizeof(JpegSeg);
+        off = align_up(off, 16);
+    }
+    *stage_bytes = off;
+    return OILPAINT_OK;
+}
+
+// The device's decoding step on the host, for the subsequences whose true
+// decoding meets no track: the same state (bit, block of the MCU,
+// coefficient), the same tables and rules, over the same stripped data.
+struct HostStepper {
+    const uint8_t* data;  // the scan's stripped bytes, 16 zero bytes after
+    const ScanPlan* pl;
+    uint32_t peek32(uint64_t p, uint64_t end) const {
+        if (p >= end) return 0u;
+        const uint8_t* b = data + (p >> 3);
+        const uint64_t x = (uint64_t)b[0] << 32 | (uint64_t)b[1] << 24 | (uint64_t)b[2] << 16 | (uint64_t)b[3] << 8 | b[4];
+        uint32_t v = (uint32_t)(x >> (8 - (p & 7)));
+        if (end - p < 32) v &= 0xFFFFFFFFu << (32 - (uint32_t)(end - p));
+        return v;
+    }
+    static int lookup(const HuffDec& t, uint32_t top, uint32_t& len) {
+        const uint32_t e = t.fast[top >> 7];
+        if (e) {
+            len = e >> 8;
+            return (int)(e & 255u);
+        }
+        for (uint32_t l = 10; l <= 16; ++l) {
+            const int32_t code = (int32_t)(top >> (16 - l));
+            if (code <= t.maxcode[l]) {
+                len = l;
+                return t.vals[(code + t.valoff[l]) & 255];
+            }
+        }
+        len = 1;
+        return -1;
+    }
+    // One symbol; false for a malformed code (the state then moves one bit).
+    bool step(uint64_t& p, uint32_t& j, uint32_t& z, uint32_t& done, uint64_t end) const {
+        const JpegDecScan& s = pl->s;
+        const uint32_t v = peek32(p, end);
+        uint32_t len;
+        if (z == 0) {
+            const int cat = lookup(pl->hdec[s.dct[j]], v >> 16, len);
+            if (cat < 0 || cat > 11) {
+                p += 1;
+                return false;
+            }
+            p += len + (uint32_t)cat;
+            z = 1;
+        } else {
+            const int rs = lookup(pl->hdec[4 + s.act[j]], v >> 16, len);
+            if (rs < 0) {
+                p += 1;
+                return false;
+            }
+            const uint32_t r = (uint32_t)rs >> 4, sz = (uint32_t)rs & 15u;
+            if (sz == 0) {
+                p += len;
+                z = r == 15 ? z + 16 : 64;
+            } else {
+                if (z + r > 63 || sz > 10) {
+                    p += 1;
+                    return false;
+                }
+                p += len + sz;
+                z += r + 1;
+            }
+        }
+        if (z >= 64) {
+            z = 0;
+            j = j + 1 == (uint32_t)s.bpm ? 0u : j + 1;
+            ++done;
+        }
+        return true;
+    }
+    // Decode from `state` until the position reaches `until`; the blocks
+    // completed.
+    uint32_t run_until(uint64_t& state, uint64_t seg_end, uint64_t until) const {
+        uint64_t p = state >> 16;
+        uint32_t j = (uint32_t)(state >> 8) & 255u, z = (uint32_t)state & 255u, done = 0;
+        while (p < until) (void)step(p, j, z, done, seg_end);
+        state = p << 16 | (uint64_t)j << 8 | z;
+        return done;
+    }
+};
+
+// Follow the links from every restart interval's start: the two parts of
+// every subsequence's true decoding into entries[2i], entries[2i + 1].
+void walk_links(const ScanPlan& pl, const uint8_t* data, const JpegTrack* tracks, const JpegLink* links,
+                JpegEntry* entries) {
+    const int nt = 2 * pl.s.bpm;
+    const uint64_t ck = (uint64_t)pl.s.check_bits;
+    const HostStepper hs{data, &pl};
+    for (const JpegSeg& seg : pl.segs) {
+        int i = seg.first_sub;
+        uint64_t state = pl.subs[i].begin << 16;  // block 0, its DC: track 0
+        int u = 0;
+        uint32_t pre = tracks[(size_t)i * nt].pre;
+        int64_t block = seg.first_block;
+        for (;; ++i) {
+            const JpegSub& sub = pl.subs[i];
+            JpegEntry& a = entries[2 * (size_t)i];
+            JpegEntry& b = entries[2 * (size_t)i + 1];
+            a.state = state;
+            a.block = block;
+            b.block = -1;
+            b.state = 0;
+            b.stop = 0;
+            if (sub.flags & 2) {
+                a.stop = kJpegStopAtBlocks;
+                break;
+            }
+            const JpegSub& nx = pl.subs[i + 1];
+            uint32_t blocks;
+            if (u >= 0) {  // the true decoding follows track u from its checkpoint
+                const JpegTrack& t = tracks[(size_t)i * nt + u];
+                const JpegLink& l = links[(size_t)i * nt + u];
+                a.stop = sub.begin + ck;
+                b.state = t.check;
+                b.block = block + pre;
+                b.stop = sub.end;
+                blocks = pre + t.post;
+                state = t.exit;
+                u = l.next == kJpegNoTrack ? -1 : (int)l.next;
+                pre = l.blocks;
+            } else {  // no track: decode this subsequence here, in one part there
+                a.stop = sub.end;
+                blocks = hs.run_until(state, sub.seg_end, sub.end);
+                uint64_t probe = state;
+                pre = hs.run_until(probe, nx.seg_end, nx.begin + ck);
+                for (int v = 0; v < nt; ++v)
+                    if (tracks[(size_t)(i + 1) * nt + v].check == probe) {
+                        u = v;
+                        break;
+                    }
+            }
+            block += blocks;
+        }
+    }
+}
+
+// Entropy-decode every scan on the device into jd.coef (zeroed first; the
+// blocks no scan covers stay 0).  Waits for each scan's tracks and, at the
+// end, for the decoding, to report a malformed stream.
+int device_entropy_decode(const uint8_t* data, const Frame& f, JpegDevice& jd, int device, hipStream_t s,
+                          double* host_ms, std::chrono::steady_clock::time_point t0) {
+    std::vector<ScanPlan> plans;
+    std::vector<uint8_t> bytes;
+    bytes.reserve(f.scans.empty() ? 0 : f.scans.back().end - f.scans.front().begin + 64);
+    size_t total = 0;
+    int st = plan_scans(data, f, plans, bytes, &total);
+    if (st != OILPAINT_OK) return st;
+    if ((st = jd.reserve_stage(total)) != OILPAINT_OK) return st;
+    std::memcpy(jd.stage, bytes.data(), bytes.size());
+    size_t max_sub = 1, max_tracks = 1;
+    for (ScanPlan& pl : plans) {
+        std::memcpy(jd.stage + pl.tables_off, pl.tables, sizeof(pl.tables));
+        std::memcpy(jd.stage + pl.subs_off, pl.subs.data(), pl.subs.size() * sizeof(JpegSub));
+        std::memcpy(jd.stage + pl.segs_off, pl.segs.data(), pl.segs.size() * sizeof(JpegSeg));
+        max_sub = std::max(max_sub, pl.subs.size());
+        max_tracks = std::max(max_tracks, pl.subs.size() * 2 * (size_t)pl.s.bpm);
+    }
+    double host = ms_since(t0);
+    if ((st = jd.reserve_coder(device)) != OILPAINT_OK) return st;
+    const size_t nblk = std::max<size_t>(f.blocks, 1);
+    if ((st = JpegDevice::grow(jd.tracks, jd.tracks_cap, max_tracks)) != OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.links, jd.links_cap, max_tracks)) != OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.entries, jd.entries_cap, 2 * max_sub)) != OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.dcdiff, jd.dcdiff_cap, 2 * nblk)) != OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.dsum, jd.dsum_cap, nblk)) != OILPAINT_OK ||
+        (st = JpegDevice::grow(jd.tiles, jd.tiles_cap, (size_t)huff_scan_tiles((int64_t)nblk))) != OILPAINT_OK ||
+        (st = jd.reserve_hwork(max_tracks * (sizeof(JpegTrack) + sizeof(JpegLink)) + 2 * max_sub * sizeof(JpegEntry))) !=
+            OILPAINT_OK)
+        return st;
+    if (!jd.dflags && hipMalloc(reinterpret_cast<void**>(&jd.dflags), 16) != hipSuccess) return OILPAINT_ERR_NOMEM;
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(jd.dstage, jd.stage, total, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        note_hip("hipMemsetAsync", hipMemsetAsync(jd.coef, 0, f.blocks * 64 * sizeof(int16_t), s)) != hipSuccess ||
+        note_hip("hipMemsetAsync", hipMemsetAsync(jd.dflags, 0, 16, s)) != hipSuccess)
+        return OILPAINT_ERR_HIP;
+    JpegTrack* htracks = reinterpret_cast<JpegTrack*>(jd.hwork);
+    JpegLink* hlinks = reinterpret_cast<JpegLink*>(jd.hwork + max_tracks * sizeof(JpegTrack));
+    JpegEntry* hentries =
+        reinterpret_cast<JpegEntry*>(jd.hwork + max_tracks * (sizeof(JpegTrack) + sizeof(JpegLink)));
+    for (ScanPlan& pl : plans) {
+        JpegDecScan sc = pl.s;
+        sc.words = reinterpret_cast<const uint32_t*>(jd.dstage + pl.words_off);
+        sc.tables = reinterpret_cast<const JpegHuffTable*>(jd.dstage + pl.tables_off);
+        sc.subs = reinterpret_cast<const JpegSub*>(jd.dstage + pl.subs_off);
+        sc.segs = reinterpret_cast<const JpegSeg*>(jd.dstage + pl.segs_off);
+        sc.coef = jd.coef;
+        sc.dcdiff = jd.dcdiff;
+        const size_t ntr = pl.subs.size() * 2 * (size_t)pl.s.bpm;
+        if (launch_huff_tracks(sc, pl.sub_bits, jd.tracks, jd.links, s) != hipSuccess ||
+            note_hip("hipMemcpyAsync", hipMemcpyAsync(htracks, jd.tracks, ntr * sizeof(JpegTrack),
+                                                      hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            note_hip("hipMemcpyAsync", hipMemcpyAsync(hlinks, jd.links, ntr * sizeof(JpegLink),
+                                                      hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+        const auto t1 = std::chrono::steady_clock::now();
+        walk_links(pl, bytes.data() + pl.words_off, htracks, hlinks, hentries);
+        host += ms_since(t1);
+        if (note_hip("hipMemcpyAsync", hipMemcpyAsync(jd.entries, hentries, 2 * pl.subs.size() * sizeof(JpegEntry),
+                                                      hipMemcpyHostToDevice, s)) != hipSuccess ||
+            launch_huff_decode(sc, pl.sub_bits, jd.entries, jd.dflags, jd.tiles, reinterpret_cast<uint64_t*>(jd.dflags + 2),
+                               jd.dcdiff + nblk, jd.dsum, s) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+    }
+    uint32_t* flags_host = reinterpret_cast<uint32_t*>(jd.small_host->totals);
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(flags_host, jd.dflags, 4, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+        return OILPAINT_ERR_HIP;
+    if (host_ms) *host_ms = host;
+    return flags_host[0] ? OILPAINT_ERR_ARG : OILPAINT_OK;
+}
+
+// Parse, entropy-decode on the device and start the inverse DCT on `stream`;
+// planes as given (device pointers, component samples only) or the
+// library's own (whole padded grids).
+int decode_to_planes(const uint8_t* data, size_t len, JpegDevice& jd, int device, Frame& f, uint8_t* const* user_planes,
                      const int* user_strides, hipStream_t stream, double* host_ms) {
     const auto t0 = std::chrono::steady_clock::now();
     int st = parse_frame(data, len, f);
@@ -859,11 +1272,7 @@ int decode_to_planes(const uint8_t* data, size_t len, JpegDevice& jd, Frame& f, 
     plane_layout(f, nullptr, lib_planes, lib_strides, &plane_bytes);
     if ((st = jd.wait()) != OILPAINT_OK) return st;
     if ((st = jd.reserve(f.blocks * 64, user_planes ? 0 : plane_bytes)) != OILPAINT_OK) return st;
-    if ((st = entropy_decode(data, f, jd.host)) != OILPAINT_OK) return st;
-    if (host_ms) *host_ms = ms_since(t0);
-    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(jd.coef, jd.host, f.blocks * 64 * sizeof(int16_t),
-                                                  hipMemcpyHostToDevice, stream)) != hipSuccess)
-        return OILPAINT_ERR_HIP;
+    if ((st = device_entropy_decode(data, f, jd, device, stream, host_ms, t0)) != OILPAINT_OK) return st;
     JpegIdctArgs a = idct_args(f, jd.coef);
     if (user_planes) {
         for (int c = 0; c < f.ncomp; ++c) {
@@ -949,7 +1358,7 @@ int oilpaint_jpeg_decode(const uint8_t* data, size_t len, uint8_t* dst, int dst_
     std::lock_guard<std::mutex> lock(jd.mu);
     const hipStream_t s = (hipStream_t)stream;
     Frame f;
-    if ((st = decode_to_planes(data, len, jd, f, nullptr, nullptr, s, host_ms)) != OILPAINT_OK) return st;
+    if ((st = decode_to_planes(data, len, jd, device, f, nullptr, nullptr, s, host_ms)) != OILPAINT_OK) return st;
     JpegColorArgs c;
     std::memset(&c, 0, sizeof(c));
     uint8_t* planes[kJpegMaxComps];
@@ -990,8 +1399,14 @@ int oilpaint_jpeg_decode_planes(const uint8_t* data, size_t len, uint8_t* const*
     std::lock_guard<std::mutex> lock(jd.mu);
     const hipStream_t s = (hipStream_t)stream;
     Frame f;
-    if ((st = decode_to_planes(data, len, jd, f, planes, strides, s, host_ms)) != OILPAINT_OK) return st;
+    if ((st = decode_to_planes(data, len, jd, device, f, planes, strides, s, host_ms)) != OILPAINT_OK) return st;
     return jd.mark(s);
+}
+
+int oilpaint_jpeg_set_subsequence_bits(int bits) {
+    if (bits < 64 || bits > kJpegMaxSubBits) return OILPAINT_ERR_ARG;
+    g_sub_bits.store(bits);
+    return OILPAINT_OK;
 }
 
 size_t oilpaint_jpeg_encode_bound(int width, int height) {

@@ -21,6 +21,7 @@ import oracle.jpeg_ref as J
 from paper_1405_1020_amd import binding as B
 from paper_1405_1020_amd import synth
 from gpu_util import torch_mod
+from jpeg_scans import split_scans
 
 pytestmark = pytest.mark.gpu
 PIL = pytest.importorskip("PIL.Image")
@@ -39,11 +40,13 @@ def near_half(v: np.ndarray, window: np.ndarray) -> np.ndarray:
     return np.abs(f - 0.5) < window
 
 
-def check_planes(data: bytes, planes_gpu) -> int:
-    """Every sample of every component against the oracle; returns how many
-    sat within the fp32 bound of a rounding boundary."""
+def check_planes(data: bytes, planes_gpu, coefs=None) -> int:
+    """Every sample of every component against the oracle (its inverse DCT
+    of `coefs`, by default its own decoding of the file's coefficients);
+    returns how many sat within the fp32 bound of a rounding boundary."""
     j = J.parse(data)
-    coefs = J.decode_coefficients(j)
+    if coefs is None:
+        coefs = J.decode_coefficients(j)
     want = J.reconstruct_planes(j, coefs)
     vals, sums = J.idct_values(j, coefs)
     flagged = 0
@@ -109,6 +112,106 @@ def test_decode_full_hd():
     check_planes(data, planes)
     want = J.planes_to_rgb(J.parse(data), [p.cpu().numpy() for p in planes])
     assert np.array_equal(rgb.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("ss,restart", [(2, 0), (0, 7), (1, 1)])
+def test_decode_per_component_scans(ss, restart):
+    """Files with one scan per component (blocks over each component's own
+    grid), with and without restart intervals."""
+    torch = torch_mod()
+    img = synth.make_image(203, 117, seed=11 + ss, n_blobs=6, sigma=(2, 40))
+    data = split_scans(pil_jpeg(img, 85, ss), restart)
+    assert len(J.parse(data).scans) == 3
+    planes = B.jpeg_decode_planes(data)
+    torch.cuda.synchronize()
+    check_planes(data, planes)
+
+
+def test_decode_any_subsequence_length():
+    """The device decoder gives the same samples whatever the subsequences'
+    length, 64 bits (many subsequences and links, a short checkpoint) to
+    16384; interleaved, restart-marked and per-component files, and noise at
+    quality 100 (long codes, stuffed bytes, few end-of-block codes, so that
+    tracks rarely meet the true decoding and the host decodes many
+    subsequences itself)."""
+    torch = torch_mod()
+    img = synth.make_image(640, 480, seed=21, n_blobs=12, sigma=(2, 60))
+    noise = np.random.default_rng(8).integers(0, 256, (96, 160, 3), dtype=np.uint8)
+    files = [pil_jpeg(img, 90, 2), pil_jpeg(img, 75, 0, restart_marker_blocks=5),
+             split_scans(pil_jpeg(img[:200, :300].copy(), 80, 1), 9), pil_jpeg(noise, 100, 0)]
+    ref = [[p.cpu().numpy() for p in B.jpeg_decode_planes(f)] for f in files]
+    check_planes(files[1], [torch.from_numpy(p) for p in ref[1]])
+    check_planes(files[3], [torch.from_numpy(p) for p in ref[3]])
+    try:
+        for bits in (64, 100, 333, 4096, 16384):
+            B.jpeg_set_subsequence_bits(bits)
+            for f, r in zip(files, ref):
+                got = [p.cpu().numpy() for p in B.jpeg_decode_planes(f)]
+                assert all(np.array_equal(a, b) for a, b in zip(got, r)), bits
+    finally:
+        B.jpeg_set_subsequence_bits(512)
+    with pytest.raises(B.OilpaintError):
+        B.jpeg_set_subsequence_bits(63)
+
+
+def test_decode_corrupt_streams_as_host_decoder():
+    """Bits flipped in the entropy-coded data: the device decoder reports a
+    malformed stream (ERR_ARG) exactly when the library's host decoder does,
+    and otherwise decodes the host decoder's coefficients (the oracle's
+    inverse DCT of them gives its samples)."""
+    torch = torch_mod()
+    img = synth.make_image(160, 120, seed=31, n_blobs=6, sigma=(2, 40))
+    data = pil_jpeg(img, 80, 2, restart_marker_blocks=4)
+    begin = data.index(b"\xff\xda") + 2 + (data[data.index(b"\xff\xda") + 2] << 8 | data[data.index(b"\xff\xda") + 3])
+    end = len(data) - 2
+    rng = np.random.default_rng(5)
+    outcomes = set()
+    cases = []
+    for trial in range(24):
+        b = bytearray(data)
+        while True:
+            pos = int(rng.integers(begin + 1, end - 1))
+            new = b[pos] ^ (1 << int(rng.integers(0, 8)))
+            if 0xFF not in (b[pos - 1], b[pos], new):
+                break
+        b[pos] = new
+        cases.append(bytes(b))
+    # 64 one bits (stuffed 0xFF bytes) in the middle of the data: no code is
+    # all ones (T.81 C), so both decoders must stop there
+    mid = (begin + end) // 2
+    while 0xFF in data[mid - 1:mid + 1]:
+        mid += 1
+    cases.append(data[:mid] + b"\xff\x00" * 8 + data[mid:])
+    B.jpeg_set_subsequence_bits(64)
+    try:
+        for trial, bad in enumerate(cases):
+            try:
+                B.jpeg_coefficients(bad)
+                host_ok = True
+            except B.OilpaintError as e:
+                assert e.status == B.ERR_ARG
+                host_ok = False
+            try:
+                planes = B.jpeg_decode_planes(bad)
+                torch.cuda.synchronize()
+                dev_ok = True
+            except B.OilpaintError as e:
+                assert e.status == B.ERR_ARG
+                dev_ok = False
+            assert host_ok == dev_ok, trial
+            if dev_ok:
+                # the oracle's decoder stops at a marker where the library
+                # reads zero bits (an interval whose data runs short), so
+                # the coefficients here are the host decoder's
+                info, coef = B.jpeg_coefficients(bad)
+                coefs = [coef.reshape(-1, 64)[info.first_block[c]:info.first_block[c] + info.blocks_w[c] *
+                                               info.blocks_h[c]].reshape(info.blocks_h[c], info.blocks_w[c], 64)
+                         .astype(np.int64) for c in range(info.components)]
+                check_planes(bad, planes, coefs)
+            outcomes.add(dev_ok)
+    finally:
+        B.jpeg_set_subsequence_bits(512)
+    assert outcomes == {True, False}
 
 
 def check_encoded(img: np.ndarray, data: bytes, quality: int, ss: int) -> int:

@@ -121,3 +121,19 @@ def test_errors():
         B.jpeg_encode_info(10, 10, 0, 0)
     with pytest.raises(B.OilpaintError):
         B.jpeg_encode_info(10, 10, 50, 3)
+
+
+@pytest.mark.parametrize("ss,restart", [(2, 0), (0, 7), (1, 1)])
+def test_entropy_decode_per_component_scans(ss, restart):
+    """The host decoder on files with one scan per component (T.81 A.2.2),
+    written by the test helper, against the oracle's decoder."""
+    from jpeg_scans import split_scans
+    img = synth.make_image(71, 45, seed=ss, n_blobs=4, sigma=(2, 20))
+    data = split_scans(pil_jpeg(img, 85, ss), restart)
+    info, coef = B.jpeg_coefficients(data)
+    j = J.parse(data)
+    want = J.decode_coefficients(j)
+    for c in range(3):
+        first, bw, bh = info.first_block[c], info.blocks_w[c], info.blocks_h[c]
+        got = coef.reshape(-1, 64)[first:first + bw * bh].reshape(bh, bw, 64)
+        assert np.array_equal(got, want[c])

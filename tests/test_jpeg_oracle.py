@@ -232,3 +232,22 @@ def test_forward_path_matches_libjpeg(quality):
                 qc, _, _ = J.quantize_blocks(planes[c], j.qtables[j.components[c].tq])
                 d = np.abs(qc - coefs[c])
                 assert d.max() <= 2 and (d == 0).mean() > 0.99
+
+
+@pytest.mark.parametrize("ss,restart", [(2, 0), (0, 7), (1, 1)])
+def test_split_scans_helper_keeps_coefficients(ss, restart):
+    """The test helper that rewrites a file with one scan per component keeps
+    every coefficient of each component's own block grid (read back by the
+    oracle's decoder, which follows T.81's non-interleaved order)."""
+    from jpeg_scans import split_scans
+    img = np.random.default_rng(ss).integers(0, 256, (37, 53, 3), dtype=np.uint8)
+    data = pil_jpeg(img, 85, ss)
+    split = split_scans(data, restart)
+    j0, j1 = J.parse(data), J.parse(split)
+    assert len(j1.scans) == 3 and j1.restart == restart
+    a, b = J.decode_coefficients(j0), J.decode_coefficients(j1)
+    _, _, _, _, grids = J.block_grid(j0)
+    for c in range(3):
+        (_, _), (bw, bh) = grids[c]
+        assert np.array_equal(a[c][:bh, :bw], b[c][:bh, :bw])
+        assert not b[c][bh:].any() and not b[c][:, bw:].any()
