@@ -168,7 +168,16 @@ int parse_frame(const uint8_t* d, size_t n, Frame& f) {
                 sc.ac[t] = ac[t];
             }
             sc.begin = i;
-            while (i + 1 < n && !(d[i] == 0xFF && d[i + 1] != 0 && !(d[i + 1] >= 0xD0 && d[i + 1] <= 0xD7))) ++i;
+            // the data ends at the first 0xFF followed by neither a stuffed
+            // zero nor RSTn
+            for (;;) {
+                const void* hit = i < n ? std::memchr(d + i, 0xFF, n - i) : nullptr;
+                i = hit ? (size_t)(static_cast<const uint8_t*>(hit) - d) : n;
+                if (i + 1 >= n) break;
+                const uint8_t nx = d[i + 1];
+                if (nx != 0 && !(nx >= 0xD0 && nx <= 0xD7)) break;
+                i += 2;
+            }
             if (i + 1 >= n) return OILPAINT_ERR_ARG;
             sc.end = i;
             f.scans.push_back(sc);
@@ -942,6 +951,10 @@ int plan_scans(const uint8_t* data, const Frame& f, std::vector<ScanPlan>& plans
                size_t* stage_bytes) {
     const uint64_t sub_bits = (uint64_t)g_sub_bits.load();
     plans.resize(f.scans.size());
+    for (ScanPlan& pl : plans) {
+        pl.subs.clear();
+        pl.segs.clear();
+    }
     for (size_t si = 0; si < f.scans.size(); ++si) {
         const Scan& sc = f.scans[si];
         ScanPlan& pl = plans[si];
@@ -1006,6 +1019,8 @@ int plan_scans(const uint8_t* data, const Frame& f, std::vector<ScanPlan>& plans
         s.nwords = (int64_t)((bytes.size() - pl.words_off) / 4);
         const int64_t nseg = f.restart ? (s.mcus + f.restart - 1) / f.restart : 1;
         if ((int64_t)starts.size() - 1 < nseg) return OILPAINT_ERR_ARG;  // a restart marker is missing
+        pl.segs.reserve((size_t)nseg);
+        pl.subs.reserve((size_t)nseg + 8 * (starts.back() - starts.front()) / sub_bits + 1);
         for (int64_t g = 0; g < nseg; ++g) {
             JpegSeg seg;
             seg.first_block = (f.restart ? g * f.restart : 0) * s.bpm;
@@ -1186,9 +1201,11 @@ void walk_links(const ScanPlan& pl, const uint8_t* data, const JpegTrack* tracks
 // end, for the decoding, to report a malformed stream.
 int device_entropy_decode(const uint8_t* data, const Frame& f, JpegDevice& jd, int device, hipStream_t s,
                           double* host_ms, std::chrono::steady_clock::time_point t0) {
-    std::vector<ScanPlan> plans;
-    std::vector<uint8_t> bytes;
-    bytes.reserve(f.scans.empty() ? 0 : f.scans.back().end - f.scans.front().begin + 64);
+    // kept from call to call on each thread (their pages stay mapped)
+    static thread_local std::vector<ScanPlan> plans;
+    static thread_local std::vector<uint8_t> bytes;
+    bytes.clear();
+    bytes.reserve(f.scans.empty() ? 0 : f.scans.back().end - f.scans.front().begin + 64 * f.scans.size());
     size_t total = 0;
     int st = plan_scans(data, f, plans, bytes, &total);
     if (st != OILPAINT_OK) return st;
