@@ -713,14 +713,12 @@ void fill_info(const Frame& f, oilpaint_jpeg_info* info) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-device buffers: coefficients (device and pinned host) and sample
-// planes, grown on demand; `done` marks the end of the last call's device
-// work on them, `uploaded` the end of its host-to-device copy.
+// Per-device buffers: coefficients and sample planes, grown on demand;
+// `done` marks the end of the last call's device work on them.
 // ---------------------------------------------------------------------------
 struct JpegDevice {
     std::mutex mu;
     int16_t* coef = nullptr;
-    int16_t* host = nullptr;
     size_t coef_cap = 0;  // coefficients
     uint8_t* planes = nullptr;
     size_t plane_cap = 0;
@@ -761,7 +759,6 @@ struct JpegDevice {
     ~JpegDevice() {
         if (pending) (void)hipEventSynchronize(done);
         if (coef) (void)hipFree(coef);
-        if (host) (void)hipHostFree(host);
         if (planes) (void)hipFree(planes);
         if (done) (void)hipEventDestroy(done);
         if (small) (void)hipFree(small);
@@ -823,15 +820,10 @@ struct JpegDevice {
             return OILPAINT_ERR_HIP;
         if (ncoef > coef_cap) {
             if (coef) (void)hipFree(coef);
-            if (host) (void)hipHostFree(host);
             coef = nullptr;
-            host = nullptr;
             coef_cap = 0;
             const size_t cap = std::max(ncoef, (size_t)1 << 20);
             if (hipMalloc(&coef, cap * sizeof(int16_t)) != hipSuccess) return OILPAINT_ERR_NOMEM;
-            if (hipHostMalloc(reinterpret_cast<void**>(&host), cap * sizeof(int16_t), hipHostMallocDefault) !=
-                hipSuccess)
-                return OILPAINT_ERR_NOMEM;
             coef_cap = cap;
         }
         if (nplane > plane_cap) {
