@@ -149,10 +149,13 @@ int oilpaint_async(const uint8_t *src, uint8_t *dst, int width, int height, int 
  *                         chip; one wavefront per workgroup, or, for radius
  *                         <= 15 and at most 64 levels, 1, 2 or 4 wavefronts
  *                         sharing the strip (runs as in STREAM: waves x 64
- *                         threads work one run of `rows` output rows).
+ *                         threads work one run of `rows` output rows), and
+ *                         for radius 16..31 and at most 64 levels 2 or 4
+ *                         (the same count-word form with wider fields).
  *                         Batches and plans run such jobs with 4 wavefronts
- *                         from radius 7; below it in the streamed layout
- *                         (with waves = 1 in the paper form).
+ *                         from radius 7 to 15; below it in the streamed
+ *                         layout (with waves = 1 in the paper form); above
+ *                         it with one wavefront.
  *   OILPAINT_HIST_REGS    the PACKED bin word of every level in each lane's
  *                         own registers instead of LDS (the listing's
  *                         per-level arrays per thread): a window update adds

@@ -60,6 +60,7 @@ size_t lds_bytes(const Job& j) {
     }
     if (j.hist == OILPAINT_HIST_COLUMN) {
         if (column15(j)) return column15_lds_bytes(j.levels, j.waves);
+        if (column31(j)) return column31_lds_bytes(j.levels, j.waves);
         const size_t tw = 64 + 2 * (size_t)j.radius;
         return ((nb * tw * 8 + 15) & ~(size_t)15) + (tw + 1) * 16 + 192;
     }
@@ -141,7 +142,9 @@ int apply_variant(Job& j, const oilpaint_variant& v, int device) {
             return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_COLUMN) {
         // several wavefronts per strip in the radius <= 15 form only
-        const bool ok_waves = v.waves == 1 || (column15(j) && column15_wave_index(v.waves) >= 0);
+        Job jw = j;
+        jw.waves = v.waves;
+        const bool ok_waves = v.waves == 1 || (column15(j) && column15_wave_index(v.waves) >= 0) || column31(jw);
         if (j.radius > kColumnMaxRadius || !ok_waves || v.lanes != 64) return OILPAINT_ERR_UNSUPPORTED;
     } else if (v.hist == OILPAINT_HIST_WIDE) {
         if (j.radius > kWideMaxRadius) return OILPAINT_ERR_UNSUPPORTED;

@@ -312,10 +312,21 @@ __device__ __forceinline__ uint32_t shifted_prefix(uint32_t s0, uint32_t s1, int
 //   LDS, after the count words: [keys: NV x 64 x 4 B][partial words:
 //   (NV - 1) x 64 x 8 B, slot (w - finalizer - 1) mod NV][output row
 //   buffer: 192 B]
-template <int NW, int NV>
+//
+// WIDE: the form for radius 16..31 (tile_column31 below): windows up to
+// 63 x 63, so window counts need 12 bits -- two 16-bit counts per word (word
+// w: levels 2w, 2w+1) -- and window sums 20 bits, more than a 64-bit word
+// holds beside them: pass 2 sums the column entries into two words, sums 0
+// and 2 in one, sum 1 and the count in the other, each field with room to
+// grow.  Column entries keep the F18 word (a column holds at most 63
+// pixels).  Partial words are 16 bytes per lane.
+template <int NW, int NV, bool WIDE = false>
 __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* lds) {
     static_assert(NV == 1 || NV == 2 || NV == 4, "one, two or four wavefronts per strip");
-    constexpr int CS = kColumn15Stride;
+    constexpr int CS = WIDE ? kColumn31Stride : kColumn15Stride;
+    constexpr int FB = WIDE ? 16 : 10;                 // bits of a count field
+    constexpr int NF = WIDE ? 2 : 3;                   // count fields per word
+    constexpr uint32_t FM = (1u << FB) - 1u;
     constexpr int RS = CS * 8;  // bytes per level row
     constexpr int NT = 64 * NV;
     constexpr int NPX = 4 / NV;  // step pixels per lane of each wavefront
@@ -333,7 +344,7 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
     uint32_t* cw = reinterpret_cast<uint32_t*>(lds + (size_t)L * RS);
     uint32_t* keys = cw + NW * CS;
     uint64_t* words = reinterpret_cast<uint64_t*>(keys + NV * 64);
-    uint8_t* obuf = reinterpret_cast<uint8_t*>(words + (NV - 1) * 64);
+    uint8_t* obuf = reinterpret_cast<uint8_t*>(words + (NV - 1) * 64 * (WIDE ? 2 : 1));
     const bool paper = j.paper != 0;
     auto barrier = [] {
         if constexpr (NV > 1)
@@ -349,9 +360,11 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
     auto inc = [](const PixelBytes& p) -> uint64_t {
         return ((uint64_t)((p.c2 << 4) | (1u << 22)) << 32) | (p.c0 | (p.c1 << 18));
     };
-    // count word and field of level k < 128: k / 3 == (43 k) >> 7
-    auto count_word = [](uint32_t k) { return mul24(k, 43u) >> 7; };
-    auto count_bit = [&](uint32_t k) { return 1u << mul24(10u, k - mul24(3u, count_word(k))); };
+    // count word and field of level k < 128: k / 3 == (43 k) >> 7, or k / 2
+    auto count_word = [](uint32_t k) { return WIDE ? k >> 1 : mul24(k, 43u) >> 7; };
+    auto count_bit = [&](uint32_t k) {
+        return WIDE ? 1u << (16u * (k & 1u)) : 1u << mul24(10u, k - mul24(3u, count_word(k)));
+    };
     auto entry_at = [&](uint32_t k, int c) {
         return reinterpret_cast<uint64_t*>(ch + mul24(k, RS) + (uint32_t)c * 8u);
     };
@@ -434,8 +447,8 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
             const uint32_t s1 = wave_scan_add(v1) + (uint32_t)__builtin_amdgcn_readlane((int)s0, 63);
             const uint32_t dd = shifted_prefix(s0, s1, lane, 2 * R) - (s0 - v0);
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-                key = max(key, (((dd >> (10 * k)) & 1023u) << 7) | (127u - (uint32_t)(3 * w + k)));
+            for (int k = 0; k < NF; ++k)
+                key = max(key, (((dd >> (FB * k)) & FM) << 7) | (127u - (uint32_t)(NF * w + k)));
         }
         if constexpr (NV > 1) keys[wv * 64 + lane] = key;
         barrier();
@@ -458,27 +471,75 @@ __device__ __forceinline__ void tile_column15(const Job& j, int unit, uint8_t* l
         // pass 2: this wavefront's share of the winning level's window word
         const uint32_t n = key >> 7;
         const uint64_t* ent = entry_at(127u - (key & 127u), lane);
-        uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        int d = d0;
-#pragma unroll 1
-        for (; d + 4 <= d1; d += 4) {
-            a0 += ent[d];
-            a1 += ent[d + 1];
-            a2 += ent[d + 2];
-            a3 += ent[d + 3];
-        }
-        for (; d < d1; ++d) a0 += ent[d];
-        uint64_t word = (a0 + a1) + (a2 + a3);
         const int fin = NV == 1 ? 0 : ((y - ya) & (NV - 1));
-        if constexpr (NV > 1)
-            if (wv != fin) words[((wv - fin - 1) & (NV - 1)) * 64 + lane] = word;
-        barrier();
-        if (wv == fin) {
-            if constexpr (NV > 1) {
-#pragma unroll
-                for (int v = 0; v < NV - 1; ++v) word += words[v * 64 + lane];
+        if constexpr (!WIDE) {
+            uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int d = d0;
+#pragma unroll 1
+            for (; d + 4 <= d1; d += 4) {
+                a0 += ent[d];
+                a1 += ent[d + 1];
+                a2 += ent[d + 2];
+                a3 += ent[d + 3];
             }
-            store_row(j, x0, y, n, finalize_packed<false>(n, word), obuf);
+            for (; d < d1; ++d) a0 += ent[d];
+            uint64_t word = (a0 + a1) + (a2 + a3);
+            if constexpr (NV > 1)
+                if (wv != fin) words[((wv - fin - 1) & (NV - 1)) * 64 + lane] = word;
+            barrier();
+            if (wv == fin) {
+                if constexpr (NV > 1) {
+#pragma unroll
+                    for (int v = 0; v < NV - 1; ++v) word += words[v * 64 + lane];
+                }
+                store_row(j, x0, y, n, finalize_packed<false>(n, word), obuf);
+            }
+        } else {
+            // sums 0 and 2 (bits 0 and 36) in one word, sum 1 and the count
+            // (bits 0 and 36 after a shift by 18) in the other: each total
+            // stays below 2^20, clear of the next field
+            constexpr uint64_t MA = 0x3FFFFull | (0x3FFFFull << 36);
+            constexpr uint64_t MB = 0x3FFFFull | (0x3FFull << 36);
+            uint64_t a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+            int d = d0;
+#pragma unroll 1
+            for (; d + 2 <= d1; d += 2) {
+                const uint64_t e0 = ent[d], e1 = ent[d + 1];
+                a0 += e0 & MA;
+                b0 += (e0 >> 18) & MB;
+                a1 += e1 & MA;
+                b1 += (e1 >> 18) & MB;
+            }
+            if (d < d1) {
+                const uint64_t e0 = ent[d];
+                a0 += e0 & MA;
+                b0 += (e0 >> 18) & MB;
+            }
+            uint64_t wa = a0 + a1, wb = b0 + b1;
+            if constexpr (NV > 1)
+                if (wv != fin) {
+                    uint64_t* slot = words + (size_t)((wv - fin - 1) & (NV - 1)) * 128 + 2 * lane;
+                    slot[0] = wa;
+                    slot[1] = wb;
+                }
+            barrier();
+            if (wv == fin) {
+                if constexpr (NV > 1) {
+#pragma unroll
+                    for (int v = 0; v < NV - 1; ++v) {
+                        const uint64_t* slot = words + (size_t)v * 128 + 2 * lane;
+                        wa += slot[0];
+                        wb += slot[1];
+                    }
+                }
+                const uint32_t nn = n ? n : 1u;
+                const double rn = 1.0 / (double)nn;
+                const uint32_t s0 = (uint32_t)wa & 0xFFFFFu, s2 = (uint32_t)(wa >> 36) & 0xFFFFFu;
+                const uint32_t s1 = (uint32_t)wb & 0xFFFFFu;
+                store_row(j, x0, y, n,
+                          div_exact32(s0, nn, rn) | (div_exact32(s1, nn, rn) << 8) | (div_exact32(s2, nn, rn) << 16),
+                          obuf);
+            }
         }
 #pragma unroll
         for (int q = 0; q < NPX; ++q)

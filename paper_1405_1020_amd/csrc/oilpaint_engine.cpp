@@ -57,6 +57,12 @@ int batch_shape(Job& j, int device) {
         v.waves = 1;
         v.per_cu = 8;
     }
+    if (v.hist == OILPAINT_HIST_COLUMN && v.waves > 1 && j.radius > kPackedMaxRadius) {
+        // the radius 16..31 form has no persistent kernel: the generic column classes
+        v.waves = 1;
+        v.rows = 0;
+        v.per_cu = 8;
+    }
     if (v.hist == OILPAINT_HIST_COLUMN && v.waves > 1) {
         // the column layout's four-wavefront classes from
         // kBatchColumnMinRadius; below it the streamed layout's classes,

@@ -43,6 +43,23 @@ inline size_t column15_lds_bytes(int levels, int waves) {
 }
 // Wavefronts per strip of the radius <= 15 form: 1, 2 or 4 (index 0, 1, 2).
 inline int column15_wave_index(int waves) { return waves == 1 ? 0 : waves == 2 ? 1 : waves == 4 ? 2 : -1; }
+// The same form for radius 16..31 (tile_column15's WIDE form, plain
+// launches with two or four wavefronts per strip; one wavefront keeps the
+// generic column form): level rows of kColumn31Stride columns, two 16-bit
+// counts per word (column31_words(levels) words, bucketed: 4, 10, 16, 32).
+constexpr int kColumn31Stride = 126;  // 64 + 2 * 31
+constexpr int kColumn31MinRadius = 16;
+constexpr int kColumn31MaxRadius = 31;
+inline int column31_bucket(int levels) { return levels <= 8 ? 0 : levels <= 20 ? 1 : levels <= 32 ? 2 : 3; }
+inline int column31_words(int levels) {
+    constexpr int kWords[kColumn15Buckets] = {4, 10, 16, 32};
+    return kWords[column31_bucket(levels)];
+}
+// [column histograms][count words][keys][partial word pairs][row buffer]
+inline size_t column31_lds_bytes(int levels, int waves) {
+    return (size_t)levels * kColumn31Stride * 8 + (size_t)column31_words(levels) * kColumn31Stride * 4 +
+           (size_t)waves * 64 * 4 + (size_t)(waves - 1) * 64 * 16 + 192;
+}
 // Largest window pixel count the packed layout's division table covers.
 constexpr int kPackedMaxCount = 961;
 
@@ -104,6 +121,11 @@ __host__ __device__ inline bool is_split(const Job& j) { return is_stream(j.hist
 // Whether a column-layout job takes the radius <= 15 form.
 inline bool column15(const Job& j) {
     return j.radius >= 0 && j.radius <= kPackedMaxRadius && j.levels >= 1 && j.levels <= kColumn15MaxLevels;
+}
+// Whether a column-layout job takes the radius 16..31 form.
+inline bool column31(const Job& j) {
+    return j.radius >= kColumn31MinRadius && j.radius <= kColumn31MaxRadius && j.levels >= 1 &&
+           j.levels <= kColumn15MaxLevels && (j.waves == 2 || j.waves == 4);
 }
 inline int split_bins(int levels) {
     return levels <= 8 ? 2 : levels <= 16 ? 4 : levels <= 20 ? 5 : levels <= 32 ? 8 : 16;
@@ -225,6 +247,8 @@ extern const BatchKernel kBatchColumn[kColumnChunks];
 // Its radius <= 15 form, [column15_wave_index(waves)][column15_bucket(levels)];
 // batch forms with one and with four wavefronts per strip.
 extern const PlainKernel kColumn15[3][kColumn15Buckets];
+// Its radius 16..31 form, [waves == 4][column31_bucket(levels)].
+extern const PlainKernel kColumn31[2][kColumn15Buckets];
 extern const BatchKernel kBatchColumn15[kColumn15Buckets];
 extern const BatchKernel kBatchColumn15x4[kColumn15Buckets];
 

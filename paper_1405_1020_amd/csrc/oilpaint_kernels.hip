@@ -89,6 +89,7 @@ int g_split_lds_done[8][4];
 int g_split4_lds_done[kPackedMaxRadius + 1][5];
 int g_column_lds_done[kColumnChunks];
 int g_column15_lds_done[3][kColumn15Buckets];
+int g_column31_lds_done[2][kColumn15Buckets];
 int g_plain_lds_done;
 int g_regs_lds_done;
 int g_batch_lds_done[kBatchClasses];
@@ -122,6 +123,11 @@ hipError_t launch_plain(const Job& j, int waves, size_t lds, hipStream_t stream)
             if (wi < 0) return hipErrorInvalidValue;
             k = kColumn15[wi][b];
             done = &g_column15_lds_done[wi][b];
+        } else if (column31(j)) {
+            const int b = column31_bucket(j.levels), wi = j.waves == 4 ? 1 : 0;
+            if (waves != j.waves) return hipErrorInvalidValue;
+            k = kColumn31[wi][b];
+            done = &g_column31_lds_done[wi][b];
         } else {
             if (waves != 1) return hipErrorInvalidValue;
             const int nt = column_chunks(j.radius);

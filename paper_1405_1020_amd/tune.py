@@ -72,6 +72,10 @@ def candidates(radius: int, levels: int) -> list[B.Variant]:
     if radius > 15:
         for per_cu in (1, 2, 4, 8, 16):
             out.append(B.Variant(0, 1, B.HIST_COLUMN, 64, per_cu))
+        if radius <= 31 and levels <= 64:
+            # the count-word form with wider fields, two or four wavefronts per strip
+            for waves, per_cu in ((2, 4), (2, 8), (4, 2), (4, 4), (4, 5), (4, 6), (4, 8)):
+                out.append(B.Variant(0, waves, B.HIST_COLUMN, 64, per_cu))
     elif radius >= 3 and levels <= 64:
         # column histograms cost O(levels) per row (and 2r+1 reads for the
         # winning level): they can win at wide windows and few levels; one,

@@ -156,7 +156,8 @@ def test_stream8_limits():
 def test_column_limits():
     # column histograms: 64 lanes, radius <= 255, and the (levels + 1) x
     # (64 + 2r) 8-byte histograms within the on-chip budget; one wavefront
-    # per strip, or two or four in the radius <= 15 form
+    # per strip, or two or four in the count-word forms (radius <= 31, at most
+    # 64 levels)
     v = B.Variant(0, 1, B.HIST_COLUMN, 64, 2)
     try:
         assert B.set_variant(0, 1, v) == B.OK
@@ -164,15 +165,19 @@ def test_column_limits():
         assert B.set_variant(32, 40, v) == B.OK
         assert B.set_variant(256, 20, v) == B.ERR_UNSUPPORTED
         assert B.set_variant(200, 256, v) == B.ERR_UNSUPPORTED
-        assert B.set_variant(20, 20, B.Variant(0, 2, B.HIST_COLUMN, 64, 2)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(32, 20, B.Variant(0, 2, B.HIST_COLUMN, 64, 2)) == B.ERR_UNSUPPORTED
         assert B.set_variant(20, 20, B.Variant(0, 1, B.HIST_COLUMN, 32, 2)) == B.ERR_UNSUPPORTED
-        # two or four wavefronts per strip: radius <= 15 and at most 64 levels
+        # two or four wavefronts per strip: radius <= 31 and at most 64 levels
         for waves in (2, 4):
             assert B.set_variant(15, 20, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.OK
             assert B.set_variant(0, 64, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.OK
-            assert B.set_variant(16, 20, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.ERR_UNSUPPORTED
+            assert B.set_variant(16, 20, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.OK
+            assert B.set_variant(31, 40, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.OK
+            assert B.set_variant(32, 20, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.ERR_UNSUPPORTED
             assert B.set_variant(15, 65, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.ERR_UNSUPPORTED
+            assert B.set_variant(20, 65, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.ERR_UNSUPPORTED
         assert B.set_variant(15, 20, B.Variant(0, 3, B.HIST_COLUMN, 64, 4)) == B.ERR_UNSUPPORTED
+        assert B.set_variant(20, 20, B.Variant(0, 3, B.HIST_COLUMN, 64, 4)) == B.ERR_UNSUPPORTED
     finally:
         B.clear_variants()
 

@@ -117,6 +117,80 @@ def test_column15_paper_form_and_bands(waves):
         B.clear_variants()
 
 
+# the radius 16..31 form (16-bit counts, 20-bit sums; two or four wavefronts
+# per strip): every radius 16..31 (some clipped by the image), both sides of
+# each count-word bucket edge (8/9, 20/21, 32/33 levels) and 64, run lengths
+# from 1 row, strips from one to three
+WIDE = [
+    ((65, 70), (16, 17, 18, 19)),
+    ((130, 57), (20, 21, 22, 23)),
+    ((200, 80), (24, 25, 26, 27)),
+    ((97, 100), (28, 29, 30, 31)),
+    ((40, 20), (16, 31)),
+]
+
+
+@pytest.mark.parametrize("waves", (2, 4))
+@pytest.mark.parametrize("case", range(len(WIDE)))
+def test_column31_matches_oracle(case, waves):
+    (w, h), radii = WIDE[case]
+    img = image(w, h, seed=600 + case)
+    for r in radii:
+        for L in (1, 8, 9, 20, 21, 32, 33, 64):
+            want = ref(img, r, L)
+            for rows in (1, 3, 64):
+                v = B.Variant(rows, waves, B.HIST_COLUMN, 64)
+                got = run_variant(img, r, L, v, pad=(w + rows) % 5)
+                mm = first_mismatch(got, want)
+                assert mm is None, (w, h, r, L, waves, rows, mm)
+
+
+@pytest.mark.parametrize("waves", (2, 4))
+def test_column31_paper_form_bands_and_batch(waves):
+    # the paper form and a row band through the registered launch shape, and
+    # a batch of the same jobs (the radius 16..31 form has no persistent
+    # kernel: the batch runs them in the generic column classes)
+    torch = torch_mod()
+    img = image(170, 120, seed=27)
+    items, want = [], []
+    try:
+        for r, L in ((16, 20), (23, 8), (31, 33), (31, 64)):
+            assert B.set_variant(r, L, B.Variant(0, waves, B.HIST_COLUMN, 64, 4)) == B.OK
+            src, _ = to_device(img)
+            junk = np.random.default_rng(r + L).integers(0, 256, img.shape, dtype=np.uint8)
+            dst, _ = to_device(junk)
+            B.run(B.Item(src, dst, r, L, flags=B.FLAG_PAPER))
+            torch.cuda.synchronize()
+            mm = first_mismatch(from_device(dst), ref(img, r, L, paper=True, out=junk.copy()))
+            assert mm is None, ("paper", r, L, waves, mm)
+            dst, _ = to_device(junk)
+            B.run(B.Item(src, dst, r, L, row_begin=21, row_end=99))
+            torch.cuda.synchronize()
+            wt = junk.copy()
+            wt[21:99] = ref(img, r, L)[21:99]
+            mm = first_mismatch(from_device(dst), wt)
+            assert mm is None, ("band", r, L, waves, mm)
+            bdst, _ = empty_like_device(img)
+            items.append(B.Item(src, bdst, r, L))
+            want.append(ref(img, r, L))
+        B.batch(items)
+        torch.cuda.synchronize()
+        for it, wt in zip(items, want):
+            mm = first_mismatch(from_device(it.dst), wt)
+            assert mm is None, ("batch", it.radius, it.levels, mm)
+    finally:
+        B.clear_variants()
+
+
+def test_column31_full_hd():
+    # 1920x1080 at r = 20, 20 levels and r = 31, 64 levels, every byte
+    img = synth.fhd_image()
+    for r, L, waves in ((20, 20, 4), (31, 64, 4), (24, 32, 2)):
+        got = run_variant(img, r, L, B.Variant(0, waves, B.HIST_COLUMN, 64, 4))
+        mm = first_mismatch(got, ref(img, r, L))
+        assert mm is None, (r, L, waves, mm)
+
+
 def test_batch_with_column15_shapes():
     # jobs whose registered shape is the r <= 15 column form: a batch runs the
     # paper form in the column layout's one-wavefront classes and the rest in

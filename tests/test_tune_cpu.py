@@ -30,3 +30,8 @@ def test_candidates_cover_registers_and_column_form():
     for r, L in [(2, 20), (5, 65)]:
         assert (B.HIST_COLUMN, 4) not in hists(r, L)
     assert (B.HIST_COLUMN, 1) in hists(16, 20)
+    # the count-word column form with two or four wavefronts up to radius 31
+    for r, L in [(16, 8), (31, 64)]:
+        assert {(B.HIST_COLUMN, 2), (B.HIST_COLUMN, 4), (B.HIST_COLUMN, 1)} <= hists(r, L)
+    for r, L in [(32, 20), (20, 65)]:
+        assert (B.HIST_COLUMN, 4) not in hists(r, L)
