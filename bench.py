@@ -162,6 +162,9 @@ def kernel_name(r: int, L: int, v) -> str:
     if v.hist == 4 and r <= 15 and L <= 64:  # column histograms, radius <= 15 form
         words = 3 if L <= 9 else 7 if L <= 21 else 11 if L <= 33 else 22
         return "k_plain_column15<%d, %d>" % (words, v.waves)
+    if v.hist == 4 and 16 <= r <= 31 and L <= 64 and v.waves in (2, 4):  # column histograms, radius 16..31 form
+        words = 4 if L <= 8 else 10 if L <= 20 else 16 if L <= 32 else 32
+        return "k_plain_column31<%d, %d>" % (words, v.waves)
     if v.hist == 4:  # column histograms
         return "k_plain_column<%d>" % ((64 + 2 * r + 63) // 64)
     if v.hist == 0 and v.lanes == 64 and r <= 15 and L <= 64:

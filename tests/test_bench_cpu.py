@@ -22,6 +22,9 @@ def test_kernel_names():
     assert bench.kernel_name(5, 8, B.Variant(0, 2, B.HIST_COLUMN, 64, 8)) == "k_plain_column15<3, 2>"
     assert bench.kernel_name(5, 64, B.Variant(0, 4, B.HIST_COLUMN, 64, 4)) == "k_plain_column15<22, 4>"
     assert bench.kernel_name(16, 20, B.Variant(0, 1, B.HIST_COLUMN, 64, 8)) == "k_plain_column<2>"
+    assert bench.kernel_name(16, 20, B.Variant(0, 4, B.HIST_COLUMN, 64, 4)) == "k_plain_column31<10, 4>"
+    assert bench.kernel_name(31, 64, B.Variant(0, 2, B.HIST_COLUMN, 64, 8)) == "k_plain_column31<32, 2>"
+    assert bench.kernel_name(32, 20, B.Variant(0, 4, B.HIST_COLUMN, 64, 4)) == "k_plain_column<2>"
     assert bench.kernel_name(15, 100, B.Variant(0, 1, B.HIST_COLUMN, 64, 8)) == "k_plain_column<2>"
     assert bench.kernel_name(5, 64, B.Variant(0, 4, B.HIST_STREAM, 64, 4)) == "k_plain_split<5, 16>"
     assert bench.kernel_name(10, 20, B.Variant(0, 4, B.HIST_STREAM8, 64, 5)) == "k_plain_split8<10, 5>"
