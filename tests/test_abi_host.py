@@ -114,6 +114,12 @@ def test_pick_variant_shapes():
     assert B.pick_variant(1920, 1080, 5, 256).hist == B.HIST_WIDE
     # a radius beyond the image behaves as the image size
     assert B.pick_variant(12, 10, 1000, 20).hist == B.HIST_STREAM
+    # rows derived from the workgroup density: about per_cu (8 by default for
+    # one wavefront) workgroups per CU, at least 2 rows, at most 1024
+    assert B.pick_variant(1920, 1080, 2, 20).rows == 16    # 30 strips x 1080 rows / (8 x 256)
+    assert B.pick_variant(640, 480, 2, 20).rows == 3       # 10 x 480 / 2048
+    assert B.pick_variant(256, 256, 2, 20).rows == 2       # half a row per workgroup: the floor
+    assert B.pick_variant(64, 100000, 2, 20).rows == 49
     assert B.pick_variant(20, 10, 1000, 20).hist == B.HIST_COLUMN  # effective radius 19
 
 
