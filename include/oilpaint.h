@@ -403,7 +403,10 @@ int oilpaint_queue_destroy(oilpaint_queue *q);
  *
  * What is computed (the same definitions as the test oracle):
  *   decode: Huffman decoding (F.2.2) on the GPU, parallel over subsequences
- *     of the entropy-coded data that resynchronize round by round (the host
+ *     of the entropy-coded data: each is decoded from every guess of where
+ *     its decoding starts, the guesses meet the true decoding at a
+ *     checkpoint (Huffman codes resynchronize), and the host follows the
+ *     links between subsequences to hand each its true start (the host also
  *     strips the byte stuffing and RST markers and plans the subsequences);
  *     on the GPU too, dequantization (A.3.5) and the 8 x 8 inverse DCT (A.3.3) in fp32, each
  *     sample + 128 rounded half up and clamped to [0, 255]; each chroma sample

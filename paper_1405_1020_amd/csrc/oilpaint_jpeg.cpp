@@ -744,7 +744,8 @@ struct JpegDevice {
     int cus = 0;
     // Huffman decoding on the device: the staged upload (stripped data,
     // tables, subsequences, intervals) in `stage` (pinned) and `dstage`, the
-    // rounds' state, block bases and DC sums.
+    // tracks, links and entries of the subsequences, the DC differences and
+    // their sums.
     uint8_t* stage = nullptr;
     uint8_t* dstage = nullptr;
     size_t stage_cap = 0, dstage_cap = 0;
