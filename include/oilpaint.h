@@ -468,9 +468,10 @@ int oilpaint_jpeg_decode(const uint8_t *data, size_t len, uint8_t *dst, int dst_
 int oilpaint_jpeg_decode_planes(const uint8_t *data, size_t len, uint8_t *const *planes, const int *strides,
                                 void *stream, double *host_ms);
 /* Length in bits of the subsequences the device's Huffman decoding splits
- * the data into, 64 .. 16384 (default 512; ERR_ARG outside): shorter ones
- * give more threads, each with less to decode, and more links to follow.
- * Process-wide. */
+ * the data into, 64 .. 16384, or 0 (the default): chosen per scan, about
+ * 0.35 x the square root of its data bits in multiples of 64 within
+ * 128 .. 1024 (ERR_ARG otherwise).  Shorter ones give more threads, each
+ * with less to decode, and more links to follow.  Process-wide. */
 int oilpaint_jpeg_set_subsequence_bits(int bits);
 /* Encode width x height interleaved RGB (device memory, rows `stride` bytes
  * apart) as a JFIF file into `out` (host memory).  *out_len receives the

@@ -447,7 +447,7 @@ def jpeg_write(coef, width: int, height: int, quality: int, subsampling: int) ->
 
 
 def jpeg_set_subsequence_bits(bits: int) -> None:
-    """oilpaint_jpeg_set_subsequence_bits (process-wide)."""
+    """oilpaint_jpeg_set_subsequence_bits (process-wide; 0: chosen per scan)."""
     _check(lib().oilpaint_jpeg_set_subsequence_bits(int(bits)), "oilpaint_jpeg_set_subsequence_bits")
 
 

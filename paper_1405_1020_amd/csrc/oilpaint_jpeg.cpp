@@ -11,6 +11,7 @@
 #include <atomic>
 #include <climits>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -723,6 +724,7 @@ struct JpegDevice {
     uint8_t* planes = nullptr;
     size_t plane_cap = 0;
     hipEvent_t done = nullptr;
+    hipEvent_t ready = nullptr;  // polled by sync()
     bool pending = false;
     // Huffman coding on the device: symbol counts, code tables and the two
     // totals (bits, 0xFF bytes) in `small` (device) and `small_host`
@@ -762,6 +764,7 @@ struct JpegDevice {
         if (coef) (void)hipFree(coef);
         if (planes) (void)hipFree(planes);
         if (done) (void)hipEventDestroy(done);
+        if (ready) (void)hipEventDestroy(ready);
         if (small) (void)hipFree(small);
         if (small_host) (void)hipHostFree(small_host);
         for (void* p : {(void*)bits, (void*)offset, (void*)tiles, (void*)words, (void*)stuffed, (void*)dstage,
@@ -849,6 +852,26 @@ struct JpegDevice {
         pending = true;
         return OILPAINT_OK;
     }
+    // Wait (host) for everything enqueued on s so far.  The calls wait for
+    // their own GPU work, tens to hundreds of microseconds, after which a
+    // blocking wait's wake-up would add about as much again: the event is
+    // polled for up to kSpinMs, and only a longer wait (other work queued on
+    // the stream before the call) blocks.
+    static constexpr double kSpinMs = 2.0;
+    int sync(hipStream_t s) {
+        if (!ready && note_hip("hipEventCreate", hipEventCreateWithFlags(&ready, hipEventDisableTiming)) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+        if (note_hip("hipEventRecord", hipEventRecord(ready, s)) != hipSuccess) return OILPAINT_ERR_HIP;
+        const auto t0 = std::chrono::steady_clock::now();
+        hipError_t e;
+        while ((e = hipEventQuery(ready)) == hipErrorNotReady) {
+            if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > kSpinMs) {
+                e = hipEventSynchronize(ready);
+                break;
+            }
+        }
+        return note_hip("hipEventQuery", e) == hipSuccess ? OILPAINT_OK : OILPAINT_ERR_HIP;
+    }
 };
 
 JpegDevice& jpeg_device(int device) {
@@ -893,7 +916,21 @@ JpegIdctArgs idct_args(const Frame& f, const int16_t* coef) {
 // Huffman decoding on the device (oilpaint_k_huffdec.hip): the host strips
 // the markers and plans the subsequences, the kernels decode.
 // ---------------------------------------------------------------------------
-std::atomic<int> g_sub_bits{kJpegSubBits};
+std::atomic<int> g_sub_bits{0};  // 0: automatic (auto_sub_bits)
+
+// The subsequence length for a scan of `bits` bits of data.  A thread
+// decodes its subsequence serially, so the tracks, links and decode passes
+// last in proportion to the length while the GPU has threads to spare; the
+// host's walk and the subsequences it decodes itself grow with their number.
+// The sum is least near a length proportional to the square root of the
+// data: about 0.35 sqrt(bits), in multiples of 64 between 128 and 1024
+// (measured best at 640x480, 1024x768, 1920x1080 and 2560x1600, quality 90:
+// 128, 192-256, 384-512 and 512-1024 bits).
+uint64_t auto_sub_bits(uint64_t bits) {
+    const double s = 0.35 * std::sqrt((double)bits);
+    const uint64_t r = (uint64_t)(s / 64.0 + 0.5) * 64;
+    return std::min<uint64_t>(1024, std::max<uint64_t>(128, r));
+}
 
 // Scan sc's entropy-coded bytes without the stuffed zero bytes and the RST
 // markers (T.81 B.1.1.5, E.1.4), appended to out; starts receives the byte
@@ -929,7 +966,7 @@ void to_dev_table(const HuffDec& h, JpegHuffTable& t) {
 // pieces sit in the staged upload.
 struct ScanPlan {
     JpegDecScan s;
-    int sub_bits = kJpegSubBits;
+    int sub_bits = 0;
     size_t words_off = 0, tables_off = 0, subs_off = 0, segs_off = 0;
     std::vector<JpegSub> subs;
     std::vector<JpegSeg> segs;
@@ -942,7 +979,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Plans every scan, stages the upload in jd.stage and returns its size.
 int plan_scans(const uint8_t* data, const Frame& f, std::vector<ScanPlan>& plans, std::vector<uint8_t>& bytes,
                size_t* stage_bytes) {
-    const uint64_t sub_bits = (uint64_t)g_sub_bits.load();
+    const uint64_t fixed_bits = (uint64_t)g_sub_bits.load();
     plans.resize(f.scans.size());
     for (ScanPlan& pl : plans) {
         pl.subs.clear();
@@ -1012,6 +1049,7 @@ int plan_scans(const uint8_t* data, const Frame& f, std::vector<ScanPlan>& plans
         s.nwords = (int64_t)((bytes.size() - pl.words_off) / 4);
         const int64_t nseg = f.restart ? (s.mcus + f.restart - 1) / f.restart : 1;
         if ((int64_t)starts.size() - 1 < nseg) return OILPAINT_ERR_ARG;  // a restart marker is missing
+        const uint64_t sub_bits = fixed_bits ? fixed_bits : auto_sub_bits(8 * (uint64_t)(starts.back() - starts.front()));
         pl.segs.reserve((size_t)nseg);
         pl.subs.reserve((size_t)nseg + 8 * (starts.back() - starts.front()) / sub_bits + 1);
         for (int64_t g = 0; g < nseg; ++g) {
@@ -1248,7 +1286,7 @@ int device_entropy_decode(const uint8_t* data, const Frame& f, JpegDevice& jd, i
                                                       hipMemcpyDeviceToHost, s)) != hipSuccess ||
             note_hip("hipMemcpyAsync", hipMemcpyAsync(hlinks, jd.links, ntr * sizeof(JpegLink),
                                                       hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+            jd.sync(s) != OILPAINT_OK)
             return OILPAINT_ERR_HIP;
         const auto t1 = std::chrono::steady_clock::now();
         walk_links(pl, bytes.data() + pl.words_off, htracks, hlinks, hentries);
@@ -1262,7 +1300,7 @@ int device_entropy_decode(const uint8_t* data, const Frame& f, JpegDevice& jd, i
     uint32_t* flags_host = reinterpret_cast<uint32_t*>(jd.small_host->totals);
     if (note_hip("hipMemcpyAsync", hipMemcpyAsync(flags_host, jd.dflags, 4, hipMemcpyDeviceToHost, s)) !=
             hipSuccess ||
-        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+        jd.sync(s) != OILPAINT_OK)
         return OILPAINT_ERR_HIP;
     if (host_ms) *host_ms = host;
     return flags_host[0] ? OILPAINT_ERR_ARG : OILPAINT_OK;
@@ -1414,7 +1452,7 @@ int oilpaint_jpeg_decode_planes(const uint8_t* data, size_t len, uint8_t* const*
 }
 
 int oilpaint_jpeg_set_subsequence_bits(int bits) {
-    if (bits < 64 || bits > kJpegMaxSubBits) return OILPAINT_ERR_ARG;
+    if (bits != 0 && (bits < 64 || bits > kJpegMaxSubBits)) return OILPAINT_ERR_ARG;
     g_sub_bits.store(bits);
     return OILPAINT_OK;
 }
@@ -1478,7 +1516,7 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
         launch_huff_stats(m, jd.coef, dev->freq, jd.cus, s) != hipSuccess ||
         note_hip("hipMemcpyAsync", hipMemcpyAsync(hs->freq, dev->freq, sizeof(hs->freq), hipMemcpyDeviceToHost,
                                                   s)) != hipSuccess ||
-        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+        jd.sync(s) != OILPAINT_OK)
         return OILPAINT_ERR_HIP;
     const auto t0 = std::chrono::steady_clock::now();
     HuffEnc dc[2], ac[2];
@@ -1519,7 +1557,7 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
         launch_huff_stuff(jd.words, nbits, jd.tiles, &dev->totals[1], jd.stuffed, s) != hipSuccess ||
         note_hip("hipMemcpyAsync", hipMemcpyAsync(hs->totals, dev->totals, sizeof(hs->totals),
                                                   hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+        jd.sync(s) != OILPAINT_OK)
         return OILPAINT_ERR_HIP;
     if (hs->totals[0] != nbits) {
         note_error("oilpaint_jpeg_encode: the device's bit count disagrees with the symbol statistics");
@@ -1531,7 +1569,7 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
     std::memcpy(out, head.data(), head.size());
     if (note_hip("hipMemcpyAsync", hipMemcpyAsync(out + head.size(), jd.stuffed, data, hipMemcpyDeviceToHost, s)) !=
             hipSuccess ||
-        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+        jd.sync(s) != OILPAINT_OK)
         return OILPAINT_ERR_HIP;
     out[*out_len - 2] = 0xFF;
     out[*out_len - 1] = 0xD9;

@@ -109,7 +109,7 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint64_t* tiles,
 // Huffman decoding on the device (oilpaint_k_huffdec.hip).  The host takes
 // the stuffed zero bytes and the RST markers out of a scan's entropy-coded
 // data (T.81 B.1.1.5, E.1.4) and cuts each restart interval's bits into
-// subsequences of kJpegSubBits bits; a subsequence decodes the symbols that
+// subsequences of equal length; a subsequence decodes the symbols that
 // start in it.  Where its decoding really starts -- the bit, the block of the
 // MCU, the coefficient -- is where its predecessor's decoding crosses into it,
 // known only by decoding everything before.  So each subsequence is first
@@ -122,9 +122,10 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint64_t* tiles,
 // and names the track met there; the host follows the links from each
 // interval's known start (decoding itself the rare subsequence whose true
 // decoding meets no track) and hands every subsequence its true start state
-// and first block; the last pass decodes and writes the coefficients.
-constexpr int kJpegSubBits = 512;    // the default; oilpaint_jpeg_set_subsequence_bits
-constexpr int kJpegCheckBits = 256;  // the checkpoint, at most the subsequence length
+// and first block; the last pass decodes and writes the coefficients.  The
+// subsequence length is chosen per scan from its length (auto_sub_bits)
+// unless oilpaint_jpeg_set_subsequence_bits fixes it.
+constexpr int kJpegCheckBits = 256;  // the checkpoint, at most half the subsequence length
 
 // One table for decoding (T.81 C, F.2.2.3): codes up to 9 bits by lookup,
 // longer ones by the largest code of each length.

@@ -214,3 +214,15 @@ def test_kernel_integer_identities():
     for L in range(1, 257):
         for s in range(766):
             assert int(((s * L) / 3.0) / 255.0) == (s * L) // 765
+
+
+def test_jpeg_subsequence_bits_range():
+    # 0 (chosen per scan) or a fixed 64 .. 16384 bits; pure host state
+    lib = B.lib()
+    try:
+        for bits in (0, 64, 512, 16384):
+            assert lib.oilpaint_jpeg_set_subsequence_bits(bits) == B.OK
+        for bits in (-1, 1, 63, 16385):
+            assert lib.oilpaint_jpeg_set_subsequence_bits(bits) == B.ERR_ARG
+    finally:
+        assert lib.oilpaint_jpeg_set_subsequence_bits(0) == B.OK

@@ -130,7 +130,7 @@ def test_decode_per_component_scans(ss, restart):
 def test_decode_any_subsequence_length():
     """The device decoder gives the same samples whatever the subsequences'
     length, 64 bits (many subsequences and links, a short checkpoint) to
-    16384; interleaved, restart-marked and per-component files, and noise at
+    16384, and with the length chosen per scan; interleaved, restart-marked and per-component files, and noise at
     quality 100 (long codes, stuffed bytes, few end-of-block codes, so that
     tracks rarely meet the true decoding and the host decodes many
     subsequences itself)."""
@@ -143,13 +143,13 @@ def test_decode_any_subsequence_length():
     check_planes(files[1], [torch.from_numpy(p) for p in ref[1]])
     check_planes(files[3], [torch.from_numpy(p) for p in ref[3]])
     try:
-        for bits in (64, 100, 333, 4096, 16384):
+        for bits in (64, 100, 333, 4096, 16384, 0):
             B.jpeg_set_subsequence_bits(bits)
             for f, r in zip(files, ref):
                 got = [p.cpu().numpy() for p in B.jpeg_decode_planes(f)]
                 assert all(np.array_equal(a, b) for a, b in zip(got, r)), bits
     finally:
-        B.jpeg_set_subsequence_bits(512)
+        B.jpeg_set_subsequence_bits(0)
     with pytest.raises(B.OilpaintError):
         B.jpeg_set_subsequence_bits(63)
 
@@ -210,7 +210,7 @@ def test_decode_corrupt_streams_as_host_decoder():
                 check_planes(bad, planes, coefs)
             outcomes.add(dev_ok)
     finally:
-        B.jpeg_set_subsequence_bits(512)
+        B.jpeg_set_subsequence_bits(0)
     assert outcomes == {True, False}
 
 
