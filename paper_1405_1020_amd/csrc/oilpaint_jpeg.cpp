@@ -724,7 +724,6 @@ struct JpegDevice {
     uint8_t* planes = nullptr;
     size_t plane_cap = 0;
     hipEvent_t done = nullptr;
-    hipEvent_t ready = nullptr;  // polled by sync()
     bool pending = false;
     // Huffman coding on the device: symbol counts, code tables and the two
     // totals (bits, 0xFF bytes) in `small` (device) and `small_host`
@@ -764,7 +763,6 @@ struct JpegDevice {
         if (coef) (void)hipFree(coef);
         if (planes) (void)hipFree(planes);
         if (done) (void)hipEventDestroy(done);
-        if (ready) (void)hipEventDestroy(ready);
         if (small) (void)hipFree(small);
         if (small_host) (void)hipHostFree(small_host);
         for (void* p : {(void*)bits, (void*)offset, (void*)tiles, (void*)words, (void*)stuffed, (void*)dstage,
@@ -851,26 +849,6 @@ struct JpegDevice {
         if (note_hip("hipEventRecord", hipEventRecord(done, s)) != hipSuccess) return OILPAINT_ERR_HIP;
         pending = true;
         return OILPAINT_OK;
-    }
-    // Wait (host) for everything enqueued on s so far.  The calls wait for
-    // their own GPU work, tens to hundreds of microseconds, after which a
-    // blocking wait's wake-up would add about as much again: the event is
-    // polled for up to kSpinMs, and only a longer wait (other work queued on
-    // the stream before the call) blocks.
-    static constexpr double kSpinMs = 2.0;
-    int sync(hipStream_t s) {
-        if (!ready && note_hip("hipEventCreate", hipEventCreateWithFlags(&ready, hipEventDisableTiming)) != hipSuccess)
-            return OILPAINT_ERR_HIP;
-        if (note_hip("hipEventRecord", hipEventRecord(ready, s)) != hipSuccess) return OILPAINT_ERR_HIP;
-        const auto t0 = std::chrono::steady_clock::now();
-        hipError_t e;
-        while ((e = hipEventQuery(ready)) == hipErrorNotReady) {
-            if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > kSpinMs) {
-                e = hipEventSynchronize(ready);
-                break;
-            }
-        }
-        return note_hip("hipEventQuery", e) == hipSuccess ? OILPAINT_OK : OILPAINT_ERR_HIP;
     }
 };
 
@@ -1286,7 +1264,7 @@ int device_entropy_decode(const uint8_t* data, const Frame& f, JpegDevice& jd, i
                                                       hipMemcpyDeviceToHost, s)) != hipSuccess ||
             note_hip("hipMemcpyAsync", hipMemcpyAsync(hlinks, jd.links, ntr * sizeof(JpegLink),
                                                       hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            jd.sync(s) != OILPAINT_OK)
+            note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
             return OILPAINT_ERR_HIP;
         const auto t1 = std::chrono::steady_clock::now();
         walk_links(pl, bytes.data() + pl.words_off, htracks, hlinks, hentries);
@@ -1300,7 +1278,7 @@ int device_entropy_decode(const uint8_t* data, const Frame& f, JpegDevice& jd, i
     uint32_t* flags_host = reinterpret_cast<uint32_t*>(jd.small_host->totals);
     if (note_hip("hipMemcpyAsync", hipMemcpyAsync(flags_host, jd.dflags, 4, hipMemcpyDeviceToHost, s)) !=
             hipSuccess ||
-        jd.sync(s) != OILPAINT_OK)
+        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
         return OILPAINT_ERR_HIP;
     if (host_ms) *host_ms = host;
     return flags_host[0] ? OILPAINT_ERR_ARG : OILPAINT_OK;
@@ -1516,7 +1494,7 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
         launch_huff_stats(m, jd.coef, dev->freq, jd.cus, s) != hipSuccess ||
         note_hip("hipMemcpyAsync", hipMemcpyAsync(hs->freq, dev->freq, sizeof(hs->freq), hipMemcpyDeviceToHost,
                                                   s)) != hipSuccess ||
-        jd.sync(s) != OILPAINT_OK)
+        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
         return OILPAINT_ERR_HIP;
     const auto t0 = std::chrono::steady_clock::now();
     HuffEnc dc[2], ac[2];
@@ -1557,7 +1535,7 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
         launch_huff_stuff(jd.words, nbits, jd.tiles, &dev->totals[1], jd.stuffed, s) != hipSuccess ||
         note_hip("hipMemcpyAsync", hipMemcpyAsync(hs->totals, dev->totals, sizeof(hs->totals),
                                                   hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        jd.sync(s) != OILPAINT_OK)
+        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
         return OILPAINT_ERR_HIP;
     if (hs->totals[0] != nbits) {
         note_error("oilpaint_jpeg_encode: the device's bit count disagrees with the symbol statistics");
@@ -1569,7 +1547,7 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
     std::memcpy(out, head.data(), head.size());
     if (note_hip("hipMemcpyAsync", hipMemcpyAsync(out + head.size(), jd.stuffed, data, hipMemcpyDeviceToHost, s)) !=
             hipSuccess ||
-        jd.sync(s) != OILPAINT_OK)
+        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
         return OILPAINT_ERR_HIP;
     out[*out_len - 2] = 0xFF;
     out[*out_len - 1] = 0xD9;
