@@ -179,8 +179,8 @@ typedef struct oilpaint_variant {
     int32_t hist;   /* OILPAINT_HIST_* */
     int32_t lanes;  /* active lanes (= output columns) per wavefront: 64, 32 or 16 */
     int32_t per_cu; /* with rows = 0: rows are chosen so that an image yields about
-                       per_cu workgroups per compute unit (1..64), then halved
-                       while the on-chip footprint does not fit */
+                       per_cu workgroups per compute unit (1..64), 2 .. 1024 rows,
+                       then halved while the on-chip footprint does not fit */
 } oilpaint_variant;
 
 /* The variant oilpaint_async would use for (radius, levels) and an image of
