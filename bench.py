@@ -991,9 +991,27 @@ def counter_fields(run: str):
 def counter_workload(name: str, torch, B, synth):
     """The camera (4000x3000, r = 10, L = 32: five plain launches) or the
     64-image batch (three replays of its captured plan), after tuning, for
-    the counter passes."""
+    the counter passes; or the JPEG leg's decode / filter (r = 2, 4, 6, 8,
+    L = 20) / encode at 640x480 or 1920x1080, six rounds, for a kernel
+    trace."""
     from paper_1405_1020_amd import tune
-    if name == "camera":
+    if name in ("jpeg640", "jpeg1920"):
+        import io
+        from PIL import Image
+        w, h = (640, 480) if name == "jpeg640" else (1920, 1080)
+        tune.ensure([(r, 20) for r in (2, 4, 6, 8)], w, h)
+        img = synth.make_image(w, h, seed=w, **synth.LARGE_BLOBS)
+        b = io.BytesIO()
+        Image.fromarray(img).save(b, format="JPEG", quality=90, subsampling=2)
+        data = b.getvalue()
+        dev = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(dev)
+        for _ in range(6):
+            B.jpeg_decode(data, out=dev)
+            for r in (2, 4, 6, 8):
+                B.oilpaint_async(dev, dst, r, 20)
+            B.jpeg_encode(dst, quality=90, subsampling=2)
+    elif name == "camera":
         tune.ensure([synth.CAMERA_RL], 4000, 3000)
         src = torch.from_numpy(synth.camera_image()).cuda()
         dst = torch.empty_like(src)
@@ -1030,7 +1048,7 @@ def main():
                     help="print per sweep run the kernel-trace durations from rocprofv3 --kernel-trace output in DIR")
     ap.add_argument("--counter-summary", metavar="DIR",
                     help="write the LDS/VALU counter summary under profiles/ from the counter passes in DIR")
-    ap.add_argument("--counter-workload", choices=["camera", "batched"],
+    ap.add_argument("--counter-workload", choices=["camera", "batched", "jpeg640", "jpeg1920"],
                     help="run only that workload (for a counter pass) and exit")
     ap.add_argument("--sweep-json", metavar="FILE",
                     help="with --hbm-summary or --trace-summary: the output of the profiled bench.py --quick run")

@@ -1,10 +1,11 @@
 // Device steps of the JPEG codec around the filter: dequantization and the
 // 8 x 8 inverse DCT (T.81 A.3.3, A.3.5), JFIF colour conversion with chroma
 // replication (decode); JFIF colour conversion with chroma averaging, the
-// forward DCT and quantization (T.81 A.3.3, A.3.4) (encode).  One wavefront
-// per 8 x 8 block (lane = one sample or coefficient), separable passes through
-// LDS; colour conversion one lane per pixel.  Entropy decoding runs on the
-// host (oilpaint_jpeg.cpp), the encoder's Huffman coding in
+// forward DCT and quantization (T.81 A.3.3, A.3.4) (encode).  Eight lanes
+// per 8 x 8 block, eight blocks per wavefront: a lane transforms one row of
+// its block in registers, the rows meet through LDS, and the lane then
+// transforms one column; colour conversion one lane per pixel.  Huffman
+// decoding runs in oilpaint_k_huffdec.hip, the encoder's Huffman coding in
 // oilpaint_k_huff.hip.
 #include "oilpaint_internal.h"
 #include "oilpaint_jpeg.h"
@@ -13,7 +14,7 @@ namespace oilpaint_impl {
 namespace {
 
 // cos(m pi / 16) / sqrt(2), m = 0..8.
-__constant__ float kCosR2[9] = {
+constexpr float kCosR2[9] = {
     0.70710678118654752f, 0.69351992266107906f, 0.65328148243818826f, 0.58794459036236287f,
     0.50000000000000000f, 0.39284747919355110f, 0.27059805007309849f, 0.13794968964147150f,
     0.0f};
@@ -21,8 +22,9 @@ __constant__ float kCosR2[9] = {
 // sqrt(2) x C(u)/2 x cos((2x+1) u pi / 16): exactly 1/2 for u = 0 and +-1/2
 // for u = 4, so that blocks whose exact transform is rational (flat blocks,
 // the u, v in {0, 4} terms) come out exact in fp32; the transform is this
-// basis applied twice, then halved.
-__device__ __forceinline__ float basis(int u, int x) {
+// basis applied twice, then halved.  Evaluated at compile time: the loops
+// below are unrolled, so every basis value is an immediate operand.
+constexpr float basis(int u, int x) {
     if (u == 0) return 0.5f;
     const int m = ((2 * x + 1) * u) & 31;
     if (m <= 8) return kCosR2[m];
@@ -37,35 +39,66 @@ __device__ __forceinline__ int comp_of(const int32_t* first, int b) {
     return c;
 }
 
-// Four blocks per workgroup, one per wavefront.
+// Workgroup: four wavefronts of eight blocks; lane = (block, i): row i in the
+// first pass, column i in the second.  The rows' results go through LDS
+// (rows of 9 floats: a column read touches eight banks); each wavefront
+// works its own blocks, so program order keeps its LDS accesses in order.
+constexpr int kDctBlocksPerGroup = 32;
+constexpr int kDctPitch = 9;
+
+// Inverse: t[v][x] = sum_u S[v][u] B[u][x] (row v), s[y][x] = sum_v B[v][y]
+// t[v][x] (column x), each sum accumulated in index order; sample =
+// floor(clamp(s / 2 + 128.5)).
 __global__ __launch_bounds__(256) void k_jpeg_idct(JpegIdctArgs a) {
-    __shared__ float s_coef[4][64];
-    __shared__ float s_tmp[4][64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ float s_t[kDctBlocksPerGroup][8 * kDctPitch];
+    const int lane = threadIdx.x & 63;
+    const int lb = (int)(threadIdx.x >> 3);  // block within the workgroup
+    const int i = lane & 7;
     const int total = a.first[kJpegMaxComps];
-    const int b = blockIdx.x * 4 + wave;
+    const int b = blockIdx.x * kDctBlocksPerGroup + lb;
     const bool live = b < total;
     const int c = live ? comp_of(a.first, b) : 0;
-    const int r = lane >> 3, col = lane & 7;
-    if (live) s_coef[wave][lane] = (float)((int)a.coef[(size_t)b * 64 + lane] * (int)a.q[c][lane]);
-    __syncthreads();
-    // rows: t[v][x] = sum_u S[v][u] B[u][x]   (lane = (v, x))
-    float t = 0.f;
+    float* t = s_t[lb];
+    {
+        float S[8];
+        if (live) {
+            const uint4 raw = *reinterpret_cast<const uint4*>(a.coef + (size_t)b * 64 + i * 8);
+            const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t = fmaf(s_coef[wave][r * 8 + u], basis(u, col), t);
-    s_tmp[wave][lane] = t;
-    __syncthreads();
-    // columns: s[y][x] = sum_v B[v][y] t[v][x]   (lane = (y, x))
-    float s = 0.f;
+            for (int u = 0; u < 8; ++u) {
+                const int coef = (int)(int16_t)(w[u >> 1] >> (16 * (u & 1)));
+                S[u] = (float)(coef * (int)a.q[c][i * 8 + u]);
+            }
+        } else {
 #pragma unroll
-    for (int v = 0; v < 8; ++v) s = fmaf(basis(v, r), s_tmp[wave][v * 8 + col], s);
+            for (int u = 0; u < 8; ++u) S[u] = 0.f;
+        }
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            float acc = 0.f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = fmaf(S[u], basis(u, x), acc);
+            t[i * kDctPitch + x] = acc;
+        }
+    }
+    asm volatile("" ::: "memory");
+    float tv[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) tv[v] = t[v * kDctPitch + i];
     if (!live) return;
-    const int v = (int)floorf(fminf(fmaxf(s * 0.5f + 128.5f, 0.f), 255.f));
     const int k = b - a.first[c];
     const int by = k / a.bw[c], bx = k - by * a.bw[c];
-    const int y = by * 8 + r, x = bx * 8 + col;
-    if (x < a.limit_w[c] && y < a.limit_h[c])
-        a.plane[c][(size_t)y * a.stride[c] + x] = (uint8_t)v;
+    const int x = bx * 8 + i;
+    if (x >= a.limit_w[c]) return;
+#pragma unroll
+    for (int yy = 0; yy < 8; ++yy) {
+        float s = 0.f;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) s = fmaf(basis(v, yy), tv[v], s);
+        const int y = by * 8 + yy;
+        const int val = (int)floorf(fminf(fmaxf(s * 0.5f + 128.5f, 0.f), 255.f));
+        if (y < a.limit_h[c]) a.plane[c][(size_t)y * a.stride[c] + x] = (uint8_t)val;
+    }
 }
 
 // R = Y + 1.402 Cr', G = Y - 0.344136 Cb' - 0.714136 Cr', B = Y + 1.772 Cb'
@@ -126,35 +159,53 @@ __global__ __launch_bounds__(256) void k_jpeg_rgb(JpegRgbArgs a) {
     a.plane[2][(size_t)cy * a.pstride[2] + cx] = (uint8_t)((scr + n / 2) / n);
 }
 
+// Forward: t[y][u] = sum_x s[y][x] B[u][x] (row y), S[v][u] = sum_y B[v][y]
+// t[y][u] (column u), each sum accumulated in index order; quantized
+// coefficient = round half away from zero of S / 2 / Q.
 __global__ __launch_bounds__(256) void k_jpeg_fdct(JpegFdctArgs a) {
-    __shared__ float s_smp[4][64];
-    __shared__ float s_tmp[4][64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ float s_t[kDctBlocksPerGroup][8 * kDctPitch];
+    const int lane = threadIdx.x & 63;
+    const int lb = (int)(threadIdx.x >> 3);
+    const int i = lane & 7;
     const int total = a.first[kJpegMaxComps];
-    const int b = blockIdx.x * 4 + wave;
+    const int b = blockIdx.x * kDctBlocksPerGroup + lb;
     const bool live = b < total;
     const int c = live ? comp_of(a.first, b) : 0;
-    const int r = lane >> 3, col = lane & 7;
-    if (live) {
-        const int k = b - a.first[c];
-        const int by = k / a.bw[c], bx = k - by * a.bw[c];
-        s_smp[wave][lane] = (float)((int)a.plane[c][(size_t)(by * 8 + r) * a.stride[c] + bx * 8 + col] - 128);
+    float* t = s_t[lb];
+    {
+        float sm[8];
+        if (live) {
+            const int k = b - a.first[c];
+            const int by = k / a.bw[c], bx = k - by * a.bw[c];
+            const uint8_t* row = a.plane[c] + (size_t)(by * 8 + i) * a.stride[c] + bx * 8;
+#pragma unroll
+            for (int x = 0; x < 8; ++x) sm[x] = (float)((int)row[x] - 128);
+        } else {
+#pragma unroll
+            for (int x = 0; x < 8; ++x) sm[x] = 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            float acc = 0.f;
+#pragma unroll
+            for (int x = 0; x < 8; ++x) acc = fmaf(sm[x], basis(u, x), acc);
+            t[i * kDctPitch + u] = acc;
+        }
     }
-    __syncthreads();
-    // rows: t[y][u] = sum_x s[y][x] B[u][x]   (lane = (y, u))
-    float t = 0.f;
+    asm volatile("" ::: "memory");
+    float ty[8];
 #pragma unroll
-    for (int x = 0; x < 8; ++x) t = fmaf(s_smp[wave][r * 8 + x], basis(col, x), t);
-    s_tmp[wave][lane] = t;
-    __syncthreads();
-    // columns: S[v][u] = sum_y B[v][y] t[y][u]   (lane = (v, u))
-    float S = 0.f;
-#pragma unroll
-    for (int y = 0; y < 8; ++y) S = fmaf(basis(r, y), s_tmp[wave][y * 8 + col], S);
+    for (int y = 0; y < 8; ++y) ty[y] = t[y * kDctPitch + i];
     if (!live) return;
-    const float q = S * 0.5f / (float)a.q[c][lane];
-    const float m = floorf(fabsf(q) + 0.5f);
-    a.coef[(size_t)b * 64 + lane] = (int16_t)(q < 0.f ? -m : m);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        float S = 0.f;
+#pragma unroll
+        for (int y = 0; y < 8; ++y) S = fmaf(basis(v, y), ty[y], S);
+        const float q = S * 0.5f / (float)a.q[c][v * 8 + i];
+        const float m = floorf(fabsf(q) + 0.5f);
+        a.coef[(size_t)b * 64 + v * 8 + i] = (int16_t)(q < 0.f ? -m : m);
+    }
 }
 
 }  // namespace
@@ -162,7 +213,8 @@ __global__ __launch_bounds__(256) void k_jpeg_fdct(JpegFdctArgs a) {
 hipError_t launch_jpeg_idct(const JpegIdctArgs& a, hipStream_t stream) {
     const int total = a.first[kJpegMaxComps];
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_jpeg_idct, dim3((total + 3) / 4), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_jpeg_idct, dim3((total + kDctBlocksPerGroup - 1) / kDctBlocksPerGroup), dim3(256), 0,
+                       stream, a);
     return note_hip("k_jpeg_idct launch", hipGetLastError());
 }
 
@@ -182,7 +234,8 @@ hipError_t launch_jpeg_rgb(const JpegRgbArgs& a, hipStream_t stream) {
 hipError_t launch_jpeg_fdct(const JpegFdctArgs& a, hipStream_t stream) {
     const int total = a.first[kJpegMaxComps];
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_jpeg_fdct, dim3((total + 3) / 4), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_jpeg_fdct, dim3((total + kDctBlocksPerGroup - 1) / kDctBlocksPerGroup), dim3(256), 0,
+                       stream, a);
     return note_hip("k_jpeg_fdct launch", hipGetLastError());
 }
 
