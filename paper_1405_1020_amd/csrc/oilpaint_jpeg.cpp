@@ -1530,7 +1530,7 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
     if (note_hip("hipMemcpyAsync", hipMemcpyAsync(dev->tabs, hs->tabs, sizeof(hs->tabs), hipMemcpyHostToDevice,
                                                   s)) != hipSuccess ||
         note_hip("hipMemsetAsync", hipMemsetAsync(jd.words, 0, nwords * sizeof(uint32_t), s)) != hipSuccess ||
-        launch_huff_code(m, jd.coef, dev->tabs, jd.bits, jd.offset, jd.tiles, &dev->totals[0], jd.words, s) !=
+        launch_huff_code(m, jd.coef, dev->tabs, jd.bits, jd.offset, jd.tiles, &dev->totals[0], jd.words, jd.cus, s) !=
             hipSuccess ||
         launch_huff_stuff(jd.words, nbits, jd.tiles, &dev->totals[1], jd.stuffed, s) != hipSuccess ||
         note_hip("hipMemcpyAsync", hipMemcpyAsync(hs->totals, dev->totals, sizeof(hs->totals),

@@ -87,7 +87,8 @@ struct JpegScanMap {
 //     the bits of every block (bits[blocks]), their exclusive prefix sums
 //     (offset[blocks], using tiles[huff_scan_tiles(blocks)], total bits in
 //     *total) and the stream itself ORed into `words` (zeroed beforehand,
-//     ceil(total / 32) + 1 words; bit 0 the most significant of word 0).
+//     ceil(total / 32) + 1 words; bit 0 the most significant of word 0);
+//     `cus` sizes the grids.
 //   launch_huff_stuff: the nbits-bit stream, its last byte padded with one
 //     bits, with a zero byte after every 0xFF into `out` (room for twice its
 //     bytes); *ff_total receives the number of 0xFF bytes (tiles as above,
@@ -96,7 +97,7 @@ int64_t huff_scan_tiles(int64_t n);
 hipError_t launch_huff_stats(const JpegScanMap& m, const int16_t* coef, unsigned long long* freq, int cus,
                              hipStream_t stream);
 hipError_t launch_huff_code(const JpegScanMap& m, const int16_t* coef, const uint32_t* tabs, uint32_t* bits,
-                            uint64_t* offset, uint64_t* tiles, uint64_t* total, uint32_t* words,
+                            uint64_t* offset, uint64_t* tiles, uint64_t* total, uint32_t* words, int cus,
                             hipStream_t stream);
 hipError_t launch_huff_stuff(const uint32_t* words, uint64_t nbits, uint64_t* tiles, uint64_t* ff_total,
                              uint8_t* out, hipStream_t stream);

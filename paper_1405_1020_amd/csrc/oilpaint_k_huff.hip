@@ -4,8 +4,10 @@
 // of the entropy-coded data).  The host fits the tables between the
 // statistics pass and the coding passes; everything per block runs here.
 //
-// One wavefront per 8 x 8 block, lane k holding the k-th coefficient of the
-// zig-zag sequence: the nonzero AC coefficients come from one ballot; lane k
+// A wavefront works one 8 x 8 block at a time, lane k holding the k-th
+// coefficient of the zig-zag sequence, over a grid sized to the GPU (each
+// wavefront loads its next block while it codes the current one): the
+// nonzero AC coefficients come from one ballot; lane k
 // finds the zero run before it from the highest set bit below k, so every
 // symbol of the block is known at once.  A lane's bits (its ZRL codes, its
 // run/size code and its magnitude; lane 0: the DC code and magnitude) are
@@ -52,6 +54,18 @@ __device__ __forceinline__ T wave_scan(T v) {
         const T o = __shfl_up(v, d, 64);
         if (lane >= d) v += o;
     }
+    return v;
+}
+
+// The same for 32-bit values with DPP row shifts and broadcasts (no LDS
+// round trips).  Every lane must be active.
+__device__ __forceinline__ uint32_t wave_scan32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
 }
 
@@ -105,6 +119,21 @@ __device__ __forceinline__ BlockRef block_at(const JpegScanMap& m, const int16_t
     return r;
 }
 
+// What a lane needs of block t: its zig-zag coefficient (natural index zz),
+// the DC predictor (0 for the component's first block) and the table set.
+struct BlockVals {
+    int v, pred, tab;
+};
+
+__device__ __forceinline__ BlockVals load_block(const JpegScanMap& m, const int16_t* coef, int64_t t, int zz) {
+    const BlockRef b = block_at(m, coef, t);
+    BlockVals r;
+    r.v = b.coef[zz];
+    r.pred = b.pred ? (int)b.pred[0] : 0;
+    r.tab = b.tab;
+    return r;
+}
+
 // The symbols of one block, lane k for zig-zag position k:
 //   lane 0: the DC category `cat` (of the difference `val`), and whether the
 //     block ends with an EOB (its last AC coefficient is 0);
@@ -116,13 +145,13 @@ struct LaneSym {
     bool live, eob;
 };
 
-__device__ __forceinline__ LaneSym lane_symbols(const BlockRef& b) {
+__device__ __forceinline__ LaneSym lane_symbols(const BlockVals& b) {
     const int k = threadIdx.x & 63;
     LaneSym s;
-    const int v = b.coef[kZz[k]];
+    const int v = b.v;
     const uint64_t nz = __ballot(k > 0 && v != 0);
     if (k == 0) {
-        s.val = v - (b.pred ? (int)b.pred[0] : 0);
+        s.val = v - b.pred;
         s.cat = category(s.val);
         s.sym = s.cat;
         s.zrl = 0;
@@ -151,9 +180,15 @@ __global__ __launch_bounds__(1024) void k_huff_stats(JpegScanMap m, const int16_
     for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) h[i] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    const int zz = kZz[lane];
     const int waves = blockDim.x >> 6;
-    for (int64_t t = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); t < m.blocks; t += (int64_t)gridDim.x * waves) {
-        const BlockRef b = block_at(m, coef, t);
+    const int64_t stride = (int64_t)gridDim.x * waves;
+    int64_t t = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6);
+    BlockVals next{};
+    if (t < m.blocks) next = load_block(m, coef, t, zz);
+    for (; t < m.blocks; t += stride) {
+        const BlockVals b = next;
+        if (t + stride < m.blocks) next = load_block(m, coef, t + stride, zz);
         const LaneSym s = lane_symbols(b);
         uint32_t* dc = h + b.tab * 256;
         uint32_t* ac = h + (2 + b.tab) * 256;
@@ -184,21 +219,28 @@ __device__ __forceinline__ uint32_t lane_bits(const LaneSym& s, const uint32_t* 
     return s.zrl * (ac[0xF0] >> 16) + (ac[s.sym] >> 16) + s.cat;
 }
 
-// Bits of every block, one wavefront per block.
+// Bits of every block.
 __global__ __launch_bounds__(256) void k_huff_bits(JpegScanMap m, const int16_t* coef, const uint32_t* tabs,
                                                    uint32_t* bits) {
     __shared__ uint32_t tl[4 * 256];
     load_tables(tabs, tl);
-    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= m.blocks) return;
-    const BlockRef b = block_at(m, coef, t);
-    const LaneSym s = lane_symbols(b);
-    const uint32_t* dc = tl + b.tab * 256;
-    const uint32_t* ac = tl + (2 + b.tab) * 256;
-    uint32_t n = lane_bits(s, dc, ac);
-    if ((threadIdx.x & 63) == 0 && s.eob) n += ac[0x00] >> 16;
-    n = wave_scan(n);
-    if ((threadIdx.x & 63) == 63) bits[t] = n;
+    const int lane = threadIdx.x & 63;
+    const int zz = kZz[lane];
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    BlockVals next{};
+    if (t < m.blocks) next = load_block(m, coef, t, zz);
+    for (; t < m.blocks; t += stride) {
+        const BlockVals b = next;
+        if (t + stride < m.blocks) next = load_block(m, coef, t + stride, zz);
+        const LaneSym s = lane_symbols(b);
+        const uint32_t* dc = tl + b.tab * 256;
+        const uint32_t* ac = tl + (2 + b.tab) * 256;
+        uint32_t n = lane_bits(s, dc, ac);
+        if (lane == 0 && s.eob) n += ac[0x00] >> 16;
+        n = wave_scan32(n);
+        if (lane == 63) bits[t] = n;
+    }
 }
 
 // OR `len` (<= 32) bits of `val` into the stream at bit `pos`.
@@ -213,38 +255,52 @@ __device__ __forceinline__ void put_bits(uint32_t* words, uint64_t pos, uint32_t
 }
 
 // The bits of every block at its offset (exclusive prefix sum of the block
-// sizes), one wavefront per block.
+// sizes).
 __global__ __launch_bounds__(256) void k_huff_write(JpegScanMap m, const int16_t* coef, const uint32_t* tabs,
                                                     const uint64_t* offset, uint32_t* words) {
     __shared__ uint32_t tl[4 * 256];
     load_tables(tabs, tl);
-    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= m.blocks) return;
     const int lane = threadIdx.x & 63;
-    const BlockRef b = block_at(m, coef, t);
-    const LaneSym s = lane_symbols(b);
-    const uint32_t* dc = tl + b.tab * 256;
-    const uint32_t* ac = tl + (2 + b.tab) * 256;
-    const uint32_t n = lane_bits(s, dc, ac);
-    const uint32_t inc = wave_scan(n);
-    uint64_t pos = offset[t] + (inc - n);
-    if (lane == 0) {
-        const uint32_t e = dc[s.cat];
-        put_bits(words, pos, (e & 0xFFFFu) << s.cat | magnitude(s.val, s.cat), (e >> 16) + s.cat);
+    const int zz = kZz[lane];
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    BlockVals next{};
+    uint64_t next_off = 0;
+    if (t < m.blocks) {
+        next = load_block(m, coef, t, zz);
+        next_off = offset[t];
     }
-    const uint32_t body = (uint32_t)__shfl((int)inc, 63, 64);  // the block's bits before its EOB
-    if (lane == 0 && s.eob) {
-        const uint32_t e = ac[0x00];
-        put_bits(words, offset[t] + body, e & 0xFFFFu, e >> 16);
-    }
-    if (lane > 0 && s.live) {
-        const uint32_t z = ac[0xF0];
-        for (uint32_t i = 0; i < s.zrl; ++i) {
-            put_bits(words, pos, z & 0xFFFFu, z >> 16);
-            pos += z >> 16;
+    for (; t < m.blocks; t += stride) {
+        const BlockVals b = next;
+        const uint64_t off = next_off;
+        if (t + stride < m.blocks) {
+            next = load_block(m, coef, t + stride, zz);
+            next_off = offset[t + stride];
         }
-        const uint32_t e = ac[s.sym];
-        put_bits(words, pos, (e & 0xFFFFu) << s.cat | magnitude(s.val, s.cat), (e >> 16) + s.cat);
+        const LaneSym s = lane_symbols(b);
+        const uint32_t* dc = tl + b.tab * 256;
+        const uint32_t* ac = tl + (2 + b.tab) * 256;
+        const uint32_t n = lane_bits(s, dc, ac);
+        const uint32_t inc = wave_scan32(n);
+        uint64_t pos = off + (inc - n);
+        if (lane == 0) {
+            const uint32_t e = dc[s.cat];
+            put_bits(words, pos, (e & 0xFFFFu) << s.cat | magnitude(s.val, s.cat), (e >> 16) + s.cat);
+        }
+        const uint32_t body = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);  // the block's bits before its EOB
+        if (lane == 0 && s.eob) {
+            const uint32_t e = ac[0x00];
+            put_bits(words, off + body, e & 0xFFFFu, e >> 16);
+        }
+        if (lane > 0 && s.live) {
+            const uint32_t z = ac[0xF0];
+            for (uint32_t i = 0; i < s.zrl; ++i) {
+                put_bits(words, pos, z & 0xFFFFu, z >> 16);
+                pos += z >> 16;
+            }
+            const uint32_t e = ac[s.sym];
+            put_bits(words, pos, (e & 0xFFFFu) << s.cat | magnitude(s.val, s.cat), (e >> 16) + s.cat);
+        }
     }
 }
 
@@ -365,10 +421,11 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint64_t* tiles,
 }
 
 hipError_t launch_huff_code(const JpegScanMap& m, const int16_t* coef, const uint32_t* tabs, uint32_t* bits,
-                            uint64_t* offset, uint64_t* tiles, uint64_t* total, uint32_t* words,
+                            uint64_t* offset, uint64_t* tiles, uint64_t* total, uint32_t* words, int cus,
                             hipStream_t stream) {
     if (m.blocks <= 0) return hipSuccess;
-    const dim3 g((unsigned)((m.blocks + 3) / 4));
+    // eight workgroups of four wavefronts per CU, each wavefront a few blocks
+    const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((m.blocks + 3) / 4, 8 * (int64_t)std::max(cus, 1))));
     hipLaunchKernelGGL(k_huff_bits, g, dim3(256), 0, stream, m, coef, tabs, bits);
     if (launch_exclusive_scan(bits, m.blocks, tiles, total, offset, stream) != hipSuccess) return hipErrorLaunchFailure;
     hipLaunchKernelGGL(k_huff_write, g, dim3(256), 0, stream, m, coef, tabs, offset, words);
