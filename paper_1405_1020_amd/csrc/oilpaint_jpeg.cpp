@@ -933,8 +933,20 @@ void strip_scan(const uint8_t* d, const Scan& sc, std::vector<uint8_t>& out, std
     starts.push_back(out.size());
 }
 
-void to_dev_table(const HuffDec& h, JpegHuffTable& t) {
-    std::memcpy(t.fast, h.fast, sizeof(t.fast));
+void to_dev_table(const HuffSpec& spec, const HuffDec& h, JpegHuffTable& t) {
+    // the canonical codes (T.81 C.2) again; every code of at most
+    // kJpegFastBits bits fills the entries it prefixes (build_dec has
+    // checked that the codes fit their lengths)
+    std::memset(t.fast, 0, sizeof(t.fast));
+    int code = 0, k = 0;
+    for (int len = 1; len <= 16; ++len) {
+        for (int n = 0; n < spec.bits[len - 1]; ++n, ++k, ++code)
+            if (len <= kJpegFastBits) {
+                const int shift = kJpegFastBits - len;
+                for (int f = code << shift; f < ((code + 1) << shift); ++f) t.fast[f] = (uint16_t)(len << 8 | spec.vals[k]);
+            }
+        code <<= 1;
+    }
     for (int l = 0; l < 18; ++l) t.maxcode[l] = l < 17 ? h.maxcode[l] : INT32_MAX;
     std::memcpy(t.valoff, h.valoff, sizeof(t.valoff));
     std::memcpy(t.vals, h.vals, sizeof(t.vals));
@@ -978,8 +990,9 @@ int plan_scans(const uint8_t* data, const Frame& f, std::vector<ScanPlan>& plans
                 const int id = cls ? 4 + c.ta : c.td;
                 if (built[id]) continue;
                 HuffDec& h = pl.hdec[id];
-                if (!build_dec(cls ? sc.ac[c.ta] : sc.dc[c.td], h)) return OILPAINT_ERR_ARG;
-                to_dev_table(h, pl.tables[id]);
+                const HuffSpec& spec = cls ? sc.ac[c.ta] : sc.dc[c.td];
+                if (!build_dec(spec, h)) return OILPAINT_ERR_ARG;
+                to_dev_table(spec, h, pl.tables[id]);
                 built[id] = true;
             }
         }

@@ -128,10 +128,13 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint64_t* tiles,
 // unless oilpaint_jpeg_set_subsequence_bits fixes it.
 constexpr int kJpegCheckBits = 256;  // the checkpoint, at most half the subsequence length
 
-// One table for decoding (T.81 C, F.2.2.3): codes up to 9 bits by lookup,
-// longer ones by the largest code of each length.
+// One table for decoding (T.81 C, F.2.2.3): codes up to kJpegFastBits bits
+// by lookup, longer ones by the largest code of each length.  (At 9 bits the
+// lanes of a wavefront met a longer code in 71 % of the steps on a
+// 1920x1080 photo-like image at quality 90, at 11 bits in 17 %.)
+constexpr int kJpegFastBits = 11;
 struct JpegHuffTable {
-    uint16_t fast[512];   // (length << 8) | value by the 9 leading bits; 0: the code is longer
+    uint16_t fast[1 << kJpegFastBits];  // (length << 8) | value by the leading bits; 0: the code is longer
     int32_t maxcode[18];  // largest code of each length, -1 for none
     int32_t valoff[17];   // value index = code + valoff[length]
     uint8_t vals[256];
