@@ -756,7 +756,7 @@ struct JpegDevice {
     uint32_t* dflags = nullptr;    // [0] malformed, [2..3] a prefix-sum total
     uint32_t* dcdiff = nullptr;    // 2 x blocks: differences, then their component order
     uint64_t* dsum = nullptr;      // blocks: prefix sums
-    uint8_t* hwork = nullptr;      // pinned: tracks and links down, entries up
+    uint8_t* hwork = nullptr;      // pinned: tracks and links down, entries up; the coded stream down
     size_t tracks_cap = 0, links_cap = 0, entries_cap = 0, dcdiff_cap = 0, dsum_cap = 0, hwork_cap = 0;
     ~JpegDevice() {
         if (pending) (void)hipEventSynchronize(done);
@@ -1538,7 +1538,8 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
                                (size_t)std::max(huff_scan_tiles(m.blocks), huff_scan_tiles((int64_t)nbytes)))) !=
             OILPAINT_OK ||
         (st = JpegDevice::grow(jd.words, jd.words_cap, nwords)) != OILPAINT_OK ||
-        (st = JpegDevice::grow(jd.stuffed, jd.stuffed_cap, (size_t)(2 * nbytes + 16))) != OILPAINT_OK)
+        (st = JpegDevice::grow(jd.stuffed, jd.stuffed_cap, (size_t)(2 * nbytes + 16))) != OILPAINT_OK ||
+        (st = jd.reserve_hwork((size_t)(2 * nbytes + 16))) != OILPAINT_OK)
         return st;
     if (note_hip("hipMemcpyAsync", hipMemcpyAsync(dev->tabs, hs->tabs, sizeof(hs->tabs), hipMemcpyHostToDevice,
                                                   s)) != hipSuccess ||
@@ -1547,7 +1548,13 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
             hipSuccess ||
         launch_huff_stuff(jd.words, nbits, jd.tiles, &dev->totals[1], jd.stuffed, s) != hipSuccess ||
         note_hip("hipMemcpyAsync", hipMemcpyAsync(hs->totals, dev->totals, sizeof(hs->totals),
-                                                  hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                                                  hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return OILPAINT_ERR_HIP;
+    // The stuffed stream's whole room (twice the bytes, the most stuffing can
+    // make) comes down into pinned memory in the same wait as the totals,
+    // which say how much of it is the stream.
+    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(jd.hwork, jd.stuffed, 2 * (size_t)nbytes, hipMemcpyDeviceToHost,
+                                                  s)) != hipSuccess ||
         note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
         return OILPAINT_ERR_HIP;
     if (hs->totals[0] != nbits) {
@@ -1558,10 +1565,7 @@ int oilpaint_jpeg_encode(const uint8_t* src, int width, int height, int stride, 
     *out_len = head.size() + data + 2;
     if (!out || *out_len > capacity) return OILPAINT_ERR_NOMEM;
     std::memcpy(out, head.data(), head.size());
-    if (note_hip("hipMemcpyAsync", hipMemcpyAsync(out + head.size(), jd.stuffed, data, hipMemcpyDeviceToHost, s)) !=
-            hipSuccess ||
-        note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
-        return OILPAINT_ERR_HIP;
+    std::memcpy(out + head.size(), jd.hwork, data);
     out[*out_len - 2] = 0xFF;
     out[*out_len - 1] = 0xD9;
     return OILPAINT_OK;

@@ -278,6 +278,26 @@ def test_device_coder_matches_host_coder(size, quality, ss, noise):
     check_encoded(img, data, quality, ss)
 
 
+def test_encode_capacity():
+    """An output of exactly the file's length, or more, receives the same
+    file; one byte short is ERR_NOMEM with the output untouched."""
+    import ctypes
+    torch = torch_mod()
+    img = np.random.default_rng(3).integers(0, 256, (96, 160, 3), dtype=np.uint8)
+    src = torch.from_numpy(img).cuda()
+    want = B.jpeg_encode(src, quality=100, subsampling=0)
+    n = len(want)
+    w, h, s = B.image_geometry(src)
+    got = ctypes.c_size_t(0)
+    for cap in (n, n + 1, 2 * n):
+        buf = (ctypes.c_uint8 * cap)()
+        st = B.lib().oilpaint_jpeg_encode(src.data_ptr(), w, h, s, 100, 0, buf, cap, ctypes.byref(got), None, None)
+        assert st == B.OK and got.value == n and bytes(buf)[:n] == want, cap
+    buf = (ctypes.c_uint8 * (n - 1))(*([7] * (n - 1)))
+    st = B.lib().oilpaint_jpeg_encode(src.data_ptr(), w, h, s, 100, 0, buf, n - 1, ctypes.byref(got), None, None)
+    assert st == B.ERR_NOMEM and got.value == n and bytes(buf) == bytes([7] * (n - 1))
+
+
 def test_file_driver_decode_filter_encode():
     """The paper's program shape: a JPEG file decoded onto the device, the oil
     paint filter run there, the result encoded: the decoded image against
