@@ -724,6 +724,9 @@ struct JpegDevice {
     uint8_t* planes = nullptr;
     size_t plane_cap = 0;
     hipEvent_t done = nullptr;
+    // the decoder's tracks come down on `side` while the links are decoded
+    hipStream_t side = nullptr;
+    hipEvent_t tracks_done = nullptr;
     bool pending = false;
     // Huffman coding on the device: symbol counts, code tables and the two
     // totals (bits, 0xFF bytes) in `small` (device) and `small_host`
@@ -763,6 +766,8 @@ struct JpegDevice {
         if (coef) (void)hipFree(coef);
         if (planes) (void)hipFree(planes);
         if (done) (void)hipEventDestroy(done);
+        if (tracks_done) (void)hipEventDestroy(tracks_done);
+        if (side) (void)hipStreamDestroy(side);
         if (small) (void)hipFree(small);
         if (small_host) (void)hipHostFree(small_host);
         for (void* p : {(void*)bits, (void*)offset, (void*)tiles, (void*)words, (void*)stuffed, (void*)dstage,
@@ -814,6 +819,11 @@ struct JpegDevice {
         }
         if (!cus && note_hip("hipDeviceGetAttribute", hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                                                             device)) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+        if (!side && note_hip("hipStreamCreate", hipStreamCreateWithFlags(&side, hipStreamNonBlocking)) != hipSuccess)
+            return OILPAINT_ERR_HIP;
+        if (!tracks_done &&
+            note_hip("hipEventCreate", hipEventCreateWithFlags(&tracks_done, hipEventDisableTiming)) != hipSuccess)
             return OILPAINT_ERR_HIP;
         return OILPAINT_OK;
     }
@@ -1272,12 +1282,15 @@ int device_entropy_decode(const uint8_t* data, const Frame& f, JpegDevice& jd, i
         sc.coef = jd.coef;
         sc.dcdiff = jd.dcdiff;
         const size_t ntr = pl.subs.size() * 2 * (size_t)pl.s.bpm;
-        if (launch_huff_tracks(sc, pl.sub_bits, jd.tracks, jd.links, s) != hipSuccess ||
+        // the tracks come down on the side stream while the links decode
+        if (launch_huff_tracks(sc, pl.sub_bits, jd.tracks, jd.links, jd.tracks_done, s) != hipSuccess ||
+            note_hip("hipStreamWaitEvent", hipStreamWaitEvent(jd.side, jd.tracks_done, 0)) != hipSuccess ||
             note_hip("hipMemcpyAsync", hipMemcpyAsync(htracks, jd.tracks, ntr * sizeof(JpegTrack),
-                                                      hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                                                      hipMemcpyDeviceToHost, jd.side)) != hipSuccess ||
             note_hip("hipMemcpyAsync", hipMemcpyAsync(hlinks, jd.links, ntr * sizeof(JpegLink),
                                                       hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess)
+            note_hip("hipStreamSynchronize", hipStreamSynchronize(s)) != hipSuccess ||
+            note_hip("hipStreamSynchronize", hipStreamSynchronize(jd.side)) != hipSuccess)
             return OILPAINT_ERR_HIP;
         const auto t1 = std::chrono::steady_clock::now();
         walk_links(pl, bytes.data() + pl.words_off, htracks, hlinks, hentries);

@@ -210,10 +210,11 @@ struct JpegEntry {
 constexpr uint64_t kJpegStopAtBlocks = ~0ull;
 
 // Tracks and links of every subsequence (2 x bpm each); sub_bits: the
-// subsequences' length (at most kJpegMaxSubBits).
+// subsequences' length (at most kJpegMaxSubBits); tracks_done, if not null,
+// is recorded on `stream` once the tracks are written (before the links).
 constexpr int kJpegMaxSubBits = 16384;
 hipError_t launch_huff_tracks(const JpegDecScan& s, int sub_bits, JpegTrack* tracks, JpegLink* links,
-                              hipStream_t stream);
+                              hipEvent_t tracks_done, hipStream_t stream);
 // The decoding from the entries: coefficients into coef, DC differences
 // into dcdiff, a malformed code flagged in *malformed; then the DC prefix
 // sums per component and restart interval into coef (dcseq / dcsum: per

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(256) void k_dc_finish(JpegDecScan s, const uint32_t
 }  // namespace
 
 hipError_t launch_huff_tracks(const JpegDecScan& s, int sub_bits, JpegTrack* tracks, JpegLink* links,
-                              hipStream_t stream) {
+                              hipEvent_t tracks_done, hipStream_t stream) {
     if (s.nsub <= 0) return hipSuccess;
     const int nt = 2 * s.bpm;
     const int group = group_subs(nt, sub_bits);
@@ -394,6 +394,8 @@ hipError_t launch_huff_tracks(const JpegDecScan& s, int sub_bits, JpegTrack* tra
     const size_t lds = (size_t)(kTableWords + nstage) * 4;
     const dim3 g((unsigned)((s.nsub + group - 1) / group));
     hipLaunchKernelGGL(k_huff_tracks, g, dim3(256), lds, stream, s, group, nstage, tracks);
+    if (tracks_done && note_hip("hipEventRecord", hipEventRecord(tracks_done, stream)) != hipSuccess)
+        return hipErrorLaunchFailure;
     hipLaunchKernelGGL(k_huff_links, g, dim3(256), lds, stream, s, group, nstage, (const JpegTrack*)tracks, links);
     return note_hip("k_huff_links launch", hipGetLastError());
 }
