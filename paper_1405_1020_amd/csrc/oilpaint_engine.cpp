@@ -490,6 +490,15 @@ struct oilpaint_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int grid = 0;  // workgroups over all classes
+    oilpaint_plan() = default;
+    oilpaint_plan(const oilpaint_plan&) = delete;
+    oilpaint_plan& operator=(const oilpaint_plan&) = delete;
+    // also on a failed create, which returns before handing the plan out
+    ~oilpaint_plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (dev) (void)hipFree(dev);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -922,11 +931,7 @@ int oilpaint_plan_info(const oilpaint_plan* plan, int* tiles, int* workgroups) {
 }
 
 int oilpaint_plan_destroy(oilpaint_plan* plan) {
-    if (!plan) return OILPAINT_OK;
-    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    if (plan->dev) (void)hipFree(plan->dev);
-    delete plan;
+    delete plan;  // its graph and device block with it
     return OILPAINT_OK;
 }
 
