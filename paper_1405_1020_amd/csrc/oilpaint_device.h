@@ -47,6 +47,22 @@
 namespace oilpaint_impl {
 namespace dev {
 
+// The tile of this workgroup in a plain launch (one workgroup per tile,
+// tiles numbered strip by strip along each run of rows, run after run).
+// The dispatcher deals workgroups to the GPU's eight XCDs in turn (workgroup
+// b to XCD b mod 8), and each XCD has its own L2: in blockIdx order a
+// strip's neighbours, which read the same halo columns and cache lines,
+// would sit on other XCDs and fetch those lines again.  Here XCD k takes the
+// k-th eighth of the tiles, a band of whole runs, so neighbouring strips and
+// runs share one L2.  A bijection on 0 .. gridDim.x - 1 for any grid, so
+// the results do not depend on how workgroups are really dealt.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile() {
+    const int n = (int)gridDim.x, b = (int)blockIdx.x;
+    const int q = n / kXcds, r = n % kXcds, x = b % kXcds, i = b / kXcds;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Products of operands below 2^24: the masks let the compiler use the
 // full-rate 24-bit multiplies (v_mul_u32_u24, v_mul_hi_u32_u24) instead of
 // the quarter-rate 32-bit ones.  mul24 is exact while the product is below

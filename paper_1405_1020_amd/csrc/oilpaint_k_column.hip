@@ -10,7 +10,7 @@ namespace {
 template <int NT>
 __global__ __launch_bounds__(64) void k_plain_column(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_column<NT>(j, blockIdx.x, lds);
+    tile_column<NT>(j, xcd_tile(), lds);
 }
 
 template <int NT>
@@ -22,7 +22,7 @@ __global__ __launch_bounds__(64) void k_batch_column(BatchArgs a) {
 template <int NW, int NV>
 __global__ __launch_bounds__(64 * NV) void k_plain_column15(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_column15<NW, NV>(j, blockIdx.x, lds);
+    tile_column15<NW, NV>(j, xcd_tile(), lds);
 }
 
 template <int NW>

@@ -10,7 +10,7 @@ namespace {
 template <int NW, int NV>
 __global__ __launch_bounds__(64 * NV) void k_plain_column31(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_column15<NW, NV, true>(j, blockIdx.x, lds);
+    tile_column15<NW, NV, true>(j, xcd_tile(), lds);
 }
 
 }  // namespace

@@ -10,7 +10,7 @@ namespace {
 template <int R, int SB>
 __global__ __launch_bounds__(512) void k_plain_fast(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_packed_fast<R, SB>(j, blockIdx.x, lds);
+    tile_packed_fast<R, SB>(j, xcd_tile(), lds);
 }
 
 

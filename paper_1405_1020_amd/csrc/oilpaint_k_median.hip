@@ -72,8 +72,9 @@ __global__ __launch_bounds__(64) void k_median(MedianJob j) {
     extern __shared__ __align__(16) uint8_t lds[];
     const int lane = threadIdx.x & 63;
     const uint32_t lane4 = (uint32_t)lane * 4u;
-    const int tx = blockIdx.x % j.tiles_x;
-    const int ty = blockIdx.x / j.tiles_x;
+    const int unit = xcd_tile();
+    const int tx = unit % j.tiles_x;
+    const int ty = unit / j.tiles_x;
     const int x0 = tx * 64;
     const int ya = ty * j.rows;
     const int yb = min(ya + j.rows, j.height);
@@ -208,8 +209,9 @@ __global__ __launch_bounds__(256) void k_median4(MedianJob j) {
     const int c0 = w * C;
     auto mine = [&](int c) { return c < CMIN || c0 + c < F::SPAN; };  // uniform
     const uint32_t lane4 = (uint32_t)lane * 4u;
-    const int tx = blockIdx.x % j.tiles_x;
-    const int ty = blockIdx.x / j.tiles_x;
+    const int unit = xcd_tile();
+    const int tx = unit % j.tiles_x;
+    const int ty = unit / j.tiles_x;
     const int x0 = tx * 64;
     const int ya = ty * j.rows;
     const int yb = min(ya + j.rows, j.height);

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(64) void k_median_column(MedianJob j) {
     const int R = j.radius;
     const int TW = 64 + 2 * R;
     const int lane = threadIdx.x & 63;
-    const int unit = blockIdx.x;
+    const int unit = xcd_tile();
     const int tx = unit % j.tiles_x;
     const int ty = unit / j.tiles_x;
     const int x0 = tx * 64;

@@ -124,7 +124,7 @@ __device__ __forceinline__ void tile_regs(const Job& j, int unit, uint8_t* lds) 
 template <int R, int LB>
 __global__ __launch_bounds__(64) void k_plain_regs(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_regs<R, LB>(j, blockIdx.x, lds);
+    tile_regs<R, LB>(j, xcd_tile(), lds);
 }
 
 }  // namespace

@@ -11,7 +11,7 @@ namespace {
 template <int R, int MB>
 __global__ __launch_bounds__(64 * kSplitWaves, kSplitMinWaves) void k_plain_split8(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_stream_split8<R, MB>(j, blockIdx.x, lds);
+    tile_stream_split8<R, MB>(j, xcd_tile(), lds);
 }
 
 template <int R>

@@ -12,7 +12,7 @@ namespace {
 template <int R, int MB>
 __global__ __launch_bounds__(64 * kSplitWaves, kSplitMinWaves) void k_plain_split(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_stream_split<R, MB, false>(j, blockIdx.x, lds);
+    tile_stream_split<R, MB, false>(j, xcd_tile(), lds);
 }
 
 template <int R, int MB>

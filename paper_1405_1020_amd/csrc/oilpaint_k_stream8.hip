@@ -9,7 +9,7 @@ namespace {
 template <int R>
 __global__ __launch_bounds__(64) void k_plain_stream8(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_stream<R, 32, true>(j, blockIdx.x, lds);
+    tile_stream<R, 32, true>(j, xcd_tile(), lds);
 }
 
 template <int R>

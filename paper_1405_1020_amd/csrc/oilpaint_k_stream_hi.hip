@@ -9,7 +9,7 @@ namespace {
 template <int R, int SB>
 __global__ __launch_bounds__(64) void k_plain_stream(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
-    tile_stream<R, SB, false>(j, blockIdx.x, lds);
+    tile_stream<R, SB, false>(j, xcd_tile(), lds);
 }
 
 

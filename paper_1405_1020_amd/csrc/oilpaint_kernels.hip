@@ -12,9 +12,9 @@ namespace {
 __global__ __launch_bounds__(512) void k_plain(Job j) {
     extern __shared__ __align__(16) uint8_t lds[];
     if (j.hist == OILPAINT_HIST_WIDE)
-        tile_wide(j, blockIdx.x, lds);
+        tile_wide(j, xcd_tile(), lds);
     else
-        tile_packed(j, blockIdx.x, lds);
+        tile_packed(j, xcd_tile(), lds);
 }
 
 // Persistent, the generic class of a batch (tile-staged and wide layouts):
