@@ -52,15 +52,21 @@ namespace dev {
 // The dispatcher deals workgroups to the GPU's eight XCDs in turn (workgroup
 // b to XCD b mod 8), and each XCD has its own L2: in blockIdx order a
 // strip's neighbours, which read the same halo columns and cache lines,
-// would sit on other XCDs and fetch those lines again.  Here XCD k takes the
-// k-th eighth of the tiles, a band of whole runs, so neighbouring strips and
-// runs share one L2.  A bijection on 0 .. gridDim.x - 1 for any grid, so
-// the results do not depend on how workgroups are really dealt.
+// would sit on other XCDs and fetch those lines again.  Here the tiles go
+// to the XCDs in chunks of kXcdChunk neighbours, chunk c to XCD c mod 8, so
+// that neighbours share an L2 while every XCD still takes tiles from all
+// over the image (contiguous eighths measured slower where tile costs
+// vary).  A bijection on 0 .. gridDim.x - 1 (the last, partial round of
+// chunks keeps blockIdx order), so results do not depend on how workgroups
+// are really dealt.
 constexpr int kXcds = 8;
+constexpr int kXcdChunk = 4;
 __device__ __forceinline__ int xcd_tile() {
     const int n = (int)gridDim.x, b = (int)blockIdx.x;
-    const int q = n / kXcds, r = n % kXcds, x = b % kXcds, i = b / kXcds;
-    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    const int full = n - n % (kXcds * kXcdChunk);
+    if (b >= full) return b;
+    const int x = b % kXcds, i = b / kXcds;
+    return ((i / kXcdChunk) * kXcds + x) * kXcdChunk + i % kXcdChunk;
 }
 
 // Products of operands below 2^24: the masks let the compiler use the
