@@ -4,8 +4,10 @@
 One JSON line on stdout.  The headline `value` is the plain single-image
 kernel's throughput (megapixels/s) over one pass of the 1920x1080 sweep --
 r in {1, 2, 5, 10, 15} at L = 20 and L in {8, 64} at r = 5, seven filter
-launches per step -- with the image already resident in device memory.  The
-same line carries:
+launches per step -- with the image already resident in device memory,
+timed over K steps after W warmup steps, which follow 30 ms of untimed steps
+(`settle_steps`) that bring the GPU out of its idle state.  The same line
+carries:
   * per-(r, L) MP/s of that sweep, the 256x256 (r=2, L=20) case and the
     4000x3000 (r=10, L=32) camera case;
   * `batched`: 64 uneven images in one hipGraph-replayed persistent launch
