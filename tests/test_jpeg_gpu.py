@@ -214,6 +214,57 @@ def test_decode_corrupt_streams_as_host_decoder():
     assert outcomes == {True, False}
 
 
+@pytest.mark.parametrize("restart,bits", [(0, 64), (0, 0), (3, 0)])
+def test_decode_shifted_streams_as_host_decoder(restart, bits):
+    """A byte deleted from or repeated in the entropy-coded data shifts
+    every later code: the device's tracks, links and host walk must still
+    find the same decoding as the library's host decoder (status and every
+    coefficient), whatever the subsequence length and restart intervals."""
+    torch = torch_mod()
+    img = synth.make_image(176, 96, seed=37, n_blobs=6, sigma=(2, 40))
+    kw = {"restart_marker_blocks": restart} if restart else {}
+    data = pil_jpeg(img, 85, 2, **kw)
+    sos = data.index(b"\xff\xda")
+    begin = sos + 2 + (data[sos + 2] << 8 | data[sos + 3])
+    end = len(data) - 2
+    rng = np.random.default_rng(11 + restart + bits)
+    cases = []
+    while len(cases) < 12:
+        pos = int(rng.integers(begin + 2, end - 2))
+        if 0xFF in data[pos - 1:pos + 2]:
+            continue
+        b = bytearray(data)
+        if len(cases) % 2:
+            del b[pos]
+        else:
+            b.insert(pos, b[pos])
+        cases.append(bytes(b))
+    B.jpeg_set_subsequence_bits(bits)
+    try:
+        for trial, bad in enumerate(cases):
+            try:
+                info, coef = B.jpeg_coefficients(bad)
+                host_ok = True
+            except B.OilpaintError as e:
+                assert e.status == B.ERR_ARG
+                host_ok = False
+            try:
+                planes = B.jpeg_decode_planes(bad)
+                torch.cuda.synchronize()
+                dev_ok = True
+            except B.OilpaintError as e:
+                assert e.status == B.ERR_ARG
+                dev_ok = False
+            assert host_ok == dev_ok, trial
+            if dev_ok:
+                coefs = [coef.reshape(-1, 64)[info.first_block[c]:info.first_block[c] + info.blocks_w[c] *
+                                               info.blocks_h[c]].reshape(info.blocks_h[c], info.blocks_w[c], 64)
+                         .astype(np.int64) for c in range(info.components)]
+                check_planes(bad, planes, coefs)
+    finally:
+        B.jpeg_set_subsequence_bits(0)
+
+
 def check_encoded(img: np.ndarray, data: bytes, quality: int, ss: int) -> int:
     """The file's quantized coefficients (read with the oracle's decoder)
     against the oracle's colour, chroma averaging, FDCT and quantization of
