@@ -57,6 +57,20 @@ def test_fhd_column15_exact(r, L, waves, per_cu):
     check(synth.fhd_image(), r, L, variant=B.Variant(0, waves, B.HIST_COLUMN, 64, per_cu))
 
 
+# Plain launches deal their tiles to the XCDs in chunks of neighbours, with
+# the last partial round of chunks in launch order: grids just below, at
+# and above whole rounds (32 tiles), one strip wide and three, in each
+# layout family (fixed 8-row runs, so the tile count is set by the height)
+@pytest.mark.parametrize("tiles_x,tiles_y", [(1, 31), (1, 32), (1, 33), (1, 97), (3, 11), (3, 21), (5, 13)])
+@pytest.mark.parametrize("variant", [B.Variant(8, 1, B.HIST_STREAM, 64, 8), B.Variant(8, 4, B.HIST_STREAM, 64, 4),
+                                     B.Variant(8, 4, B.HIST_COLUMN, 64, 4)], ids=["stream", "split", "column15"])
+def test_tile_dealing_grid_sizes(tiles_x, tiles_y, variant):
+    w, h = 64 * tiles_x - 17, 8 * tiles_y - 3  # ragged last strip and run
+    img = synth.make_image(w, h, seed=tiles_x * 100 + tiles_y, n_blobs=6, sigma=(3, 25))
+    print("tile grid", tiles_x, tiles_y, variant, flush=True)
+    check(img, 5, 20, variant=variant)
+
+
 def test_camera_exact():
     img = synth.camera_image()
     r, L = synth.CAMERA_RL
