@@ -514,7 +514,7 @@ def bench_jpeg(torch, B, synth, oracle_mod, threads: int, reps: int = 5) -> dict
             t3 = time.perf_counter()
             enc_bytes = B.jpeg_encode(dst, quality=90, subsampling=2, times=t)
             t4 = time.perf_counter()
-            if k:  # the first round warms up
+            if k:  # the first pass warms up
                 dec.append((t1 - t0) * 1e3)
                 dec_host.append(dh)
                 enc.append((t4 - t3) * 1e3)
